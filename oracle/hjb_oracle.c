@@ -1,0 +1,488 @@
+/*
+ * hjb_oracle.c -- plain, slow, CPU FP64 oracle for the patchy semi-Lagrangian
+ * scheme for the minimum-time HJB equation (Cacace, Cristiani, Falcone,
+ * Picarelli, "A Patchy Dynamic Programming Scheme for a Class of
+ * Hamilton-Jacobi-Bellman Equations").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include,
+ * link or call this file; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it.  It shares no code with the GPU path.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC.
+ * Every floating-point expression below is written as separate IEEE binary64
+ * multiplies and adds; with contraction off the compiler must not fuse them.
+ *
+ * What is computed (paper sections in brackets):
+ *   - the SL fixed-point operator F of Section 2.1 (eq. SLscheme) in the
+ *     Kruzkov variable v = 1 - exp(-T):
+ *         [F(v)]_p = min_k beta * I[v](p + s (c_p a_k + w_p)) + (1 - beta)
+ *     on active non-target nodes, 0 on target nodes;
+ *   - value iteration v^{n+1} = min(v^n, F(v^n)) from v^0 = 0 on the target,
+ *     1 elsewhere (eq. iterativeSLscheme), Jacobi order, until no node changes
+ *     (or the sup-norm change is below tol);
+ *   - Patchy Algorithm (Section 3): Step 1 coarse solve, Step 2 prolongation
+ *     and discrete feedback (eq. feedbackcontrol), Step 3.1 colour transport
+ *     with frozen feedback (eq. HJBridotta_discreta) and labels, Step 3.2
+ *     independent per-patch iteration, Step 4 merge.
+ *
+ * Readings where the paper leaves the details open (all documented with the
+ * design notes of the repository):
+ *   - index-space foot point: displacement d = s * (c a + w) per axis,
+ *     cell q = floor(d), local coordinate t = d - q;
+ *   - "linear interpolation in R^d" is the tensor product of 1D linear
+ *     interpolations in weights form, nested x, then y, then z:
+ *         r = (1 - t) * lo + t * hi;
+ *   - grid boundary: every box node is an unknown; corners outside the box
+ *     take the ghost value (1 for v: state constraint; 0 for the colours);
+ *   - patch boundary (state constraint, Section 3 "Details on boundary
+ *     conditions"): in patch j, non-target nodes with another label are
+ *     ghosts with value 1; all target nodes are 0 in every patch;
+ *   - feedback: the first control (ascending k) attaining the minimum of the
+ *     interpolated value I[U^(0)] (raw I, before the affine Kruzkov map);
+ *     target nodes carry no feedback (255);
+ *   - colours: target nodes are fixed (1 on their own part, 0 elsewhere),
+ *     non-target nodes start at 0 and rise as phi <- max(phi, I[phi]) until
+ *     nothing changes; the label is the part with the largest colour, lowest
+ *     part index on ties, -1 if every colour is 0 (node never reached,
+ *     cf. Section 4.6 on unreachable regions);
+ *   - merge: target 0, label -1 gives 1, else the value of patch label.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL 1
+#define ORC_ENOCONV 4
+#define ORC_ENOMEM 3
+
+typedef struct {
+  int32_t dim;
+  int32_t n[3];
+  double step[3];
+  double beta;
+  double omb;
+  int32_t n_controls;
+  const double *controls;      /* [Nc][dim] */
+  const double *speed;         /* [N] */
+  const double *drift;         /* [N][dim] or NULL */
+  const int16_t *target_part;  /* [N], -1 = not target */
+  int32_t n_parts;
+} orc_problem;
+
+/* Active-set description: patch < 0 means "every box node is active"
+ * (global solve); otherwise a node is active iff it is a target node or its
+ * label equals patch. */
+typedef struct {
+  const int16_t *labels;
+  int patch;
+} orc_active;
+
+static long long orc_N(const orc_problem *P) {
+  return (long long)P->n[0] * P->n[1] * P->n[2];
+}
+
+static int orc_check(const orc_problem *P) {
+  if (!P || (P->dim != 2 && P->dim != 3)) return ORC_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (P->n[d] < 1) return ORC_EINVAL;
+  if (P->n[0] < 2 || P->n[1] < 2 || (P->dim == 3 && P->n[2] < 2)) return ORC_EINVAL;
+  if (P->dim == 2 && P->n[2] != 1) return ORC_EINVAL;
+  if (P->n_controls < 1 || !P->controls || !P->speed || !P->target_part) return ORC_EINVAL;
+  return ORC_OK;
+}
+
+/* Value of a corner node: stored value if inside the box and active, else
+ * the ghost value. */
+static double orc_corner(const orc_problem *P, const double *v, const orc_active *A,
+                         long long x, long long y, long long z, double ghost) {
+  if (x < 0 || y < 0 || z < 0 || x >= P->n[0] || y >= P->n[1] || z >= P->n[2]) return ghost;
+  long long q = x + (long long)P->n[0] * (y + (long long)P->n[1] * z);
+  if (A) {
+    int tp = P->target_part[q];
+    if (tp < 0 && A->patch >= 0 && A->labels[q] != A->patch) return ghost;
+  }
+  return v[q];
+}
+
+/* 1D linear interpolation in weights form. */
+static double orc_lin(double t, double lo, double hi) {
+  double omt = 1.0 - t;
+  double a = omt * lo;
+  double b = t * hi;
+  return a + b;
+}
+
+/* Foot-point displacement of node q under control k, in cells, per axis. */
+static void orc_displacement(const orc_problem *P, long long q, int k, double disp[3]) {
+  double c = P->speed[q];
+  for (int d = 0; d < 3; ++d) disp[d] = 0.0;
+  for (int d = 0; d < P->dim; ++d) {
+    double g = c * P->controls[(long long)k * P->dim + d];
+    if (P->drift) g = g + P->drift[q * P->dim + d];
+    disp[d] = P->step[d] * g;
+  }
+}
+
+/* I[v](p + disp): interpolated value at the foot point. */
+static double orc_interp(const orc_problem *P, const double *v, const orc_active *A,
+                         long long px, long long py, long long pz, const double disp[3],
+                         double ghost) {
+  double fl[3], t[3];
+  long long c0[3];
+  for (int d = 0; d < 3; ++d) {
+    fl[d] = floor(disp[d]);
+    t[d] = disp[d] - fl[d];
+    c0[d] = (long long)fl[d];
+  }
+  long long x0 = px + c0[0], y0 = py + c0[1];
+  if (P->dim == 2) {
+    double v00 = orc_corner(P, v, A, x0, y0, 0, ghost);
+    double v10 = orc_corner(P, v, A, x0 + 1, y0, 0, ghost);
+    double v01 = orc_corner(P, v, A, x0, y0 + 1, 0, ghost);
+    double v11 = orc_corner(P, v, A, x0 + 1, y0 + 1, 0, ghost);
+    double r0 = orc_lin(t[0], v00, v10);
+    double r1 = orc_lin(t[0], v01, v11);
+    return orc_lin(t[1], r0, r1);
+  }
+  long long z0 = pz + c0[2];
+  double rz[2];
+  for (int ez = 0; ez < 2; ++ez) {
+    double v00 = orc_corner(P, v, A, x0, y0, z0 + ez, ghost);
+    double v10 = orc_corner(P, v, A, x0 + 1, y0, z0 + ez, ghost);
+    double v01 = orc_corner(P, v, A, x0, y0 + 1, z0 + ez, ghost);
+    double v11 = orc_corner(P, v, A, x0 + 1, y0 + 1, z0 + ez, ghost);
+    double r0 = orc_lin(t[0], v00, v10);
+    double r1 = orc_lin(t[0], v01, v11);
+    rz[ez] = orc_lin(t[1], r0, r1);
+  }
+  return orc_lin(t[2], rz[0], rz[1]);
+}
+
+/* [F(v)]_q for a non-target active node q (Section 2.1, eq. SLscheme in the
+ * Kruzkov variable): min over the discrete controls of beta*I + (1-beta). */
+static double orc_F_node(const orc_problem *P, const double *v, const orc_active *A, long long q,
+                         long long px, long long py, long long pz) {
+  double best = INFINITY;
+  for (int k = 0; k < P->n_controls; ++k) {
+    double disp[3];
+    orc_displacement(P, q, k, disp);
+    double I = orc_interp(P, v, A, px, py, pz, disp, 1.0);
+    double bI = P->beta * I;
+    double cand = bI + P->omb;
+    if (cand < best) best = cand;
+  }
+  return best;
+}
+
+static int orc_is_updated(const orc_problem *P, const orc_active *A, long long q) {
+  if (P->target_part[q] >= 0) return 0;
+  if (A && A->patch >= 0 && A->labels[q] != A->patch) return 0;
+  return 1;
+}
+
+/* Public: apply F once (no min with the old value) to every node, for tests
+ * of the operator's invariants.  Inactive non-target nodes copy v_in. */
+int orc_apply_F(const orc_problem *P, const int16_t *labels, int patch, const double *v_in,
+                double *v_out) {
+  if (orc_check(P)) return ORC_EINVAL;
+  orc_active A = {labels, patch};
+  const orc_active *Ap = (patch >= 0) ? &A : NULL;
+  long long nx = P->n[0], ny = P->n[1], nz = P->n[2];
+  for (long long z = 0; z < nz; ++z)
+    for (long long y = 0; y < ny; ++y)
+      for (long long x = 0; x < nx; ++x) {
+        long long q = x + nx * (y + ny * z);
+        if (P->target_part[q] >= 0) v_out[q] = 0.0;
+        else if (!orc_is_updated(P, Ap, q)) v_out[q] = v_in[q];
+        else v_out[q] = orc_F_node(P, v_in, Ap, q, x, y, z);
+      }
+  return ORC_OK;
+}
+
+/* Public: F at a list of nodes (raw operator, no min with the old value),
+ * so that a large result can be checked node by node. */
+int orc_F_at(const orc_problem *P, const int16_t *labels, int patch, const double *v,
+             const long long *idx, long long count, double *out) {
+  if (orc_check(P)) return ORC_EINVAL;
+  orc_active A = {labels, patch};
+  const orc_active *Ap = (patch >= 0) ? &A : NULL;
+  long long nx = P->n[0], ny = P->n[1];
+  for (long long i = 0; i < count; ++i) {
+    long long q = idx[i];
+    long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
+    if (P->target_part[q] >= 0) out[i] = 0.0;
+    else out[i] = orc_F_node(P, v, Ap, q, x, y, z);
+  }
+  return ORC_OK;
+}
+
+/* Jacobi value iteration over the node list `nodes` (all updated nodes of
+ * the active set), in place on v which must hold the initial values.
+ * Stops when the sup-norm change of a sweep is <= tol (tol == 0: exact fixed
+ * point, no node changes). */
+static int orc_jacobi(const orc_problem *P, const orc_active *A, const long long *nodes,
+                      long long count, double tol, int max_sweeps, double *v, int *sweeps_out,
+                      double *res_out) {
+  long long N = orc_N(P);
+  double *vn = (double *)malloc(sizeof(double) * (size_t)N);
+  if (!vn) return ORC_ENOMEM;
+  memcpy(vn, v, sizeof(double) * (size_t)N);
+  long long nx = P->n[0], ny = P->n[1];
+  int sweeps = 0;
+  double res = 0.0;
+  int rc = ORC_ENOCONV;
+  while (sweeps < max_sweeps) {
+    res = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : res)
+    for (long long i = 0; i < count; ++i) {
+      long long q = nodes[i];
+      long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
+      double f = orc_F_node(P, v, A, q, x, y, z);
+      double nv = f < v[q] ? f : v[q];
+      double dlt = v[q] - nv;
+      if (dlt > res) res = dlt;
+      vn[q] = nv;
+    }
+    for (long long i = 0; i < count; ++i) v[nodes[i]] = vn[nodes[i]];
+    ++sweeps;
+    if (res <= tol) { rc = ORC_OK; break; }
+  }
+  free(vn);
+  if (sweeps_out) *sweeps_out = sweeps;
+  if (res_out) *res_out = res;
+  return rc;
+}
+
+/* Public: global solve (every box node active), eq. iterativeSLscheme.
+ * Outputs v [N]; sweeps, final residual and node-control updates. */
+int orc_solve_global(const orc_problem *P, double tol, int max_sweeps, double *v, int *sweeps,
+                     double *residual, long long *updates) {
+  if (orc_check(P)) return ORC_EINVAL;
+  long long N = orc_N(P), cnt = 0;
+  long long *nodes = (long long *)malloc(sizeof(long long) * (size_t)(N > 0 ? N : 1));
+  if (!nodes) return ORC_ENOMEM;
+  for (long long q = 0; q < N; ++q) {
+    if (P->target_part[q] >= 0) v[q] = 0.0;
+    else { v[q] = 1.0; nodes[cnt++] = q; }
+  }
+  int sw = 0;
+  int rc = orc_jacobi(P, NULL, nodes, cnt, tol, max_sweeps, v, &sw, residual);
+  if (sweeps) *sweeps = sw;
+  if (updates) *updates = (long long)sw * cnt * P->n_controls;
+  free(nodes);
+  return rc;
+}
+
+/* Public: Step 2, prolongation of the coarse values onto the fine grid.
+ * Fine node p_d maps to coarse index coordinate X = p_d (nc_d-1) / (nf_d-1);
+ * Q = min(floor X, nc_d - 2), T = X - Q; nested linear interpolation. */
+int orc_prolong(const orc_problem *C, const double *vc, const orc_problem *F, double *u0) {
+  if (orc_check(C) || orc_check(F) || C->dim != F->dim) return ORC_EINVAL;
+  int dim = F->dim;
+  long long nf[3] = {F->n[0], F->n[1], F->n[2]};
+  long long ncn[3] = {C->n[0], C->n[1], C->n[2]};
+  for (long long z = 0; z < nf[2]; ++z)
+    for (long long y = 0; y < nf[1]; ++y)
+      for (long long x = 0; x < nf[0]; ++x) {
+        long long p[3] = {x, y, z};
+        long long Q[3] = {0, 0, 0};
+        double T[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < dim; ++d) {
+          double X = (double)(p[d] * (ncn[d] - 1)) / (double)(nf[d] - 1);
+          double fq = floor(X);
+          if (fq > (double)(ncn[d] - 2)) fq = (double)(ncn[d] - 2);
+          Q[d] = (long long)fq;
+          T[d] = X - fq;
+        }
+        double val;
+#define CV(a, b, c) vc[(Q[0] + (a)) + ncn[0] * ((Q[1] + (b)) + ncn[1] * (Q[2] + (c)))]
+        if (dim == 2) {
+          double r0 = orc_lin(T[0], CV(0, 0, 0), CV(1, 0, 0));
+          double r1 = orc_lin(T[0], CV(0, 1, 0), CV(1, 1, 0));
+          val = orc_lin(T[1], r0, r1);
+        } else {
+          double rz[2];
+          for (int ez = 0; ez < 2; ++ez) {
+            double r0 = orc_lin(T[0], CV(0, 0, ez), CV(1, 0, ez));
+            double r1 = orc_lin(T[0], CV(0, 1, ez), CV(1, 1, ez));
+            rz[ez] = orc_lin(T[1], r0, r1);
+          }
+          val = orc_lin(T[2], rz[0], rz[1]);
+        }
+#undef CV
+        u0[x + nf[0] * (y + nf[1] * z)] = val;
+      }
+  return ORC_OK;
+}
+
+/* Public: Step 2, discrete feedback (eq. feedbackcontrol): for every
+ * non-target fine node the first k minimising I[U^(0)](p + s(c a_k + w)),
+ * ghost 1 outside the box, every node active.  Target nodes get 255. */
+int orc_feedback(const orc_problem *F, const double *u0, uint8_t *fb) {
+  if (orc_check(F) || F->n_controls > 255) return ORC_EINVAL;
+  long long nx = F->n[0], ny = F->n[1], nz = F->n[2];
+#pragma omp parallel for schedule(static) collapse(2)
+  for (long long z = 0; z < nz; ++z)
+    for (long long y = 0; y < ny; ++y)
+      for (long long x = 0; x < nx; ++x) {
+        long long q = x + nx * (y + ny * z);
+        if (F->target_part[q] >= 0) { fb[q] = 255; continue; }
+        double best = INFINITY;
+        int bk = 0;
+        for (int k = 0; k < F->n_controls; ++k) {
+          double disp[3];
+          orc_displacement(F, q, k, disp);
+          double I = orc_interp(F, u0, NULL, x, y, z, disp, 1.0);
+          if (I < best) { best = I; bk = k; }
+        }
+        fb[q] = (uint8_t)bk;
+      }
+  return ORC_OK;
+}
+
+/* Public: Step 3.1 for one part j -- colour transport with the frozen
+ * feedback, eq. HJBridotta_discreta, iterated (Jacobi) from below to the
+ * exact fixed point.  phi [N] is output. */
+int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sweeps, double *phi,
+                   int *sweeps_out) {
+  if (orc_check(F)) return ORC_EINVAL;
+  long long N = orc_N(F), nx = F->n[0], ny = F->n[1];
+  long long cnt = 0;
+  long long *nodes = (long long *)malloc(sizeof(long long) * (size_t)N);
+  double *pn = (double *)malloc(sizeof(double) * (size_t)N);
+  if (!nodes || !pn) { free(nodes); free(pn); return ORC_ENOMEM; }
+  for (long long q = 0; q < N; ++q) {
+    int tp = F->target_part[q];
+    if (tp >= 0) phi[q] = (tp == part) ? 1.0 : 0.0;
+    else { phi[q] = 0.0; nodes[cnt++] = q; }
+  }
+  memcpy(pn, phi, sizeof(double) * (size_t)N);
+  int sweeps = 0, rc = ORC_ENOCONV;
+  while (sweeps < max_sweeps) {
+    int changed = 0;
+#pragma omp parallel for schedule(static) reduction(| : changed)
+    for (long long i = 0; i < cnt; ++i) {
+      long long q = nodes[i];
+      long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
+      double disp[3];
+      orc_displacement(F, q, fb[q], disp);
+      double I = orc_interp(F, phi, NULL, x, y, z, disp, 0.0);
+      double nv = I > phi[q] ? I : phi[q];
+      if (nv != phi[q]) changed = 1;
+      pn[q] = nv;
+    }
+    for (long long i = 0; i < cnt; ++i) phi[nodes[i]] = pn[nodes[i]];
+    ++sweeps;
+    if (!changed) { rc = ORC_OK; break; }
+  }
+  if (sweeps_out) *sweeps_out = sweeps;
+  free(nodes);
+  free(pn);
+  return rc;
+}
+
+/* Public: Step 3.1 for all parts, then the labels (projection/assembly,
+ * eq. proiezionecolore with Remark 3.1): label = target part on target
+ * nodes; elsewhere the part with the largest colour (lowest index on ties),
+ * -1 where every colour is 0.  phi_sum (optional) receives sum_j phi^j. */
+int orc_labels(const orc_problem *F, const uint8_t *fb, int max_sweeps, int16_t *labels,
+               double *phi_sum, int *max_trace_sweeps) {
+  if (orc_check(F) || F->n_parts < 1) return ORC_EINVAL;
+  long long N = orc_N(F);
+  double *phi = (double *)malloc(sizeof(double) * (size_t)N);
+  double *best = (double *)malloc(sizeof(double) * (size_t)N);
+  if (!phi || !best) { free(phi); free(best); return ORC_ENOMEM; }
+  for (long long q = 0; q < N; ++q) {
+    best[q] = 0.0;
+    labels[q] = -1;
+    if (phi_sum) phi_sum[q] = 0.0;
+  }
+  int mx = 0, rc = ORC_OK;
+  for (int j = 0; j < F->n_parts; ++j) {
+    int sw = 0;
+    int r = orc_trace_part(F, fb, j, max_sweeps, phi, &sw);
+    if (r != ORC_OK) rc = r;
+    if (sw > mx) mx = sw;
+    for (long long q = 0; q < N; ++q) {
+      if (phi_sum) phi_sum[q] = phi_sum[q] + phi[q];
+      if (phi[q] > best[q]) { best[q] = phi[q]; labels[q] = (int16_t)j; }
+    }
+  }
+  for (long long q = 0; q < N; ++q)
+    if (F->target_part[q] >= 0) labels[q] = F->target_part[q];
+  if (max_trace_sweeps) *max_trace_sweeps = mx;
+  free(phi);
+  free(best);
+  return rc;
+}
+
+/* Public: Step 3.2 + Step 4 -- independent value iteration in every patch
+ * (state-constraint patch boundary), then merge.  `only_patch` >= 0 solves
+ * that single patch (other nodes of v are left at 1 / 0). */
+int orc_solve_patches(const orc_problem *F, const int16_t *labels, double tol, int max_sweeps,
+                      int only_patch, double *v, int *sweeps_per_patch, long long *updates) {
+  if (orc_check(F) || F->n_parts < 1) return ORC_EINVAL;
+  long long N = orc_N(F);
+  long long *cnt = (long long *)calloc((size_t)F->n_parts, sizeof(long long));
+  long long *start = (long long *)calloc((size_t)F->n_parts + 1, sizeof(long long));
+  long long *nodes = (long long *)malloc(sizeof(long long) * (size_t)(N > 0 ? N : 1));
+  double *work = (double *)malloc(sizeof(double) * (size_t)N);
+  if (!cnt || !start || !nodes || !work) {
+    free(cnt); free(start); free(nodes); free(work);
+    return ORC_ENOMEM;
+  }
+  for (long long q = 0; q < N; ++q) {
+    if (F->target_part[q] >= 0) { v[q] = 0.0; continue; }
+    v[q] = 1.0;
+    int L = labels[q];
+    if (L >= F->n_parts) { free(cnt); free(start); free(nodes); free(work); return ORC_EINVAL; }
+    if (L >= 0) cnt[L]++;
+  }
+  for (int j = 0; j < F->n_parts; ++j) start[j + 1] = start[j] + cnt[j];
+  for (int j = 0; j < F->n_parts; ++j) cnt[j] = 0;
+  for (long long q = 0; q < N; ++q) {
+    int L = labels[q];
+    if (F->target_part[q] < 0 && L >= 0) nodes[start[L] + cnt[L]++] = q;
+  }
+  int rc = ORC_OK;
+  long long upd = 0;
+  for (int j = 0; j < F->n_parts; ++j) {
+    if (sweeps_per_patch) sweeps_per_patch[j] = 0;
+    if (only_patch >= 0 && j != only_patch) continue;
+    /* Patch-local iterate: target 0, patch nodes 1; other nodes are ghosts
+     * (never read as values, see orc_corner). */
+    for (long long q = 0; q < N; ++q) work[q] = (F->target_part[q] >= 0) ? 0.0 : 1.0;
+    orc_active A = {labels, j};
+    int sw = 0;
+    int r = orc_jacobi(F, &A, nodes + start[j], cnt[j], tol, max_sweeps, work, &sw, NULL);
+    if (r != ORC_OK) rc = r;
+    if (sweeps_per_patch) sweeps_per_patch[j] = sw;
+    upd += (long long)sw * cnt[j] * F->n_controls;
+    for (long long i = start[j]; i < start[j] + cnt[j]; ++i) v[nodes[i]] = work[nodes[i]];
+  }
+  if (updates) *updates = upd;
+  free(cnt); free(start); free(nodes); free(work);
+  return rc;
+}
+
+/* Public: number of threads the parallel loops use. */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -1,0 +1,363 @@
+"""Seeded synthetic minimum-time problems (inputs only).
+
+This module tabulates control problems of the family ``f(x, a) = c(x) a + w(x)``
+on a uniform box grid and emits the arrays both the GPU library and the CPU
+oracle consume.  It contains none of the scheme's arithmetic (no foot points,
+no interpolation, no value iteration): only the problem statement of the
+paper's eq. (HJB) in Section 1 -- box, target, dynamics and control set -- plus
+the discretisation parameters h, k and beta = exp(-h) of Section 2.1.
+
+Conventions shared by every consumer:
+
+* nodes ``p = (p_x, p_y, p_z)``, flat index ``p_x + n_x (p_y + n_y p_z)``
+  (x fastest); in 2D ``n_z = 1``;
+* ``x_i = lo + i k`` with ``k = (hi - lo) / (n - 1)``;
+* ``step[d] = h / k_d``: foot-point displacement in cells per unit of f;
+* ``target_part[p] = -1`` for non-target nodes, else the index ``j`` of the
+  part of the target the node belongs to (Section 3: the target is divided
+  into R parts);
+* ``beta = exp(-h)`` is computed here with the host libm; when the value grid
+  is to be stored in FP32 the instance carries ``float32(exp(-h))`` so that
+  beta and ``1 - beta`` are exact in both precisions; ``omb = 1 - beta`` is
+  exact in FP64 because beta lies in [0.5, 1).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "Problem", "grid_coords", "unit_controls_2d", "fibonacci_controls_3d",
+    "eikonal_2d", "config1", "variable_speed_2d", "config2", "config3",
+    "variable_speed_3d", "line_target_2d", "zermelo_2d", "batched_problem",
+    "config4", "ServingRequest", "serving_stream", "coarse_size_2d",
+]
+
+
+@dataclasses.dataclass
+class Problem:
+    """One tabulated minimum-time problem on a uniform grid."""
+
+    dim: int
+    n: tuple                   # (nx, ny, nz); nz == 1 in 2D
+    lo: tuple
+    hi: tuple
+    h: float                   # fictitious time step
+    step: tuple                # h / k_d per axis
+    beta: float
+    omb: float                 # 1 - beta, exact
+    controls: np.ndarray       # float64 [Nc, dim]
+    speed: np.ndarray          # float64 [N]
+    drift: Optional[np.ndarray]  # float64 [N, dim] or None
+    target_part: np.ndarray    # int16 [N]
+    n_parts: int
+    name: str = ""
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    @property
+    def n_controls(self) -> int:
+        return int(self.controls.shape[0])
+
+    @property
+    def shape(self) -> tuple:
+        """numpy shape of a node array, slowest axis first."""
+        if self.dim == 2:
+            return (self.n[1], self.n[0])
+        return (self.n[2], self.n[1], self.n[0])
+
+    @property
+    def k(self) -> tuple:
+        return tuple((self.hi[d] - self.lo[d]) / (self.n[d] - 1) if self.n[d] > 1 else 0.0
+                     for d in range(3))
+
+    def coords(self) -> List[np.ndarray]:
+        return grid_coords(self.dim, self.n, self.lo, self.hi)
+
+    def is_target(self) -> np.ndarray:
+        return self.target_part >= 0
+
+    def validate(self) -> None:
+        assert self.dim in (2, 3)
+        assert self.controls.dtype == np.float64 and self.controls.shape[1] == self.dim
+        assert self.speed.dtype == np.float64 and self.speed.shape == (self.N,)
+        assert self.target_part.dtype == np.int16 and self.target_part.shape == (self.N,)
+        if self.drift is not None:
+            assert self.drift.dtype == np.float64 and self.drift.shape == (self.N, self.dim)
+        assert 0.5 <= self.beta < 1.0 and self.omb == 1.0 - self.beta
+
+
+def grid_coords(dim: int, n: Sequence[int], lo: Sequence[float], hi: Sequence[float]):
+    """Node coordinates, each flattened to length N in x-fastest order."""
+    axes = []
+    for d in range(dim):
+        k = (hi[d] - lo[d]) / (n[d] - 1)
+        axes.append(lo[d] + k * np.arange(n[d], dtype=np.float64))
+    if dim == 2:
+        Y, X = np.meshgrid(axes[1], axes[0], indexing="ij")
+        return [X.ravel(), Y.ravel()]
+    Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return [X.ravel(), Y.ravel(), Z.ravel()]
+
+
+def _snap(a: np.ndarray) -> np.ndarray:
+    """Set components within 1e-15 of 0 or +-1 to that value exactly."""
+    a = a.copy()
+    for t in (0.0, 1.0, -1.0):
+        a[np.abs(a - t) < 1e-15] = t
+    return a
+
+
+def unit_controls_2d(nc: int) -> np.ndarray:
+    """N_c unit directions at angles 2 pi k / N_c (discretisation of B(0,1)
+    boundary, Section 2.1: the minimum over A is taken over N_c points)."""
+    th = 2.0 * math.pi * np.arange(nc) / nc
+    return _snap(np.stack([np.cos(th), np.sin(th)], axis=1))
+
+
+def fibonacci_controls_3d(nc: int = 98) -> np.ndarray:
+    """N_c quasi-uniform unit vectors on S^2 (Fibonacci lattice)."""
+    i = np.arange(nc, dtype=np.float64)
+    z = 1.0 - (2.0 * i + 1.0) / nc
+    ph = i * math.pi * (3.0 - math.sqrt(5.0))
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    return _snap(np.stack([r * np.cos(ph), r * np.sin(ph), z], axis=1))
+
+
+def _beta(h: float, fp32: bool) -> float:
+    b = math.exp(-h)
+    if fp32:
+        b = float(np.float32(b))
+    return b
+
+
+def _make(dim, n, h, controls, speed, drift, target_part, n_parts, fp32, name,
+          lo=None, hi=None, meta=None) -> Problem:
+    lo = tuple(lo if lo is not None else [-1.0] * dim) + (0.0,) * (3 - dim)
+    hi = tuple(hi if hi is not None else [1.0] * dim) + (0.0,) * (3 - dim)
+    nn = tuple(n) + (1,) * (3 - dim)
+    k = [(hi[d] - lo[d]) / (nn[d] - 1) for d in range(dim)]
+    step = tuple(h / k[d] for d in range(dim)) + (0.0,) * (3 - dim)
+    b = _beta(h, fp32)
+    p = Problem(dim=dim, n=nn, lo=lo, hi=hi, h=h, step=step, beta=b, omb=1.0 - b,
+                controls=np.ascontiguousarray(controls, dtype=np.float64),
+                speed=np.ascontiguousarray(speed, dtype=np.float64),
+                drift=None if drift is None else np.ascontiguousarray(drift, dtype=np.float64),
+                target_part=np.ascontiguousarray(target_part, dtype=np.int16),
+                n_parts=int(n_parts), name=name, meta=dict(meta or {}))
+    p.validate()
+    return p
+
+
+def _ball_sectors_2d(X, Y, centre, r, R):
+    dx, dy = X - centre[0], Y - centre[1]
+    inside = dx * dx + dy * dy <= r * r
+    th = np.arctan2(dy, dx)
+    th = np.where(th < 0.0, th + 2.0 * math.pi, th)
+    part = np.minimum(R - 1, np.floor(R * th / (2.0 * math.pi)).astype(np.int64))
+    return np.where(inside, part, -1).astype(np.int16)
+
+
+def eikonal_2d(n: int = 101, nc: int = 32, r: float = 0.1, R: int = 1,
+               centre=(0.0, 0.0), fp32: bool = False, name: str = "eikonal2d") -> Problem:
+    """f = a, A = N_c unit directions, target = ball of radius r, [-1,1]^2,
+    h = k.  The target is split into R equal-angle sectors."""
+    lo, hi = (-1.0, -1.0), (1.0, 1.0)
+    k = 2.0 / (n - 1)
+    X, Y = grid_coords(2, (n, n), lo, hi)
+    tp = _ball_sectors_2d(X, Y, centre, r, R)
+    return _make(2, (n, n), k, unit_controls_2d(nc), np.ones(n * n), None, tp, R, fp32, name,
+                 meta=dict(r=r, centre=tuple(centre), c=1.0))
+
+
+def config1() -> Problem:
+    """2D eikonal, 101^2 on [-1,1]^2, 32 controls, target ball r = 0.1 at the
+    origin, h = k = 0.02, FP64; closed form T = |x| - 0.1."""
+    return eikonal_2d(101, 32, 0.1, 1, (0.0, 0.0), fp32=False, name="config1-eikonal-101")
+
+
+def coarse_size_2d(n: int, ratio: int = 16, lo: int = 17, hi: int = 65) -> int:
+    return int(min(hi, max(lo, round((n - 1) / ratio) + 1)))
+
+
+def variable_speed_2d(seed: int, n: int = 1025, nc_coarse: int = 65, nc: int = 32, R: int = 16,
+                      r: float = 0.1, fp32: bool = True, drift_sign: Optional[int] = None,
+                      name: str = "varspeed2d"):
+    """Speed c = 1 + 0.5 sin(2 pi k1 x) sin(2 pi k2 y), (k1,k2) in {1,2,3}
+    from the seed; target ball r centred at a seeded point in [-0.5,0.5]^2,
+    split into R equal-angle parts.  Returns (fine, coarse).  With
+    ``drift_sign`` set, adds the Zermelo-type drift
+    w = 0.3 s (-sin(pi y), sin(pi x))."""
+    rng = np.random.default_rng(seed)
+    k1, k2 = (int(v) for v in rng.integers(1, 4, 2))
+    centre = tuple(float(v) for v in rng.uniform(-0.5, 0.5, 2))
+    out = []
+    for nn, is_fp32 in ((n, fp32), (nc_coarse, False)):
+        lo, hi = (-1.0, -1.0), (1.0, 1.0)
+        kk = 2.0 / (nn - 1)
+        X, Y = grid_coords(2, (nn, nn), lo, hi)
+        c = 1.0 + 0.5 * np.sin(2.0 * math.pi * k1 * X) * np.sin(2.0 * math.pi * k2 * Y)
+        w = None
+        if drift_sign is not None:
+            w = 0.3 * drift_sign * np.stack([-np.sin(math.pi * Y), np.sin(math.pi * X)], axis=1)
+        tp = _ball_sectors_2d(X, Y, centre, r, R)
+        out.append(_make(2, (nn, nn), kk, unit_controls_2d(nc), c, w, tp, R, is_fp32,
+                         f"{name}-s{seed}-n{nn}",
+                         meta=dict(seed=seed, k1=k1, k2=k2, centre=centre, r=r)))
+    return out[0], out[1]
+
+
+def config2(seed: int = 0, n: int = 1025, nc_coarse: int = 65):
+    """2D variable-speed patchy problem, 1025^2 fine / 65^2 coarse, 32
+    controls, 16 equal-angle target parts (fine instance FP32-ready)."""
+    return variable_speed_2d(seed, n, nc_coarse, 32, 16, 0.1, True, None, "config2")
+
+
+def _sphere_parts(X, Y, Z, centre, r, bands, sectors):
+    dx, dy, dz = X - centre[0], Y - centre[1], Z - centre[2]
+    rr = dx * dx + dy * dy + dz * dz
+    inside = rr <= r * r
+    rad = np.sqrt(rr)
+    uz = np.where(rad > 0.0, dz / np.where(rad > 0.0, rad, 1.0), 1.0)
+    band = np.minimum(bands - 1, np.floor(bands * (1.0 - uz) / 2.0).astype(np.int64))
+    th = np.arctan2(dy, dx)
+    th = np.where(th < 0.0, th + 2.0 * math.pi, th)
+    sec = np.minimum(sectors - 1, np.floor(sectors * th / (2.0 * math.pi)).astype(np.int64))
+    part = band * sectors + sec
+    part = np.where(rad > 0.0, part, 0)
+    return np.where(inside, part, -1).astype(np.int16)
+
+
+def variable_speed_3d(seed: int, n: int = 257, nc_coarse: int = 33, nc: int = 98,
+                      bands: int = 8, sectors: int = 8, r: float = 0.15, fp32: bool = True,
+                      name: str = "varspeed3d"):
+    """Speed c = 1 + 0.4 prod_i sin(2 pi k_i x_i), k_i in {1,2} from the
+    seed; 98 Fibonacci directions; target ball r at the origin split into
+    ``bands`` equal-area z-bands x ``sectors`` azimuth sectors."""
+    rng = np.random.default_rng(seed)
+    ks = [int(v) for v in rng.integers(1, 3, 3)]
+    R = bands * sectors
+    out = []
+    for nn, is_fp32 in ((n, fp32), (nc_coarse, False)):
+        lo, hi = (-1.0,) * 3, (1.0,) * 3
+        kk = 2.0 / (nn - 1)
+        X, Y, Z = grid_coords(3, (nn, nn, nn), lo, hi)
+        c = 1.0 + 0.4 * (np.sin(2.0 * math.pi * ks[0] * X) * np.sin(2.0 * math.pi * ks[1] * Y)
+                         * np.sin(2.0 * math.pi * ks[2] * Z))
+        tp = _sphere_parts(X, Y, Z, (0.0, 0.0, 0.0), r, bands, sectors)
+        out.append(_make(3, (nn, nn, nn), kk, fibonacci_controls_3d(nc), c, None, tp, R, is_fp32,
+                         f"{name}-s{seed}-n{nn}", meta=dict(seed=seed, ks=ks, r=r)))
+    return out[0], out[1]
+
+
+def config3(seed: int = 0, n: int = 257, nc_coarse: int = 33):
+    """3D variable-speed patchy problem, 257^3 / 33^3, 98 controls, 64 parts."""
+    return variable_speed_3d(seed, n, nc_coarse, 98, 8, 8, 0.15, True, "config3")
+
+
+def eikonal_3d(n: int = 33, nc: int = 98, r: float = 0.3, bands: int = 1, sectors: int = 1,
+               fp32: bool = False, name: str = "eikonal3d") -> Problem:
+    lo, hi = (-1.0,) * 3, (1.0,) * 3
+    kk = 2.0 / (n - 1)
+    X, Y, Z = grid_coords(3, (n, n, n), lo, hi)
+    tp = _sphere_parts(X, Y, Z, (0.0, 0.0, 0.0), r, bands, sectors)
+    return _make(3, (n, n, n), kk, fibonacci_controls_3d(nc), np.ones(n ** 3), None, tp,
+                 bands * sectors, fp32, name, meta=dict(r=r, c=1.0))
+
+
+def line_target_2d(n: int = 41, nc: int = 32, col: Optional[int] = None, strips: int = 1,
+                   fp32: bool = False, name: str = "line2d") -> Problem:
+    """Target = one grid column {x = x_col}; with ``strips`` > 1 the column is
+    split into that many horizontal strips (parts) of equal node count."""
+    col = n // 2 if col is None else col
+    lo, hi = (-1.0, -1.0), (1.0, 1.0)
+    kk = 2.0 / (n - 1)
+    tp = np.full((n, n), -1, dtype=np.int16)
+    rows = np.arange(n)
+    tp[:, col] = np.minimum(strips - 1, rows * strips // n).astype(np.int16)
+    return _make(2, (n, n), kk, unit_controls_2d(nc), np.ones(n * n), None, tp.ravel(), strips,
+                 fp32, name, meta=dict(col=col))
+
+
+def zermelo_2d(n: int = 101, nc: int = 64, c: float = 1.0, w=(0.4, 0.0), r: float = 0.2,
+               fp32: bool = False, name: str = "zermelo2d") -> Problem:
+    """Constant-drift Zermelo problem f = c a + w (|w| < c), target ball r at
+    the origin (cf. Table test2d, Zermelo)."""
+    lo, hi = (-1.0, -1.0), (1.0, 1.0)
+    kk = 2.0 / (n - 1)
+    X, Y = grid_coords(2, (n, n), lo, hi)
+    tp = _ball_sectors_2d(X, Y, (0.0, 0.0), r, 1)
+    drift = np.tile(np.asarray(w, dtype=np.float64), (n * n, 1))
+    return _make(2, (n, n), kk, unit_controls_2d(nc), np.full(n * n, float(c)), drift, tp, 1,
+                 fp32, name, meta=dict(c=c, w=tuple(w), r=r))
+
+
+def batched_problem(seed_seq: np.random.SeedSequence, index: int = 0,
+                    n_range=(65, 769), nc_range=(16, 64), R_range=(4, 32)):
+    """One problem of the batched workload: uneven grid side, control count
+    and patch count; C2-type speed and target with a seeded-sign Zermelo
+    drift.  Returns (fine, coarse)."""
+    rng = np.random.default_rng(seed_seq)
+    n = int(rng.integers(n_range[0], n_range[1] + 1))
+    nc = int(rng.integers(nc_range[0], nc_range[1] + 1))
+    R = int(rng.integers(R_range[0], R_range[1] + 1))
+    sign = int(rng.choice([-1, 1]))
+    sub = int(rng.integers(0, 2 ** 31 - 1))
+    ncoarse = coarse_size_2d(n)
+    f, c = variable_speed_2d(sub, n, ncoarse, nc, R, 0.1, True, sign, f"batch{index}")
+    f.meta.update(batch_index=index, drift_sign=sign)
+    return f, c
+
+
+def config4(count: int = 512, base_seed: int = 0, n_range=(65, 769)):
+    """The batched workload: ``count`` independent 2D problems."""
+    children = np.random.SeedSequence(base_seed).spawn(count)
+    return [batched_problem(s, i, n_range) for i, s in enumerate(children)]
+
+
+@dataclasses.dataclass
+class ServingRequest:
+    rid: int
+    arrival_s: float
+    fine: Problem
+    coarse: Problem
+
+
+def serving_stream(count: int, rate_per_s: float, seed: int = 0,
+                   n2d=(129, 1025), n3d=(65, 193), frac3d: float = 0.2):
+    """Poisson arrivals of solve requests: ``1 - frac3d`` 2D (half eikonal
+    with 16 sector parts, half the batched generator), ``frac3d`` 3D (the 3D
+    variable-speed generator).  Returns a generator of ServingRequest."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    for i in range(count):
+        t += float(rng.exponential(1.0 / rate_per_s))
+        u = float(rng.uniform())
+        sub = int(rng.integers(0, 2 ** 31 - 1))
+        if u < frac3d:
+            n = int(rng.integers(n3d[0], n3d[1] + 1))
+            ncoarse = int(min(33, max(9, round((n - 1) / 8) + 1)))
+            srng = np.random.default_rng(sub)
+            ks_seed = int(srng.integers(0, 2 ** 31 - 1))
+            f, c = variable_speed_3d(ks_seed, n, ncoarse, 98, 8, 8, 0.15, True, f"req{i}")
+            tnodes = int((f.target_part >= 0).sum())
+            R = int(min(64, max(8, tnodes // 16)))
+            if R != 64:
+                bands = max(1, int(round(math.sqrt(R))))
+                sectors = max(1, R // bands)
+                f, c = variable_speed_3d(ks_seed, n, ncoarse, 98, bands, sectors, 0.15, True,
+                                         f"req{i}")
+        elif u < frac3d + (1.0 - frac3d) / 2.0:
+            n = int(rng.integers(n2d[0], n2d[1] + 1))
+            f = eikonal_2d(n, 32, 0.1, 16, (0.0, 0.0), True, f"req{i}")
+            c = eikonal_2d(coarse_size_2d(n), 32, 0.1, 16, (0.0, 0.0), False, f"req{i}-c")
+        else:
+            n = int(rng.integers(n2d[0], n2d[1] + 1))
+            f, c = batched_problem(np.random.SeedSequence(sub), i, (n, n))
+        yield ServingRequest(i, t, f, c)
