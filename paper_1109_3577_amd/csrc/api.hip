@@ -1,0 +1,367 @@
+// Exported C ABI of libhjb (declared in include/hjb.h): the four calls of
+// the Patchy Algorithm of the paper (Section 3) plus handle accessors.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace hjb;
+
+struct hjb_coarse_s : CoarseHandle {};
+struct hjb_patches_s : PatchesHandle {};
+
+namespace hjb {
+const char *last_error_cstr();
+}
+
+namespace {
+
+hipStream_t as_stream(hjb_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+void copy_out(void *dst, const void *src, size_t bytes, int32_t mem, hipStream_t s) {
+  HJB_REQUIRE(dst != nullptr, "output pointer is NULL");
+  HJB_REQUIRE(mem == HJB_MEM_HOST || mem == HJB_MEM_DEVICE, "mem must be HJB_MEM_HOST or HJB_MEM_DEVICE");
+  HJB_HIP(hipMemcpyAsync(dst, src, bytes, mem == HJB_MEM_HOST ? hipMemcpyDeviceToHost
+                                                               : hipMemcpyDeviceToDevice, s));
+  HJB_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+namespace hjb {
+
+// Value iteration on one problem with the tiled engine; fills st.
+int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *v, bool fp64,
+                 const hjb_solve_opts *opts, double tol, int32_t max_sweeps, hipStream_t s,
+                 hjb_stats *st, double t0) {
+  HJB_HIP(launch_init_values(fp64, code, P.N, v, s));
+  const SolveConfig cfg = make_config(P.dim, fp64, opts, tol, max_sweeps);
+  ProblemItems items = build_items(P, code, n_patches, cfg.shape, s);
+  SweepEngine eng(cfg, s);
+  eng.add_problem(P, code, &items, v);
+  eng.begin();
+  const int status = eng.run();
+  if (st) {
+    const EngineResult r = eng.results()[0];
+    st->node_updates = (int64_t)r.work_nodes;
+    st->updates = (int64_t)r.work_nodes * P.nc;
+    st->item_runs = (int64_t)r.item_runs;
+    st->items = eng.total_items();
+    st->rounds = (int32_t)eng.rounds();
+    st->residual = r.residual;
+    st->ms_kernel = eng.kernel_ms();
+    st->kernel_launches = eng.kernel_launches();
+    st->status = status;
+    st->ms_wall = now_ms() - t0;
+  }
+  return status;
+}
+
+// Steps 2 and 3.1: prolongation, feedback, chunked colour transport, labels.
+std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const CoarseHandle &C,
+                                                  hipStream_t s) {
+  auto hp = std::make_unique<PatchesHandle>();
+  PatchesHandle &H = *hp;
+  H.dim = F.dim;
+  for (int d = 0; d < 3; ++d) H.n[d] = F.n[d];
+  H.N = F.N;
+  H.n_parts = F.n_parts;
+  const size_t N = F.N;
+  const int dim = F.dim;
+  double t0 = now_ms();
+  H.u0.reset(N * sizeof(double));
+  H.feedback.reset(N);
+  H.labels.reset(N * sizeof(int16_t));
+  H.code.reset(N * sizeof(int16_t));
+
+  // Per-axis prolongation tables: coarse cell Q and local coordinate T of
+  // every fine index, X = p (nc - 1) / (nf - 1).
+  std::vector<int32_t> Q;
+  std::vector<double> T;
+  for (int d = 0; d < 3; ++d) {
+    const int nf = F.n[d], nc = C.n[d];
+    for (int p = 0; p < nf; ++p) {
+      if (d >= dim) {
+        Q.push_back(0);
+        T.push_back(0.0);
+        continue;
+      }
+      const double X = (double)((long long)p * (nc - 1)) / (double)(nf - 1);
+      double q = std::floor(X);
+      if (q > (double)(nc - 2)) q = (double)(nc - 2);
+      Q.push_back((int32_t)q);
+      T.push_back(X - q);
+    }
+  }
+  DBuf dQ(Q.size() * sizeof(int32_t)), dT(T.size() * sizeof(double));
+  HJB_HIP(hipMemcpyAsync(dQ.get(), Q.data(), Q.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HJB_HIP(hipMemcpyAsync(dT.get(), T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  const int32_t nf3[3] = {F.n[0], F.n[1], F.n[2]};
+  const int32_t nc3[3] = {C.n[0], C.n[1], C.n[2]};
+  HJB_HIP(launch_prolong(dim, nf3, nc3, C.v.as<double>(), dQ.as<int32_t>(), dT.as<double>(),
+                         H.u0.as<double>(), s));
+
+  TraceArgs a;
+  std::memset(&a, 0, sizeof a);
+  const SweepShape tsh = trace_shape(dim);
+  const int TT[3] = {tsh.tx, tsh.ty, dim == 3 ? tsh.tz : 1};
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = F.n[d];
+    a.ntile[d] = div_up(F.n[d], TT[d]);
+    a.step[d] = F.step[d];
+  }
+  a.nc = F.nc;
+  a.has_drift = F.drift ? 1 : 0;
+  a.ctrl64 = F.ctrl64;
+  a.speed64 = F.speed64;
+  a.drift64 = F.drift64;
+  a.target_part = F.tp;
+  a.feedback = H.feedback.as<uint8_t>();
+  a.N = N;
+  HJB_HIP(launch_feedback(dim, a, H.u0.as<double>(), H.feedback.as<uint8_t>(), s));
+  HJB_HIP(hipStreamSynchronize(s));
+  const double t1 = now_ms();
+
+  // Colour transport, CH parts at a time.
+  const int CH = trace_chunk_capacity(dim);
+  const int ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
+  DBuf phi((size_t)CH * N * sizeof(double)), best(N * sizeof(double));
+  DBuf lists[2], flags[2], count(4 * sizeof(uint32_t)), work(2 * sizeof(unsigned long long));
+  for (int i = 0; i < 2; ++i) {
+    lists[i].reset((size_t)ntiles * sizeof(int32_t));
+    flags[i].reset((size_t)ntiles * sizeof(uint32_t));
+  }
+  HJB_HIP(launch_fill_f64(best.as<double>(), 0.0, N, s));
+  HJB_HIP(launch_fill_i16(H.labels.as<int16_t>(), (int16_t)-1, N, s));
+  HJB_HIP(hipMemsetAsync(work.get(), 0, work.bytes(), s));
+  PinnedBuf host(64);
+  a.phi = phi.as<double>();
+  const int grid = std::min(ntiles, 4096);
+  const int rpp = 4;
+  long long rounds = 0;
+  for (int part0 = 0; part0 < H.n_parts; part0 += CH) {
+    a.chunk = std::min(CH, H.n_parts - part0);
+    a.part0 = part0;
+    HJB_HIP(launch_trace_init(dim, a, s));
+    for (int i = 0; i < 2; ++i) HJB_HIP(launch_fill_u32(flags[i].as<uint32_t>(), 0u, ntiles, s));
+    HJB_HIP(launch_fill_u32(count.as<uint32_t>(), 0u, 4, s));
+    RoundArgs ra;
+    std::memset(&ra, 0, sizeof ra);
+    ra.count = count.as<uint32_t>();
+    ra.work = work.as<unsigned long long>();
+    // seeding appends to list[0]/count[0] as if it were round -1 (== 2 mod 3)
+    ra.list_out = lists[0].as<int32_t>();
+    ra.flags_out = flags[0].as<uint32_t>();
+    ra.round = 2;
+    HJB_HIP(launch_trace_seed(dim, a, ra, s));
+    uint32_t r = 0;
+    while (true) {
+      for (int i = 0; i < rpp; ++i, ++r) {
+        ra.list_in = lists[r & 1].as<int32_t>();
+        ra.list_out = lists[(r + 1) & 1].as<int32_t>();
+        ra.flags_in = flags[r & 1].as<uint32_t>();
+        ra.flags_out = flags[(r + 1) & 1].as<uint32_t>();
+        ra.round = r;
+        HJB_HIP(launch_trace(dim, grid, a, ra, nullptr, s));
+      }
+      rounds += rpp;
+      HJB_HIP(hipMemcpyAsync(host.as<uint32_t>(), count.as<uint32_t>() + (r % 3), sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, s));
+      HJB_HIP(hipStreamSynchronize(s));
+      if (host.as<uint32_t>()[0] == 0) break;
+      HJB_REQUIRE(rounds < 100000000, "colour transport did not settle");
+    }
+    HJB_HIP(launch_label_update(a, best.as<double>(), H.labels.as<int16_t>(), s));
+  }
+  DBuf unreached(sizeof(uint32_t) * 2);
+  HJB_HIP(launch_fill_u32(unreached.as<uint32_t>(), 0u, 1, s));
+  HJB_HIP(launch_label_final(F.tp, N, H.labels.as<int16_t>(), unreached.as<uint32_t>(), s));
+  HJB_HIP(launch_make_code(F.tp, H.labels.as<int16_t>(), nullptr, N, H.code.as<int16_t>(), s));
+  uint32_t un = 0;
+  unsigned long long w[2] = {0, 0};
+  HJB_HIP(hipMemcpyAsync(&un, unreached.get(), sizeof un, hipMemcpyDeviceToHost, s));
+  HJB_HIP(hipMemcpyAsync(w, work.get(), sizeof w, hipMemcpyDeviceToHost, s));
+  HJB_HIP(hipStreamSynchronize(s));
+  const double t2 = now_ms();
+  std::memset(&H.st, 0, sizeof H.st);
+  H.st.ms_prolong_feedback = t1 - t0;
+  H.st.ms_trace = t2 - t1;
+  H.st.trace_node_updates = (int64_t)w[1] * TT[0] * TT[1] * TT[2];
+  H.st.unreached = (int32_t)un;
+  H.st.rounds = (int32_t)rounds;
+  H.st.item_runs = (int64_t)w[1];
+  H.st.updates = (int64_t)F.N * F.nc;  // feedback evaluations
+  H.st.ms_wall = t2 - t0;
+  return hp;
+}
+
+std::unique_ptr<CoarseHandle> coarse_solve_impl(const hjb_problem *coarse, double tol,
+                                                int32_t max_sweeps, hipStream_t s, int *status) {
+  const double t0 = now_ms();
+  validate_problem(coarse, s);
+  auto P = upload_problem(*coarse, false, s);
+  auto h = std::make_unique<CoarseHandle>();
+  h->dim = P->dim;
+  for (int d = 0; d < 3; ++d) h->n[d] = P->n[d];
+  h->N = P->N;
+  h->v.reset(P->N * sizeof(double));
+  DBuf code(P->N * sizeof(int16_t));
+  HJB_HIP(launch_make_code(P->tp, nullptr, nullptr, P->N, code.as<int16_t>(), s));
+  *status = engine_solve(*P, code.as<int16_t>(), 1, h->v.get(), true, nullptr, tol, max_sweeps, s,
+                         &h->st, t0);
+  return h;
+}
+
+}  // namespace hjb
+
+extern "C" {
+
+const char *hjb_last_error(void) { return hjb::last_error_cstr(); }
+
+const char *hjb_version(void) { return "hjb-mi355x 0.1 (gfx950)"; }
+
+int hjb_coarse_solve(const hjb_problem *coarse, double tol, int32_t max_sweeps, hjb_stream_t stream,
+                     hjb_coarse_t **out) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    int status = HJB_OK;
+    auto h = coarse_solve_impl(coarse, tol, max_sweeps, as_stream(stream), &status);
+    auto* ph = new hjb_coarse_s();
+    static_cast<CoarseHandle &>(*ph) = std::move(*h);
+    *out = ph;
+    return status;
+  });
+}
+
+int hjb_coarse_values(const hjb_coarse_t *c, double *out, int32_t mem) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(c != nullptr, "coarse handle is NULL");
+    copy_out(out, c->v.get(), c->N * sizeof(double), mem, nullptr);
+    return HJB_OK;
+  });
+}
+
+void hjb_coarse_free(hjb_coarse_t *c) { delete c; }
+
+int hjb_build_patches(const hjb_problem *fine, const hjb_coarse_t *coarse, hjb_stream_t stream,
+                      hjb_patches_t **out, hjb_stats *st) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    HJB_REQUIRE(coarse != nullptr, "coarse handle is NULL");
+    hipStream_t s = as_stream(stream);
+    validate_problem(fine, s);
+    HJB_REQUIRE(fine->dim == coarse->dim, "fine and coarse dimensions differ");
+    auto F = upload_problem(*fine, false, s);
+    auto h = build_patches_impl(*F, *coarse, s);
+    if (st) *st = h->st;
+    auto* ph = new hjb_patches_s();
+    static_cast<PatchesHandle &>(*ph) = std::move(*h);
+    *out = ph;
+    return HJB_OK;
+  });
+}
+
+int hjb_patches_labels(const hjb_patches_t *p, int16_t *out, int32_t mem) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(p != nullptr, "patches handle is NULL");
+    copy_out(out, p->labels.get(), p->N * sizeof(int16_t), mem, nullptr);
+    return HJB_OK;
+  });
+}
+
+int hjb_patches_feedback(const hjb_patches_t *p, uint8_t *out, int32_t mem) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(p != nullptr, "patches handle is NULL");
+    copy_out(out, p->feedback.get(), p->N, mem, nullptr);
+    return HJB_OK;
+  });
+}
+
+int hjb_patches_u0(const hjb_patches_t *p, double *out, int32_t mem) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(p != nullptr, "patches handle is NULL");
+    copy_out(out, p->u0.get(), p->N * sizeof(double), mem, nullptr);
+    return HJB_OK;
+  });
+}
+
+void hjb_patches_free(hjb_patches_t *p) { delete p; }
+
+int hjb_solve_patches(const hjb_problem *fine, const hjb_patches_t *p, int32_t precision,
+                      double tol, int32_t max_sweeps, void *v_out, const hjb_solve_opts *opts,
+                      hjb_stats *st, hjb_stream_t stream) {
+  return guarded([&]() -> int {
+    const double t0 = now_ms();
+    HJB_REQUIRE(p != nullptr, "patches handle is NULL");
+    HJB_REQUIRE(v_out != nullptr, "v_out is NULL");
+    HJB_REQUIRE(precision == HJB_F32 || precision == HJB_F64, "precision must be HJB_F32 or HJB_F64");
+    hipStream_t s = as_stream(stream);
+    validate_problem(fine, s);
+    HJB_REQUIRE(fine->dim == p->dim && fine->n[0] == p->n[0] && fine->n[1] == p->n[1] &&
+                    fine->n[2] == p->n[2],
+                "problem grid does not match the patches handle");
+    HJB_REQUIRE(fine->n_parts == p->n_parts, "n_parts does not match the patches handle");
+    const bool fp64 = precision == HJB_F64;
+    auto P = upload_problem(*fine, !fp64, s);
+    const int16_t *code = p->code.as<int16_t>();
+    DBuf selcode, sel;
+    if (opts && opts->patch_select) {
+      sel.reset((size_t)p->n_parts);
+      HJB_HIP(hipMemcpyAsync(sel.get(), opts->patch_select, (size_t)p->n_parts,
+                             hipMemcpyHostToDevice, s));
+      selcode.reset(P->N * sizeof(int16_t));
+      HJB_HIP(launch_make_code(P->tp, p->labels.as<int16_t>(), sel.as<uint8_t>(), P->N,
+                               selcode.as<int16_t>(), s));
+      code = selcode.as<int16_t>();
+    }
+    return engine_solve(*P, code, p->n_parts, v_out, fp64, opts, tol, max_sweeps, s, st, t0);
+  });
+}
+
+int hjb_solve_global(const hjb_problem *fine, int32_t precision, double tol, int32_t max_sweeps,
+                     void *v_out, const hjb_solve_opts *opts, hjb_stats *st,
+                     hjb_stream_t stream) {
+  return guarded([&]() -> int {
+    const double t0 = now_ms();
+    HJB_REQUIRE(v_out != nullptr, "v_out is NULL");
+    HJB_REQUIRE(precision == HJB_F32 || precision == HJB_F64, "precision must be HJB_F32 or HJB_F64");
+    hipStream_t s = as_stream(stream);
+    validate_problem(fine, s);
+    const bool fp64 = precision == HJB_F64;
+    auto P = upload_problem(*fine, !fp64, s);
+    DBuf code(P->N * sizeof(int16_t));
+    HJB_HIP(launch_make_code(P->tp, nullptr, nullptr, P->N, code.as<int16_t>(), s));
+    const int sched = opts ? opts->schedule : HJB_SCHED_TILED;
+    if (sched == HJB_SCHED_JACOBI) {
+      (void)make_config(P->dim, fp64, opts, tol, max_sweeps);  // validates opts and tol
+      DBuf cnt(sizeof(unsigned long long));
+      HJB_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(unsigned long long), s));
+      HJB_HIP(launch_count_active(code.as<int16_t>(), P->N, cnt.as<unsigned long long>(), s));
+      unsigned long long active = 0;
+      HJB_HIP(hipMemcpyAsync(&active, cnt.get(), sizeof active, hipMemcpyDeviceToHost, s));
+      HJB_HIP(hipStreamSynchronize(s));
+      hjb_stats local{};
+      const int poll = opts && opts->rounds_per_poll > 0 ? opts->rounds_per_poll : 4;
+      const int status = run_jacobi(*P, code.as<int16_t>(), fp64, v_out, tol,
+                                    max_sweeps > 0 ? max_sweeps : 1000000, poll,
+                                    opts && opts->time_kernels, s, &local);
+      if (st) {
+        *st = local;
+        st->node_updates = (int64_t)active * local.rounds;
+        st->updates = st->node_updates * P->nc;
+        st->status = status;
+        st->ms_wall = now_ms() - t0;
+      }
+      return status;
+    }
+    return engine_solve(*P, code.as<int16_t>(), 1, v_out, fp64, opts, tol, max_sweeps, s, st, t0);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,473 @@
+// Batched solves and the continuous-batching server of libhjb.
+//
+// Both rest on the independence of the patches (Section 3 of the paper:
+// each patch is computed with no information from the others, which is
+// what its distributed "Method 2" exploits).  Work items of many problems --
+// (problem, patch, tile) triples -- share the rounds of one tiled sweep
+// kernel per dimension.  Since every update is monotone and items never
+// write outside their own patch of their own problem, the result of each
+// problem is bitwise the one it gets when solved alone, whatever else is in
+// the mix.
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace hjb;
+
+namespace {
+
+hipStream_t as_stream(hjb_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+// One problem prepared for the shared sweep rounds: Steps 1-3.1 done, value
+// grid initialised, work items built.
+struct Prepared {
+  std::unique_ptr<ProblemDev> P;
+  std::unique_ptr<PatchesHandle> patches;
+  DBuf v;
+  ProblemItems items;
+  int dim = 2;
+  int engine_index = -1;
+  hjb_stats st{};
+  double ms_prepare = 0.0;
+};
+
+// Host copy of an hjb_problem's arrays (for requests queued by the server).
+struct ProblemCopy {
+  hjb_problem p{};
+  std::vector<double> ctrl, speed, drift;
+  std::vector<int16_t> tp;
+  void take(const hjb_problem &src, hipStream_t s) {
+    p = src;
+    const size_t N = (size_t)src.n[0] * src.n[1] * src.n[2];
+    ctrl.resize((size_t)src.n_controls * src.dim);
+    speed.resize(N);
+    tp.resize(N);
+    if (src.drift) drift.resize(N * src.dim);
+    const hipMemcpyKind k = src.mem == HJB_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
+    HJB_HIP(hipMemcpyAsync(ctrl.data(), src.controls, ctrl.size() * sizeof(double), k, s));
+    HJB_HIP(hipMemcpyAsync(speed.data(), src.speed, N * sizeof(double), k, s));
+    HJB_HIP(hipMemcpyAsync(tp.data(), src.target_part, N * sizeof(int16_t), k, s));
+    if (src.drift)
+      HJB_HIP(hipMemcpyAsync(drift.data(), src.drift, drift.size() * sizeof(double), k, s));
+    HJB_HIP(hipStreamSynchronize(s));
+    p.controls = ctrl.data();
+    p.speed = speed.data();
+    p.drift = src.drift ? drift.data() : nullptr;
+    p.target_part = tp.data();
+    p.mem = HJB_MEM_HOST;
+  }
+};
+
+SweepShape engine_shape(int dim, bool fp64, const hjb_solve_opts *opts) {
+  return make_config(dim, fp64, opts, 0.0, 0).shape;
+}
+
+std::unique_ptr<Prepared> prepare(const hjb_problem *fine, const hjb_problem *coarse, bool fp64,
+                                  const hjb_solve_opts *opts, hipStream_t s) {
+  const double t0 = now_ms();
+  validate_problem(fine, s);
+  HJB_REQUIRE(coarse && coarse->dim == fine->dim, "coarse problem missing or of another dimension");
+  int cst = HJB_OK;
+  auto C = coarse_solve_impl(coarse, 0.0, 0, s, &cst);
+  HJB_REQUIRE(cst == HJB_OK, "coarse solve did not converge");
+  auto pr = std::make_unique<Prepared>();
+  pr->dim = fine->dim;
+  pr->P = upload_problem(*fine, !fp64, s);
+  pr->patches = build_patches_impl(*pr->P, *C, s);
+  const size_t N = pr->P->N;
+  pr->v.reset(N * (fp64 ? sizeof(double) : sizeof(float)));
+  HJB_HIP(launch_init_values(fp64, pr->patches->code.as<int16_t>(), N, pr->v.get(), s));
+  pr->items = build_items(*pr->P, pr->patches->code.as<int16_t>(), pr->P->n_parts,
+                          engine_shape(fine->dim, fp64, opts), s);
+  // keep only what the sweeps need
+  pr->patches->u0.release();
+  pr->patches->feedback.release();
+  pr->ms_prepare = now_ms() - t0;
+  return pr;
+}
+
+size_t footprint_bytes(const hjb_problem &f, const hjb_problem &c, bool fp64) {
+  const size_t N = (size_t)f.n[0] * f.n[1] * f.n[2];
+  const size_t Nc = (size_t)c.n[0] * c.n[1] * c.n[2];
+  const size_t per_node = (fp64 ? 8 : 4) /* v */ + 8 + 4 /* speed */ + 2 /* target part */ +
+                          2 + 2 /* labels, code */ + (f.drift ? (8 + 4) * f.dim : 0);
+  const size_t transient = N * (8 /* u0 */ + 1 /* feedback */ + 8 /* best */ +
+                                8 * (size_t)(f.dim == 2 ? 8 : 4) /* colour chunk */);
+  return N * per_node + transient + Nc * 32 + (1u << 20);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- batch
+
+struct hjb_batch_s {
+  hjb_batch_opts opts{};
+  bool fp64 = false;
+  hipStream_t s = nullptr;
+  std::vector<std::unique_ptr<Prepared>> probs;
+  std::unique_ptr<SweepEngine> eng[2];
+  long long rounds[2] = {0, 0};
+  double ms_run = 0.0;
+  int status = HJB_OK;
+  bool ran = false;
+};
+
+extern "C" {
+
+int hjb_batch_create(const hjb_problem *const *fine, const hjb_problem *const *coarse,
+                     int32_t count, const hjb_batch_opts *opts, hjb_stream_t stream,
+                     hjb_batch_t **out) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    HJB_REQUIRE(count >= 1 && fine && coarse, "need count >= 1 fine and coarse problems");
+    auto b = std::make_unique<hjb_batch_s>();
+    if (opts) b->opts = *opts;
+    else b->opts.precision = HJB_F32;
+    HJB_REQUIRE(b->opts.precision == HJB_F32 || b->opts.precision == HJB_F64,
+                "precision must be HJB_F32 or HJB_F64");
+    b->fp64 = b->opts.precision == HJB_F64;
+    b->s = as_stream(stream);
+    for (int i = 0; i < count; ++i) {
+      HJB_REQUIRE(fine[i] && coarse[i], "problem %d is NULL", i);
+      b->probs.push_back(prepare(fine[i], coarse[i], b->fp64, &b->opts.solve, b->s));
+    }
+    for (int d = 0; d < 2; ++d) {
+      const int dim = d + 2;
+      SolveConfig cfg = make_config(dim, b->fp64, &b->opts.solve, b->opts.tol, b->opts.max_sweeps);
+      std::unique_ptr<SweepEngine> e;
+      for (auto &p : b->probs) {
+        if (p->dim != dim) continue;
+        if (!e) e = std::make_unique<SweepEngine>(cfg, b->s);
+        p->engine_index = e->add_problem(*p->P, p->patches->code.as<int16_t>(), &p->items, p->v.get());
+      }
+      if (e) e->begin();
+      b->eng[d] = std::move(e);
+    }
+    *out = b.release();
+    return HJB_OK;
+  });
+}
+
+int hjb_batch_run(hjb_batch_t *b, hjb_stream_t stream, hjb_stats *st) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(b != nullptr, "batch is NULL");
+    HJB_REQUIRE(!b->ran, "batch already ran");
+    (void)stream;
+    const double t0 = now_ms();
+    const long long cap = b->opts.max_sweeps > 0 ? b->opts.max_sweeps : 1000000;
+    const int rpp = std::max(1, b->opts.solve.rounds_per_poll > 0 ? b->opts.solve.rounds_per_poll : 6);
+    bool live[2] = {b->eng[0] != nullptr, b->eng[1] != nullptr};
+    int status = HJB_OK;
+    while (live[0] || live[1]) {
+      for (int d = 0; d < 2; ++d) {
+        if (!live[d]) continue;
+        const int q = b->eng[d]->run_rounds(rpp);
+        b->rounds[d] += rpp;
+        if (q == 0) live[d] = false;
+        else if (b->rounds[d] >= cap) {
+          live[d] = false;
+          status = HJB_ENOCONV;
+        }
+      }
+    }
+    b->ms_run = now_ms() - t0;
+    b->ran = true;
+    b->status = status;
+    int64_t upd = 0, nodes = 0, runs = 0, items = 0;
+    for (int d = 0; d < 2; ++d) {
+      if (!b->eng[d]) continue;
+      auto res = b->eng[d]->results();
+      items += b->eng[d]->total_items();
+      for (auto &p : b->probs) {
+        if (p->dim != d + 2) continue;
+        const EngineResult &r = res[p->engine_index];
+        p->st.node_updates = (int64_t)r.work_nodes;
+        p->st.updates = (int64_t)r.work_nodes * p->P->nc;
+        p->st.item_runs = (int64_t)r.item_runs;
+        p->st.items = (int32_t)p->items.items.size();
+        p->st.residual = r.residual;
+        p->st.rounds = (int32_t)b->rounds[d];
+        p->st.status = status;
+        p->st.ms_prolong_feedback = p->patches->st.ms_prolong_feedback;
+        p->st.ms_trace = p->patches->st.ms_trace;
+        p->st.unreached = p->patches->st.unreached;
+        upd += p->st.updates;
+        nodes += p->st.node_updates;
+        runs += p->st.item_runs;
+      }
+    }
+    if (st) {
+      std::memset(st, 0, sizeof *st);
+      st->updates = upd;
+      st->node_updates = nodes;
+      st->item_runs = runs;
+      st->items = (int32_t)items;
+      st->rounds = (int32_t)std::max(b->rounds[0], b->rounds[1]);
+      st->ms_wall = b->ms_run;
+      st->status = status;
+    }
+    return status;
+  });
+}
+
+int hjb_batch_result(const hjb_batch_t *b, int32_t i, void *v_out, int32_t mem, hjb_stats *st) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(b != nullptr, "batch is NULL");
+    HJB_REQUIRE(i >= 0 && i < (int)b->probs.size(), "problem index %d out of range", i);
+    HJB_REQUIRE(b->ran, "hjb_batch_run has not been called");
+    HJB_REQUIRE(v_out != nullptr, "v_out is NULL");
+    HJB_REQUIRE(mem == HJB_MEM_HOST || mem == HJB_MEM_DEVICE, "bad mem");
+    const Prepared &p = *b->probs[i];
+    HJB_HIP(hipMemcpyAsync(v_out, p.v.get(), p.v.bytes(),
+                           mem == HJB_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, b->s));
+    HJB_HIP(hipStreamSynchronize(b->s));
+    if (st) *st = p.st;
+    return b->status;
+  });
+}
+
+void hjb_batch_free(hjb_batch_t *b) { delete b; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- server
+
+namespace {
+
+enum ReqState { QUEUED = 0, LIVE = 1, DONE = 2 };
+
+struct Request {
+  uint64_t ticket = 0;
+  ProblemCopy fine, coarse;
+  size_t footprint = 0;
+  ReqState state = QUEUED;
+  std::unique_ptr<Prepared> prep;
+  long long rounds_live = 0;
+  int status = HJB_OK;
+  hjb_stats st{};
+};
+
+}  // namespace
+
+struct hjb_server_s {
+  size_t budget = 0, used = 0;
+  hjb_server_opts opts{};
+  bool fp64 = false;
+  hipStream_t s = nullptr;
+  uint64_t next_ticket = 1;
+  std::deque<Request *> queue;
+  std::map<uint64_t, std::unique_ptr<Request>> reqs;
+  std::unique_ptr<SweepEngine> eng[2];
+  std::vector<Request *> members[2];  // engine problem index -> request
+  std::vector<std::unique_ptr<Request>> retired;  // collected, still listed by an engine
+  SolveConfig cfg[2];
+};
+
+namespace {
+
+// Rebuilds the engine of one dimension with the live requests plus `added`,
+// carrying the queued items of the running ones over (a queued item keeps
+// its place; only its global id changes).
+void rebuild_engine(hjb_server_s &S, int d, const std::vector<Request *> &added) {
+  std::vector<int32_t> carried;  // (request index in new list, local id)
+  std::vector<Request *> keep;
+  std::vector<std::vector<int32_t>> carry_local;
+  if (S.eng[d]) {
+    const std::vector<int32_t> q = S.eng[d]->queue_now();
+    std::vector<std::vector<int32_t>> per(S.members[d].size());
+    // map a global id back to (member, local id) through the bases
+    for (int32_t g : q) {
+      int m = (int)S.members[d].size() - 1;
+      while (m > 0 && S.eng[d]->item_base(m) > g) --m;
+      per[m].push_back(g - S.eng[d]->item_base(m));
+    }
+    for (size_t m = 0; m < S.members[d].size(); ++m) {
+      Request *r = S.members[d][m];
+      if (r->state == LIVE) {
+        keep.push_back(r);
+        carry_local.push_back(per[m]);
+      }
+    }
+  }
+  for (Request *r : added) {
+    keep.push_back(r);
+    carry_local.push_back(r->prep->items.seeds);
+  }
+  S.eng[d].reset();
+  S.members[d].clear();
+  if (keep.empty()) return;
+  auto e = std::make_unique<SweepEngine>(S.cfg[d], S.s);
+  std::vector<int32_t> seeds;
+  for (size_t i = 0; i < keep.size(); ++i) {
+    Prepared &p = *keep[i]->prep;
+    p.engine_index = e->add_problem(*p.P, p.patches->code.as<int16_t>(), &p.items, p.v.get());
+  }
+  for (size_t i = 0; i < keep.size(); ++i)
+    for (int32_t l : carry_local[i]) seeds.push_back(e->item_base((int)i) + l);
+  e->begin(&seeds);
+  S.members[d] = keep;
+  S.eng[d] = std::move(e);
+}
+
+// Deletes collected requests that no engine lists any more.
+void drop_retired(hjb_server_s &S) {
+  std::vector<std::unique_ptr<Request>> still;
+  for (auto &r : S.retired) {
+    bool listed = false;
+    for (int d = 0; d < 2; ++d)
+      for (Request *m : S.members[d]) listed |= (m == r.get());
+    if (listed) still.push_back(std::move(r));
+  }
+  S.retired = std::move(still);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hjb_server_create(size_t hbm_budget, const hjb_server_opts *opts, hjb_stream_t stream,
+                      hjb_server_t **out) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    HJB_REQUIRE(hbm_budget > 0, "hbm_budget must be > 0");
+    auto S = std::make_unique<hjb_server_s>();
+    S->budget = hbm_budget;
+    if (opts) S->opts = *opts;
+    else S->opts.precision = HJB_F32;
+    HJB_REQUIRE(S->opts.precision == HJB_F32 || S->opts.precision == HJB_F64,
+                "precision must be HJB_F32 or HJB_F64");
+    S->fp64 = S->opts.precision == HJB_F64;
+    S->s = as_stream(stream);
+    for (int d = 0; d < 2; ++d)
+      S->cfg[d] = make_config(d + 2, S->fp64, &S->opts.solve, S->opts.tol, 0);
+    *out = S.release();
+    return HJB_OK;
+  });
+}
+
+int hjb_server_submit(hjb_server_t *S, const hjb_problem *fine, const hjb_problem *coarse,
+                      uint64_t *ticket) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(S != nullptr && ticket != nullptr, "server or ticket is NULL");
+    validate_problem(fine, S->s);
+    validate_problem(coarse, S->s);
+    HJB_REQUIRE(fine->dim == coarse->dim, "fine and coarse dimensions differ");
+    auto r = std::make_unique<Request>();
+    r->footprint = footprint_bytes(*fine, *coarse, S->fp64);
+    HJB_REQUIRE(r->footprint <= S->budget, "request needs %zu bytes, the budget is %zu",
+                r->footprint, S->budget);
+    r->fine.take(*fine, S->s);
+    r->coarse.take(*coarse, S->s);
+    r->ticket = S->next_ticket++;
+    *ticket = r->ticket;
+    S->queue.push_back(r.get());
+    S->reqs[r->ticket] = std::move(r);
+    return HJB_OK;
+  });
+}
+
+int hjb_server_step(hjb_server_t *S, int32_t rounds, int32_t *live, int32_t *queued) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(S != nullptr, "server is NULL");
+    // Admission by HBM footprint, first come first served.
+    std::vector<Request *> added[2];
+    while (!S->queue.empty() && S->used + S->queue.front()->footprint <= S->budget) {
+      Request *r = S->queue.front();
+      S->queue.pop_front();
+      const double t0 = now_ms();
+      r->prep = prepare(&r->fine.p, &r->coarse.p, S->fp64, &S->opts.solve, S->s);
+      r->st.ms_prolong_feedback = r->prep->patches->st.ms_prolong_feedback;
+      r->st.ms_trace = r->prep->patches->st.ms_trace;
+      r->st.unreached = r->prep->patches->st.unreached;
+      r->st.ms_wall = now_ms() - t0;
+      r->state = LIVE;
+      S->used += r->footprint;
+      added[r->prep->dim - 2].push_back(r);
+      // the request's host copies are no longer needed
+      r->fine = ProblemCopy();
+      r->coarse = ProblemCopy();
+    }
+    for (int d = 0; d < 2; ++d)
+      if (!added[d].empty()) rebuild_engine(*S, d, added[d]);
+    // Shared sweep rounds over every live request.
+    const long long cap = S->opts.max_sweeps > 0 ? S->opts.max_sweeps : 1000000;
+    for (int d = 0; d < 2; ++d) {
+      if (!S->eng[d]) continue;
+      bool any = false;
+      for (Request *r : S->members[d]) any |= r->state == LIVE;
+      if (!any) continue;
+      const int n = std::max(1, rounds);
+      S->eng[d]->run_rounds(n);
+      const std::vector<uint32_t> pa = S->eng[d]->pactive_now();
+      std::vector<EngineResult> res;
+      bool capped = false;
+      for (size_t m = 0; m < S->members[d].size(); ++m) {
+        Request *r = S->members[d][m];
+        if (r->state != LIVE) continue;
+        r->rounds_live += n;
+        const bool conv = pa[m] == 0;
+        if (conv || r->rounds_live >= cap) {
+          if (res.empty()) res = S->eng[d]->results();
+          r->state = DONE;
+          r->status = conv ? HJB_OK : HJB_ENOCONV;
+          capped |= !conv;
+          r->st.node_updates = (int64_t)res[m].work_nodes;
+          r->st.updates = (int64_t)res[m].work_nodes * r->prep->P->nc;
+          r->st.item_runs = (int64_t)res[m].item_runs;
+          r->st.items = (int32_t)r->prep->items.items.size();
+          r->st.residual = res[m].residual;
+          r->st.rounds = (int32_t)r->rounds_live;
+          r->st.status = r->status;
+        }
+      }
+      // A request stopped by the round cap may still have queued items:
+      // rebuild without it so that its buffers are never touched again.
+      if (capped) rebuild_engine(*S, d, {});
+    }
+    drop_retired(*S);
+    int nl = 0;
+    for (int d = 0; d < 2; ++d)
+      for (Request *r : S->members[d]) nl += r->state == LIVE;
+    if (live) *live = nl;
+    if (queued) *queued = (int32_t)S->queue.size();
+    return HJB_OK;
+  });
+}
+
+int hjb_server_poll(hjb_server_t *S, uint64_t ticket, void *v_out, int32_t mem, hjb_stats *st) {
+  return guarded([&]() -> int {
+    HJB_REQUIRE(S != nullptr, "server is NULL");
+    auto it = S->reqs.find(ticket);
+    HJB_REQUIRE(it != S->reqs.end(), "unknown ticket %llu", (unsigned long long)ticket);
+    Request *r = it->second.get();
+    if (r->state != DONE) return HJB_EAGAIN;
+    HJB_REQUIRE(v_out != nullptr, "v_out is NULL");
+    HJB_REQUIRE(mem == HJB_MEM_HOST || mem == HJB_MEM_DEVICE, "bad mem");
+    HJB_HIP(hipMemcpyAsync(v_out, r->prep->v.get(), r->prep->v.bytes(),
+                           mem == HJB_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, S->s));
+    HJB_HIP(hipStreamSynchronize(S->s));
+    if (st) *st = r->st;
+    const int status = r->status;
+    // A finished request has no queued item left (converged, or removed
+    // from its engine when capped), so its device buffers can go now; the
+    // request record lives on while an engine still lists it.
+    S->used -= r->footprint;
+    r->prep.reset();
+    S->retired.push_back(std::move(it->second));
+    S->reqs.erase(it);
+    drop_retired(*S);
+    return status;
+  });
+}
+
+void hjb_server_free(hjb_server_t *S) { delete S; }
+
+}  // extern "C"

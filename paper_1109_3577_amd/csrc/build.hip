@@ -1,0 +1,408 @@
+// Kernels of Steps 2 and 3.1 of the Patchy Algorithm (Section 3 of the
+// paper), all in FP64 with separate multiplies and adds so that the labels
+// they produce are reproducible bit for bit by a plain CPU evaluation:
+//
+//   k_prolong        U^(0) = linear interpolation of the coarse values;
+//   k_feedback       discrete feedback, eq. feedbackcontrol: the first
+//                    control minimising I[U^(0)] at the foot point;
+//   k_trace          colour transport with frozen feedback, eq.
+//                    HJBridotta_discreta, for a chunk of parts at once,
+//                    iterated from below (phi <- max(phi, I[phi])) on LDS
+//                    tiles with active-tile lists until nothing changes;
+//   k_label_update   projection/assembly (eq. proiezionecolore, Remark 3.1):
+//                    running argmax over the parts, lowest index on ties.
+//
+// The transport update is monotone in the colours and starts from below,
+// so like the value iteration it reaches the same least fixed point in any
+// fair order; the tiled schedule changes the work, not the bits.
+
+#include "device_math.h"
+#include "hjb_internal.h"
+
+namespace hjb {
+
+// ---------------------------------------------------------------- prolongation
+
+template <int DIM>
+__global__ void k_prolong(int nf0, int nf1, int nf2, int nc0, int nc1, const double *__restrict__ vc,
+                          const int32_t *__restrict__ Q, const double *__restrict__ T, double *u0) {
+  const size_t N = (size_t)nf0 * nf1 * nf2;
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int x = (int)(g % nf0), y = (int)((g / nf0) % nf1), z = (int)(g / ((size_t)nf0 * nf1));
+  // per-axis tables: [0, nf0) x, [nf0, nf0+nf1) y, then z
+  const int qx = Q[x], qy = Q[nf0 + y];
+  const double tx = T[x], ty = T[nf0 + y];
+  int qz = 0;
+  double tz = 0.0;
+  if (DIM == 3) {
+    qz = Q[nf0 + nf1 + z];
+    tz = T[nf0 + nf1 + z];
+  }
+  auto cv = [&](int a, int b, int c) {
+    return vc[(size_t)(qx + a) + (size_t)nc0 * ((size_t)(qy + b) + (size_t)nc1 * (qz + c))];
+  };
+  double r0 = Ar<double>::lin(tx, cv(0, 0, 0), cv(1, 0, 0));
+  double r1 = Ar<double>::lin(tx, cv(0, 1, 0), cv(1, 1, 0));
+  double val = Ar<double>::lin(ty, r0, r1);
+  if (DIM == 3) {
+    double q0 = Ar<double>::lin(tx, cv(0, 0, 1), cv(1, 0, 1));
+    double q1 = Ar<double>::lin(tx, cv(0, 1, 1), cv(1, 1, 1));
+    double v1 = Ar<double>::lin(ty, q0, q1);
+    val = Ar<double>::lin(tz, val, v1);
+  }
+  u0[g] = val;
+}
+
+hipError_t launch_prolong(int dim, const int32_t nf[3], const int32_t nc[3], const double *vc,
+                          const int32_t *Q, const double *T, double *u0, hipStream_t s) {
+  const size_t N = (size_t)nf[0] * nf[1] * nf[2];
+  const dim3 grid((unsigned)((N + 255) / 256));
+  if (dim == 2)
+    hipLaunchKernelGGL(k_prolong<2>, grid, dim3(256), 0, s, nf[0], nf[1], nf[2], nc[0], nc[1], vc,
+                       Q, T, u0);
+  else
+    hipLaunchKernelGGL(k_prolong<3>, grid, dim3(256), 0, s, nf[0], nf[1], nf[2], nc[0], nc[1], vc,
+                       Q, T, u0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- feedback
+
+// Foot-point displacement d = s (c a_k + w), FP64, separate operations.
+template <int DIM>
+__device__ __forceinline__ void displacement64(const TraceArgs &a, size_t g, int k, double *d) {
+  const double c = a.speed64[g];
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) {
+    double gg = c * a.ctrl64[k * DIM + q];
+    if (a.has_drift) gg = gg + a.drift64[g * DIM + q];
+    d[q] = a.step[q] * gg;
+  }
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256)
+k_feedback(TraceArgs a, const double *__restrict__ u0, uint8_t *__restrict__ fb) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.N) return;
+  if (a.target_part[g] >= 0) {
+    fb[g] = 255;
+    return;
+  }
+  const int px = (int)(g % a.n[0]), py = (int)((g / a.n[0]) % a.n[1]);
+  const int pz = (int)(g / ((size_t)a.n[0] * a.n[1]));
+  double best = 0.0;
+  int bk = 0;
+  for (int k = 0; k < a.nc; ++k) {
+    double d[DIM];
+    displacement64<DIM>(a, g, k, d);
+    const double I = interp_global<double, DIM>(u0, a.n, px, py, pz, d);
+    if (k == 0 || I < best) {
+      best = I;
+      bk = k;
+    }
+  }
+  fb[g] = (uint8_t)bk;
+}
+
+hipError_t launch_feedback(int dim, const TraceArgs &a, const double *u0, uint8_t *fb,
+                           hipStream_t s) {
+  const dim3 grid((unsigned)((a.N + 255) / 256));
+  if (dim == 2) hipLaunchKernelGGL(k_feedback<2>, grid, dim3(256), 0, s, a, u0, fb);
+  else hipLaunchKernelGGL(k_feedback<3>, grid, dim3(256), 0, s, a, u0, fb);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- tracing
+
+// Trace tile shapes and chunk widths (fields per pass), sized for <= 64 KB
+// of LDS per workgroup.
+constexpr int TR2_TX = 32, TR2_TY = 16, TR2_CH = 8;
+constexpr int TR3_TX = 8, TR3_TY = 8, TR3_TZ = 8, TR3_CH = 4;
+constexpr int TR_NT = 256;
+
+int trace_chunk_capacity(int dim) { return dim == 2 ? TR2_CH : TR3_CH; }
+SweepShape trace_shape(int dim) {
+  return dim == 2 ? SweepShape{2, TR2_TX, TR2_TY, 1} : SweepShape{3, TR3_TX, TR3_TY, TR3_TZ};
+}
+
+__global__ void k_trace_init(TraceArgs a) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.N) return;
+  const int tp = a.target_part[g];
+  for (int f = 0; f < a.chunk; ++f) a.phi[(size_t)f * a.N + g] = (tp == a.part0 + f) ? 1.0 : 0.0;
+}
+
+hipError_t launch_trace_init(int dim, const TraceArgs &a, hipStream_t s) {
+  (void)dim;
+  hipLaunchKernelGGL(k_trace_init, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ void queue_tile(const RoundArgs &ra, int item) {
+  if (atomicCAS(&ra.flags_out[item], 0u, 1u) == 0u) {
+    const uint32_t idx = atomicAdd(&ra.count[(ra.round + 1) % 3], 1u);
+    ra.list_out[idx] = item;
+  }
+}
+
+template <int DIM, int TX, int TY, int TZ, int NT, int CH>
+__global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
+  constexpr int LX = TX + 2 * HALO;
+  constexpr int LY = TY + 2 * HALO;
+  constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
+  constexpr int LN = LX * LY * LZ;
+  constexpr int TN = TX * TY * (DIM == 3 ? TZ : 1);
+  constexpr int NPT = TN / NT;
+  static_assert(TN % NT == 0, "tile must be a multiple of the block");
+  __shared__ double s_phi[CH * LN];
+  __shared__ int s_int[8];
+
+  const int tid = threadIdx.x;
+  const uint32_t r = ra.round;
+  if (blockIdx.x == 0 && tid == 0) ra.count[(r + 2) % 3] = 0u;
+  const uint32_t nin = ra.count[r % 3];
+  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+  const int chunk = a.chunk;
+
+  for (uint32_t li = blockIdx.x; li < nin; li += gridDim.x) {
+    const int tt = ra.list_in[li];
+    if (tid == 0) ra.flags_in[tt] = 0u;
+    const int tix = tt % a.ntile[0];
+    const int tiy = (tt / a.ntile[0]) % a.ntile[1];
+    const int tiz = tt / (a.ntile[0] * a.ntile[1]);
+    const int ox = tix * TX, oy = tiy * TY, oz = (DIM == 3) ? tiz * TZ : 0;
+
+    for (int i = tid; i < LN; i += NT) {
+      const int lx = i % LX, ly = (i / LX) % LY, lz = i / (LX * LY);
+      const int gx = ox + lx - HALO, gy = oy + ly - HALO, gz = oz + lz - HALO;
+      bool inb = (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1;
+      if (DIM == 3) inb = inb && (unsigned)gz < (unsigned)n2;
+      const size_t g = inb ? (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0)) : 0;
+#pragma unroll
+      for (int f = 0; f < CH; ++f)
+        s_phi[f * LN + i] = (inb && f < chunk) ? a.phi[(size_t)f * a.N + g] : 0.0;
+    }
+
+    // Per owned node: fixed foot point of its feedback control.
+    int base[NPT];
+    double t0[NPT], t1[NPT], t2[NPT];
+    bool act[NPT];
+    size_t gid[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      const int i = tid + j * NT;
+      const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+      const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+      bool inb = gx < n0 && gy < n1;
+      if (DIM == 3) inb = inb && gz < n2;
+      const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0));
+      gid[j] = g;
+      act[j] = inb && a.target_part[g] < 0;
+      const int off = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
+      base[j] = off;
+      t0[j] = t1[j] = t2[j] = 0.0;
+      if (act[j]) {
+        double d[DIM];
+        displacement64<DIM>(a, g, a.feedback[g], d);
+        const double f0 = __builtin_floor(d[0]), f1 = __builtin_floor(d[1]);
+        t0[j] = d[0] - f0;
+        t1[j] = d[1] - f1;
+        int o = off + (int)f0 + (int)f1 * LX;
+        if (DIM == 3) {
+          const double f2 = __builtin_floor(d[2]);
+          t2[j] = d[2] - f2;
+          o += (int)f2 * (LX * LY);
+        }
+        base[j] = o;
+      }
+    }
+    __syncthreads();
+
+    double old[NPT][CH];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      const int i = tid + j * NT;
+      const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+      const int off = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
+#pragma unroll
+      for (int f = 0; f < CH; ++f) old[j][f] = s_phi[f * LN + off];
+    }
+
+    bool converged = false;
+    for (int it = 0; it < 4096; ++it) {
+      int ch = 0;
+#pragma unroll
+      for (int j = 0; j < NPT; ++j) {
+        if (!act[j]) continue;
+        const int i = tid + j * NT;
+        const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+        const int off = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
+        const int o = base[j];
+#pragma unroll
+        for (int f = 0; f < CH; ++f) {
+          if (f >= chunk) break;
+          const double *sp = s_phi + f * LN;
+          double r0 = Ar<double>::lin(t0[j], sp[o], sp[o + 1]);
+          double r1 = Ar<double>::lin(t0[j], sp[o + LX], sp[o + LX + 1]);
+          double I = Ar<double>::lin(t1[j], r0, r1);
+          if (DIM == 3) {
+            const int oz = o + LX * LY;
+            double q0 = Ar<double>::lin(t0[j], sp[oz], sp[oz + 1]);
+            double q1 = Ar<double>::lin(t0[j], sp[oz + LX], sp[oz + LX + 1]);
+            double I1 = Ar<double>::lin(t1[j], q0, q1);
+            I = Ar<double>::lin(t2[j], I, I1);
+          }
+          if (I > sp[off]) {
+            s_phi[f * LN + off] = I;
+            ch = 1;
+          }
+        }
+      }
+      if (!__syncthreads_or(ch)) {
+        converged = true;
+        break;
+      }
+    }
+
+    int bx0 = 1 << 30, by0 = 1 << 30, bz0 = 1 << 30, bx1 = -1, by1 = -1, bz1 = -1;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      if (!act[j]) continue;
+      const int i = tid + j * NT;
+      const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+      const int off = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
+      bool changed = false;
+#pragma unroll
+      for (int f = 0; f < CH; ++f) {
+        if (f >= chunk) break;
+        const double nv = s_phi[f * LN + off];
+        if (nv != old[j][f]) {
+          a.phi[(size_t)f * a.N + gid[j]] = nv;
+          changed = true;
+        }
+      }
+      if (changed) {
+        bx0 = min(bx0, lx); bx1 = max(bx1, lx);
+        by0 = min(by0, ly); by1 = max(by1, ly);
+        bz0 = min(bz0, lz); bz1 = max(bz1, lz);
+      }
+    }
+    if (tid == 0) {
+      s_int[0] = 1 << 30; s_int[1] = 1 << 30; s_int[2] = 1 << 30;
+      s_int[3] = -1; s_int[4] = -1; s_int[5] = -1;
+    }
+    __syncthreads();
+    if (bx1 >= 0) {
+      atomicMin(&s_int[0], bx0); atomicMin(&s_int[1], by0); atomicMin(&s_int[2], bz0);
+      atomicMax(&s_int[3], bx1); atomicMax(&s_int[4], by1); atomicMax(&s_int[5], bz1);
+    }
+    __syncthreads();
+    const int cx0 = s_int[0], cy0 = s_int[1], cz0 = s_int[2];
+    const int cx1 = s_int[3], cy1 = s_int[4], cz1 = s_int[5];
+    if (cx1 >= 0) {
+      constexpr int NNB = (DIM == 3) ? 27 : 9;
+      if (tid < NNB) {
+        const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = (DIM == 3) ? tid / 9 - 1 : 0;
+        bool need;
+        if (dx == 0 && dy == 0 && dz == 0) need = !converged;
+        else
+          need = (dx < 0 ? cx0 < HALO : dx > 0 ? cx1 >= TX - HALO : true) &&
+                 (dy < 0 ? cy0 < HALO : dy > 0 ? cy1 >= TY - HALO : true) &&
+                 (dz < 0 ? cz0 < HALO : dz > 0 ? cz1 >= TZ - HALO : true);
+        const int nx = tix + dx, ny = tiy + dy, nz = tiz + dz;
+        if (need && nx >= 0 && ny >= 0 && nz >= 0 && nx < a.ntile[0] && ny < a.ntile[1] &&
+            nz < a.ntile[2])
+          queue_tile(ra, nx + a.ntile[0] * (ny + a.ntile[1] * nz));
+      }
+    }
+    if (tid == 0) atomicAdd(&ra.work[1], 1ull);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &ra,
+                        const int32_t *item_map_identity, hipStream_t s) {
+  (void)item_map_identity;
+  if (dim == 2)
+    hipLaunchKernelGGL((k_trace<2, TR2_TX, TR2_TY, 1, TR_NT, TR2_CH>), dim3(grid), dim3(TR_NT), 0,
+                       s, a, ra);
+  else
+    hipLaunchKernelGGL((k_trace<3, TR3_TX, TR3_TY, TR3_TZ, TR_NT, TR3_CH>), dim3(grid),
+                       dim3(TR_NT), 0, s, a, ra);
+  return hipGetLastError();
+}
+
+// Queue, for round 0 of a chunk, every tile within reach of a target node of
+// the chunk's parts (only those tiles can change first).
+__global__ void k_trace_seed(TraceArgs a, int tx, int ty, int tz, RoundArgs ra) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.N) return;
+  const int tp = a.target_part[g];
+  if (tp < a.part0 || tp >= a.part0 + a.chunk) return;
+  const int x = (int)(g % a.n[0]), y = (int)((g / a.n[0]) % a.n[1]);
+  const int z = (int)(g / ((size_t)a.n[0] * a.n[1]));
+  const int dz0 = a.n[2] > 1 ? -1 : 0, dz1 = a.n[2] > 1 ? 1 : 0;
+  for (int dz = dz0; dz <= dz1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int X = x + dx * HALO, Y = y + dy * HALO, Z = z + dz * HALO;
+        if (X < 0 || Y < 0 || Z < 0 || X >= a.n[0] || Y >= a.n[1] || Z >= a.n[2]) continue;
+        queue_tile(ra, X / tx + a.ntile[0] * (Y / ty + a.ntile[1] * (Z / tz)));
+      }
+}
+
+hipError_t launch_trace_seed(int dim, const TraceArgs &a, const RoundArgs &ra, hipStream_t s) {
+  const SweepShape sh = trace_shape(dim);
+  hipLaunchKernelGGL(k_trace_seed, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, sh.tx,
+                     sh.ty, sh.tz, ra);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- labels
+
+__global__ void k_label_update(TraceArgs a, double *best, int16_t *labels) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.N) return;
+  if (a.target_part[g] >= 0) return;
+  double b = best[g];
+  int L = labels[g];
+  for (int f = 0; f < a.chunk; ++f) {
+    const double p = a.phi[(size_t)f * a.N + g];
+    if (p > b) {
+      b = p;
+      L = a.part0 + f;
+    }
+  }
+  best[g] = b;
+  labels[g] = (int16_t)L;
+}
+
+hipError_t launch_label_update(const TraceArgs &a, double *best, int16_t *labels, hipStream_t s) {
+  hipLaunchKernelGGL(k_label_update, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, best,
+                     labels);
+  return hipGetLastError();
+}
+
+__global__ void k_label_final(const int16_t *__restrict__ tp, size_t N, int16_t *labels,
+                              uint32_t *unreached) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int u = 0;
+  if (g < N) {
+    if (tp[g] >= 0) labels[g] = tp[g];
+    else if (labels[g] < 0) u = 1;
+  }
+  // one atomic per wave
+  for (int o = 32; o >= 1; o >>= 1) u += __shfl_xor(u, o, 64);
+  if ((threadIdx.x & 63) == 0 && u) atomicAdd(unreached, (uint32_t)u);
+}
+
+hipError_t launch_label_final(const int16_t *target_part, size_t N, int16_t *labels,
+                              uint32_t *unreached, hipStream_t s) {
+  hipLaunchKernelGGL(k_label_final, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, target_part,
+                     N, labels, unreached);
+  return hipGetLastError();
+}
+
+}  // namespace hjb

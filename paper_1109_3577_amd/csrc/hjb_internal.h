@@ -1,0 +1,145 @@
+// Internal definitions shared by the kernels and the host runtime of libhjb.
+//
+// Device data model (one problem = one fine grid of the patchy solve, or a
+// coarse grid, or the whole grid of a global solve):
+//   - v[N]      value grid (float or double) in x-fastest order;
+//   - code[N]   int16 node role: CODE_TARGET (v fixed at 0), CODE_NONE (never
+//               updated, ghost in every patch), or the patch label j >= 0;
+//   - tiles     the box is cut into TX x TY (x TZ) tiles; a work item is one
+//               (problem, patch, tile) triple and only updates that patch's
+//               nodes of that tile.  Items are scheduled through per-round
+//               active lists (see RoundArgs).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "hjb.h"
+
+namespace hjb {
+
+constexpr int HALO = 2;  // foot points lie within 2 cells (checked on input)
+constexpr int16_t CODE_TARGET = -2;
+constexpr int16_t CODE_NONE = -1;
+
+// Per-problem parameters as the kernels see them.  Lives in device memory
+// (an array of these for a batch).  Pointers are device pointers.
+struct DevProblem {
+  int32_t dim;
+  int32_t n[3];
+  int32_t ntile[3];     // tiles per axis for the sweep tile shape
+  int32_t nc;           // number of controls
+  int32_t n_patches;    // patches addressed by item_map
+  int32_t has_drift;
+  int32_t prob_index;   // index in the batch
+  int32_t pad0;
+  double beta, omb;     // FP64 Kruzkov constants
+  double step[3];       // FP64 h / k_d
+  float betaf, ombf;    // FP32 Kruzkov constants
+  const double *ctrl64; // [nc][dim] a_k (FP64, as given)
+  const float *ctrl32;  // [nc][dim] s_d * a_kd rounded to FP32
+  const double *speed64;
+  const float *speed32;
+  const double *drift64;  // [N][dim] or null
+  const float *drift32;   // [N][dim] s_d * w_d rounded to FP32, or null
+  const int16_t *code;    // [N]
+  void *v;                // [N] float or double
+  const int32_t *item_map;  // [n_patches][ntiles]: local item id or -1
+  int32_t item_base;        // global id of local item 0
+  int32_t pad1;
+  unsigned long long *residual;  // [3] per-round max decrease (FP64 bits)
+  uint32_t *pactive;             // [3] per-round count of queued items
+  unsigned long long *work;      // [2] node updates, item runs
+};
+
+struct Item {
+  int32_t prob;
+  int32_t patch;
+  int32_t tile;
+  int32_t pad;
+};
+
+// Active-list rings of one engine.  Round r reads list[r&1] of length
+// count[r%3] (built in round r-1 with flags[r&1]), appends the items to
+// revisit to list[(r+1)&1] / count[(r+1)%3] using flags[(r+1)&1], and resets
+// count[(r+2)%3] (unused in round r).  Every item clears its own flag of
+// flags[r&1] when it is processed, so the flag array of the next-but-one
+// round starts clear.
+struct RoundArgs {
+  const int32_t *list_in;
+  int32_t *list_out;
+  uint32_t *flags_in;
+  uint32_t *flags_out;
+  uint32_t *count;            // [3]
+  unsigned long long *work;   // [2]: node updates, item runs
+  uint32_t round;
+  int32_t inner_sweeps;
+  int32_t nprob;
+  int32_t pad;
+  double tol;                 // a node "changes" when it decreases by more than tol
+};
+
+// Trace (colour transport) engine arguments.
+struct TraceArgs {
+  int32_t n[3];
+  int32_t ntile[3];
+  int32_t nc;
+  int32_t has_drift;
+  int32_t chunk;     // number of fields in this chunk (<= CH)
+  int32_t part0;     // part index of field 0
+  double step[3];
+  const double *ctrl64;
+  const double *speed64;
+  const double *drift64;
+  const int16_t *target_part;
+  const uint8_t *feedback;
+  double *phi;       // [CH][N]
+  size_t N;
+};
+
+inline int div_up(int a, int b) { return (a + b - 1) / b; }
+
+// Launchers (defined in the .hip translation units).
+struct SweepShape {
+  int dim, tx, ty, tz;
+};
+bool sweep_shape_supported(int dim, int tx, int ty, int tz);
+hipError_t launch_sweep(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
+                        const Item *items, const RoundArgs &ra, hipStream_t s);
+hipError_t launch_jacobi(bool fp64, int dim, const DevProblem *prob_dev, size_t N, const void *vin,
+                         void *vout, unsigned long long *res_slot, hipStream_t s);
+hipError_t launch_tile_bits(int dim, const int16_t *code, const int32_t n[3], const int32_t tile[3],
+                            const int32_t ntile[3], int words, uint32_t *bits, hipStream_t s);
+hipError_t launch_init_values(bool fp64, const int16_t *code, size_t N, void *v, hipStream_t s);
+hipError_t launch_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t s);
+hipError_t launch_scaled_f32(const double *src, float *dst, size_t rows, int dim,
+                             const double step[3], hipStream_t s);
+hipError_t launch_make_code(const int16_t *target_part, const int16_t *labels,
+                            const uint8_t *select, size_t N, int16_t *code, hipStream_t s);
+hipError_t launch_scan_problem(const hjb_problem &P, size_t N, const double amax[3],
+                               unsigned long long *out4, int *bad, hipStream_t s);
+
+// Build step launchers.
+hipError_t launch_prolong(int dim, const int32_t nf[3], const int32_t nc[3], const double *vc,
+                          const int32_t *Q, const double *T, double *u0, hipStream_t s);
+hipError_t launch_feedback(int dim, const TraceArgs &a, const double *u0, uint8_t *fb,
+                           hipStream_t s);
+hipError_t launch_trace_init(int dim, const TraceArgs &a, hipStream_t s);
+int trace_chunk_capacity(int dim);
+SweepShape trace_shape(int dim);
+hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &ra,
+                        const int32_t *item_map_identity, hipStream_t s);
+hipError_t launch_trace_seed(int dim, const TraceArgs &a, const RoundArgs &ra, hipStream_t s);
+hipError_t launch_label_update(const TraceArgs &a, double *best, int16_t *labels, hipStream_t s);
+hipError_t launch_label_final(const int16_t *target_part, size_t N, int16_t *labels,
+                              uint32_t *unreached, hipStream_t s);
+hipError_t launch_count_active(const int16_t *code, size_t N, unsigned long long *out,
+                               hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
+hipError_t launch_fill_i16(int16_t *p, int16_t v, size_t n, hipStream_t s);
+
+}  // namespace hjb

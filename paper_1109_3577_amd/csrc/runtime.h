@@ -1,0 +1,254 @@
+// Host runtime of libhjb: errors, device memory, problem upload and the
+// round engine that drives the tiled sweep kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdarg>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hjb_internal.h"
+
+namespace hjb {
+
+// ---------------------------------------------------------------- errors
+
+struct ApiError {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void throw_error(int code, const char *fmt, ...);
+void set_last_error(const std::string &s);
+
+#define HJB_HIP(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      ::hjb::throw_error(e_ == hipErrorOutOfMemory ? HJB_ENOMEM : HJB_EDEVICE, "%s: %s (%s:%d)", \
+                         #expr, hipGetErrorString(e_), __FILE__, __LINE__);               \
+  } while (0)
+
+#define HJB_REQUIRE(cond, ...)                            \
+  do {                                                    \
+    if (!(cond)) ::hjb::throw_error(HJB_EINVAL, __VA_ARGS__); \
+  } while (0)
+
+// Runs f() and converts exceptions into a status code + last error.
+template <typename F>
+int guarded(F &&f) {
+  try {
+    return f();
+  } catch (const ApiError &e) {
+    set_last_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_last_error("host allocation failed");
+    return HJB_ENOMEM;
+  } catch (...) {
+    set_last_error("unexpected internal error");
+    return HJB_EDEVICE;
+  }
+}
+
+// ---------------------------------------------------------------- memory
+
+// Device memory from a per-process caching pool (hipMalloc only when no
+// cached block of a suitable size exists; blocks return to the pool when the
+// owning DBuf dies).  Every API call synchronises its stream before it
+// returns, so a block handed back is idle.
+class DBuf {
+ public:
+  DBuf() = default;
+  explicit DBuf(size_t bytes);
+  ~DBuf();
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  DBuf(DBuf &&o) noexcept : p_(o.p_), bytes_(o.bytes_), cap_(o.cap_) {
+    o.p_ = nullptr;
+    o.bytes_ = o.cap_ = 0;
+  }
+  DBuf &operator=(DBuf &&o) noexcept;
+  void reset(size_t bytes);
+  void release();
+  template <typename T>
+  T *as() const { return static_cast<T *>(p_); }
+  void *get() const { return p_; }
+  size_t bytes() const { return bytes_; }
+
+ private:
+  void *p_ = nullptr;
+  size_t bytes_ = 0;
+  size_t cap_ = 0;
+};
+
+size_t pool_cached_bytes();
+void pool_trim();
+
+// Pinned host staging (allocated with hipHostMalloc).
+class PinnedBuf {
+ public:
+  explicit PinnedBuf(size_t bytes);
+  ~PinnedBuf();
+  PinnedBuf(const PinnedBuf &) = delete;
+  PinnedBuf &operator=(const PinnedBuf &) = delete;
+  template <typename T>
+  T *as() const { return static_cast<T *>(p_); }
+
+ private:
+  void *p_ = nullptr;
+};
+
+// ---------------------------------------------------------------- problems
+
+struct ProblemDev {
+  int dim = 2;
+  int n[3] = {1, 1, 1};
+  size_t N = 0;
+  int nc = 0;
+  int n_parts = 1;
+  bool drift = false;
+  double step[3] = {0, 0, 0};
+  double beta = 0, omb = 0;
+  // FP64 inputs on the device (owned copies when the caller passed host data)
+  DBuf own_ctrl64, own_speed64, own_drift64, own_tp;
+  const double *ctrl64 = nullptr;
+  const double *speed64 = nullptr;
+  const double *drift64 = nullptr;
+  const int16_t *tp = nullptr;
+  // FP32 copies (s_d folded into controls and drift)
+  DBuf ctrl32, speed32, drift32;
+  std::vector<double> ctrl_host;  // controls on the host
+};
+
+// Checks every documented requirement of an hjb_problem; throws HJB_EINVAL.
+void validate_problem(const hjb_problem *P, hipStream_t s);
+// Uploads / borrows the inputs; builds FP32 copies when need32.
+std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hipStream_t s);
+
+// ---------------------------------------------------------------- engine
+
+struct SolveConfig {
+  bool fp64 = false;
+  SweepShape shape{2, 64, 16, 1};
+  int inner_sweeps = 48;
+  int rounds_per_poll = 6;
+  bool use_graph = false;
+  bool time_kernels = false;
+  double tol = 0.0;
+  long long max_rounds = 1000000;
+};
+
+SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double tol,
+                        int32_t max_sweeps);
+
+// Work items of one problem for one tile shape, built once (tile bitmap on
+// the device, item list on the host).  Item ids are local to the problem.
+struct ProblemItems {
+  std::vector<Item> items;       // prob field is set by the engine
+  DBuf item_map;                 // [n_patches][ntiles] local id or -1
+  std::vector<int32_t> seeds;    // local ids of the items that can change first
+  int ntile[3] = {1, 1, 1};
+  int n_patches = 1;
+};
+
+ProblemItems build_items(const ProblemDev &P, const int16_t *code, int n_patches, SweepShape sh,
+                         hipStream_t s);
+
+// Per-problem result of an engine run.
+struct EngineResult {
+  unsigned long long work_nodes = 0;
+  unsigned long long item_runs = 0;
+  double residual = 0.0;
+};
+
+// Drives rounds of the tiled sweep kernel over the work items of one or
+// more problems (same dimension and precision).  Problems, their values and
+// items are borrowed and must outlive the engine.
+class SweepEngine {
+ public:
+  SweepEngine(const SolveConfig &cfg, hipStream_t s);
+  ~SweepEngine();
+  SweepEngine(const SweepEngine &) = delete;
+  SweepEngine &operator=(const SweepEngine &) = delete;
+  // Adds a problem; returns its index.  `v`, `code` and the inputs are on
+  // the device.
+  int add_problem(const ProblemDev &P, const int16_t *code, const ProblemItems *items, void *v);
+  // Uploads the tables and queues `seeds` (global ids) or, when null, the
+  // seeds of every problem.
+  void begin(const std::vector<int32_t> *seeds = nullptr);
+  // Runs rounds until no item is queued or the round cap (HJB_OK / HJB_ENOCONV).
+  int run();
+  // Enqueues `rounds` rounds, waits, returns the length of the next queue.
+  int run_rounds(int rounds);
+  // The next round's queue (global ids) and per-problem queued counts.
+  std::vector<int32_t> queue_now();
+  std::vector<uint32_t> pactive_now();
+  std::vector<EngineResult> results();
+
+  int item_base(int prob) const { return bases_[prob]; }
+  int n_problems() const { return (int)dps_.size(); }
+  long long rounds() const { return rounds_; }
+  double kernel_ms() const { return kernel_ms_; }
+  int kernel_launches() const { return kernel_launches_; }
+  int total_items() const { return (int)items_h_.size(); }
+
+ private:
+  void launch_round(uint32_t r);
+  SolveConfig cfg_;
+  hipStream_t s_;
+  std::vector<DevProblem> dps_;
+  std::vector<int> bases_;
+  std::vector<const ProblemItems *> pitems_;
+  std::vector<Item> items_h_;
+  DBuf probs_d_, items_d_, lists_[2], flags_[2], count_, counters_;
+  std::unique_ptr<PinnedBuf> host_;
+  long long rounds_ = 0;
+  uint32_t r_ = 0;
+  double kernel_ms_ = 0.0;
+  int kernel_launches_ = 0;
+  int grid_ = 1;
+  hipGraphExec_t graph_ = nullptr;
+  std::vector<hipEvent_t> events_;
+};
+
+// Handles of the C ABI.
+struct CoarseHandle {
+  int dim = 2;
+  int n[3] = {1, 1, 1};
+  size_t N = 0;
+  DBuf v;  // FP64 coarse values
+  hjb_stats st{};
+};
+
+struct PatchesHandle {
+  int dim = 2;
+  int n[3] = {1, 1, 1};
+  size_t N = 0;
+  int n_parts = 1;
+  DBuf labels, feedback, u0, code;
+  hjb_stats st{};
+};
+
+// Step 1: coarse solve (FP64 exact fixed point for tol = 0).
+std::unique_ptr<CoarseHandle> coarse_solve_impl(const hjb_problem *coarse, double tol,
+                                                int32_t max_sweeps, hipStream_t s, int *status);
+// Steps 2 and 3.1 on an uploaded fine problem.
+std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const CoarseHandle &C,
+                                                  hipStream_t s);
+// Value iteration of one problem with the tiled engine (v is initialised).
+int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *v, bool fp64,
+                 const hjb_solve_opts *opts, double tol, int32_t max_sweeps, hipStream_t s,
+                 hjb_stats *st, double t0);
+
+// Plain Jacobi on the whole grid (one launch per sweep).
+int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out, double tol,
+               long long max_sweeps, int poll, bool time_kernels, hipStream_t s, hjb_stats *st);
+
+double now_ms();
+
+}  // namespace hjb

@@ -1,0 +1,704 @@
+// Host runtime of libhjb: error state, caching device allocator, input
+// validation and upload, and the round engine of the tiled sweeps.
+
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+namespace hjb {
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string &s) { g_last_error = s; }
+const char *last_error_cstr() { return g_last_error.c_str(); }
+
+void throw_error(int code, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw ApiError{code, std::string(buf)};
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------- memory pool
+
+namespace {
+struct Pool {
+  std::mutex m;
+  std::map<int, std::multimap<size_t, void *>> free_by_dev;
+  std::unordered_map<void *, std::pair<int, size_t>> info;
+  size_t cached = 0;
+};
+Pool &pool() {
+  static Pool *p = new Pool();  // never destroyed: device memory outlives static teardown order
+  return *p;
+}
+size_t round_size(size_t b) {
+  if (b < 4096) return 4096;
+  // round to a multiple of 1/8 of the next power of two, limits waste to 12.5%
+  size_t p2 = 1;
+  while (p2 < b) p2 <<= 1;
+  const size_t q = std::max<size_t>(p2 / 8, 4096);
+  return (b + q - 1) / q * q;
+}
+void *pool_get(size_t bytes, size_t *cap) {
+  int dev = 0;
+  HJB_HIP(hipGetDevice(&dev));
+  const size_t want = round_size(bytes);
+  Pool &P = pool();
+  {
+    std::lock_guard<std::mutex> g(P.m);
+    auto &fl = P.free_by_dev[dev];
+    auto it = fl.lower_bound(want);
+    if (it != fl.end() && it->first <= want + want / 2) {
+      void *p = it->second;
+      *cap = it->first;
+      P.cached -= it->first;
+      fl.erase(it);
+      return p;
+    }
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    pool_trim();
+    e = hipMalloc(&p, want);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw_error(HJB_ENOMEM, "device allocation of %zu bytes failed", want);
+  }
+  std::lock_guard<std::mutex> g(P.m);
+  P.info[p] = {dev, want};
+  *cap = want;
+  return p;
+}
+void pool_put(void *p) {
+  if (!p) return;
+  Pool &P = pool();
+  std::lock_guard<std::mutex> g(P.m);
+  auto it = P.info.find(p);
+  if (it == P.info.end()) return;
+  P.free_by_dev[it->second.first].insert({it->second.second, p});
+  P.cached += it->second.second;
+}
+}  // namespace
+
+size_t pool_cached_bytes() {
+  std::lock_guard<std::mutex> g(pool().m);
+  return pool().cached;
+}
+
+void pool_trim() {
+  Pool &P = pool();
+  std::lock_guard<std::mutex> g(P.m);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto &kv : P.free_by_dev) {
+    if (kv.first != cur) continue;
+    for (auto &e : kv.second) {
+      (void)hipFree(e.second);
+      P.info.erase(e.second);
+      P.cached -= e.first;
+    }
+    kv.second.clear();
+  }
+}
+
+DBuf::DBuf(size_t bytes) { reset(bytes); }
+DBuf::~DBuf() { release(); }
+DBuf &DBuf::operator=(DBuf &&o) noexcept {
+  if (this != &o) {
+    release();
+    p_ = o.p_;
+    bytes_ = o.bytes_;
+    cap_ = o.cap_;
+    o.p_ = nullptr;
+    o.bytes_ = o.cap_ = 0;
+  }
+  return *this;
+}
+void DBuf::reset(size_t bytes) {
+  if (p_ && bytes <= cap_) {
+    bytes_ = bytes;
+    return;
+  }
+  release();
+  if (bytes == 0) return;
+  p_ = pool_get(bytes, &cap_);
+  bytes_ = bytes;
+}
+void DBuf::release() {
+  if (p_) pool_put(p_);
+  p_ = nullptr;
+  bytes_ = cap_ = 0;
+}
+
+PinnedBuf::PinnedBuf(size_t bytes) {
+  HJB_HIP(hipHostMalloc(&p_, std::max<size_t>(bytes, 64), hipHostMallocDefault));
+}
+PinnedBuf::~PinnedBuf() {
+  if (p_) (void)hipHostFree(p_);
+}
+
+// ---------------------------------------------------------------- validation
+
+static constexpr double kReachLimit = 1.999;  // |displacement| per axis, cells
+
+void validate_problem(const hjb_problem *P, hipStream_t s) {
+  HJB_REQUIRE(P != nullptr, "problem is NULL");
+  HJB_REQUIRE(P->dim == 2 || P->dim == 3, "dim must be 2 or 3 (got %d)", P->dim);
+  for (int d = 0; d < P->dim; ++d)
+    HJB_REQUIRE(P->n[d] >= 2, "n[%d] must be >= 2 (got %d)", d, P->n[d]);
+  if (P->dim == 2) HJB_REQUIRE(P->n[2] == 1, "2D problems need n[2] == 1 (got %d)", P->n[2]);
+  const double Nd = (double)P->n[0] * P->n[1] * P->n[2];
+  HJB_REQUIRE(Nd < 2147483647.0, "grid too large (%.0f nodes)", Nd);
+  HJB_REQUIRE(P->beta >= 0.5 && P->beta < 1.0, "beta must lie in [0.5, 1) (got %.17g)", P->beta);
+  HJB_REQUIRE(P->one_minus_beta == 1.0 - P->beta, "one_minus_beta must equal 1 - beta exactly");
+  HJB_REQUIRE(P->n_controls >= 1 && P->n_controls <= 255, "n_controls must be in 1..255 (got %d)",
+              P->n_controls);
+  HJB_REQUIRE(P->n_parts >= 1 && P->n_parts <= 32767, "n_parts must be in 1..32767 (got %d)",
+              P->n_parts);
+  HJB_REQUIRE(P->controls && P->speed && P->target_part, "controls, speed and target_part are required");
+  HJB_REQUIRE(P->mem == HJB_MEM_HOST || P->mem == HJB_MEM_DEVICE, "mem must be HJB_MEM_HOST or HJB_MEM_DEVICE");
+  for (int d = 0; d < P->dim; ++d)
+    HJB_REQUIRE(std::isfinite(P->step[d]) && P->step[d] > 0.0, "step[%d] must be finite and > 0", d);
+  const size_t N = (size_t)Nd;
+  const int dim = P->dim, nc = P->n_controls;
+  std::vector<double> ctrl((size_t)nc * dim);
+  if (P->mem == HJB_MEM_HOST) {
+    std::memcpy(ctrl.data(), P->controls, ctrl.size() * sizeof(double));
+  } else {
+    HJB_HIP(hipMemcpyAsync(ctrl.data(), P->controls, ctrl.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    HJB_HIP(hipStreamSynchronize(s));
+  }
+  double amax[3] = {0, 0, 0};
+  for (int k = 0; k < nc; ++k)
+    for (int d = 0; d < dim; ++d) {
+      const double a = ctrl[(size_t)k * dim + d];
+      HJB_REQUIRE(std::isfinite(a), "control %d is not finite", k);
+      amax[d] = std::max(amax[d], std::fabs(a));
+    }
+  double reach[3] = {0, 0, 0};
+  int maxpart = -1;
+  if (P->mem == HJB_MEM_HOST) {
+    for (size_t g = 0; g < N; ++g) {
+      const double c = P->speed[g];
+      HJB_REQUIRE(std::isfinite(c) && c >= 0.0, "speed[%zu] must be finite and >= 0", g);
+      for (int d = 0; d < dim; ++d) {
+        const double w = P->drift ? P->drift[g * dim + d] : 0.0;
+        HJB_REQUIRE(std::isfinite(w), "drift[%zu] is not finite", g);
+        reach[d] = std::max(reach[d], P->step[d] * (c * amax[d] + std::fabs(w)));
+      }
+      const int tp = P->target_part[g];
+      HJB_REQUIRE(tp >= -1, "target_part[%zu] = %d < -1", g, tp);
+      maxpart = std::max(maxpart, tp);
+    }
+  } else {
+    DBuf out(4 * sizeof(unsigned long long) + sizeof(int) * 2);
+    HJB_HIP(hipMemsetAsync(out.get(), 0, out.bytes(), s));
+    unsigned long long *o4 = out.as<unsigned long long>();
+    int *bad = reinterpret_cast<int *>(o4 + 4);
+    HJB_HIP(launch_scan_problem(*P, N, amax, o4, bad, s));
+    unsigned long long h[5] = {0, 0, 0, 0, 0};
+    HJB_HIP(hipMemcpyAsync(h, out.get(), sizeof h, hipMemcpyDeviceToHost, s));
+    HJB_HIP(hipStreamSynchronize(s));
+    int badv = 0;
+    std::memcpy(&badv, &h[4], sizeof(int));
+    HJB_REQUIRE(!badv, "speed must be finite and >= 0, drift finite, target_part >= -1");
+    for (int d = 0; d < 3; ++d) std::memcpy(&reach[d], &h[d], sizeof(double));
+    double t;
+    std::memcpy(&t, &h[3], sizeof(double));
+    maxpart = (int)t - 2;
+  }
+  for (int d = 0; d < dim; ++d)
+    HJB_REQUIRE(reach[d] <= kReachLimit,
+                "foot points reach %.4f cells on axis %d; the kernels support < 2 (halo)", reach[d], d);
+  HJB_REQUIRE(maxpart < P->n_parts, "target_part holds part %d >= n_parts %d", maxpart, P->n_parts);
+}
+
+std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hipStream_t s) {
+  auto D = std::make_unique<ProblemDev>();
+  D->dim = P.dim;
+  for (int d = 0; d < 3; ++d) {
+    D->n[d] = P.n[d];
+    D->step[d] = P.step[d];
+  }
+  D->N = (size_t)P.n[0] * P.n[1] * P.n[2];
+  D->nc = P.n_controls;
+  D->n_parts = P.n_parts;
+  D->drift = P.drift != nullptr;
+  D->beta = P.beta;
+  D->omb = P.one_minus_beta;
+  const size_t N = D->N, cb = (size_t)P.n_controls * P.dim * sizeof(double);
+  D->ctrl_host.resize((size_t)P.n_controls * P.dim);
+  if (P.mem == HJB_MEM_HOST) {
+    std::memcpy(D->ctrl_host.data(), P.controls, cb);
+    D->own_ctrl64.reset(cb);
+    D->own_speed64.reset(N * sizeof(double));
+    D->own_tp.reset(N * sizeof(int16_t));
+    HJB_HIP(hipMemcpyAsync(D->own_ctrl64.get(), P.controls, cb, hipMemcpyHostToDevice, s));
+    HJB_HIP(hipMemcpyAsync(D->own_speed64.get(), P.speed, N * sizeof(double), hipMemcpyHostToDevice, s));
+    HJB_HIP(hipMemcpyAsync(D->own_tp.get(), P.target_part, N * sizeof(int16_t), hipMemcpyHostToDevice, s));
+    D->ctrl64 = D->own_ctrl64.as<double>();
+    D->speed64 = D->own_speed64.as<double>();
+    D->tp = D->own_tp.as<int16_t>();
+    if (P.drift) {
+      D->own_drift64.reset(N * P.dim * sizeof(double));
+      HJB_HIP(hipMemcpyAsync(D->own_drift64.get(), P.drift, N * P.dim * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      D->drift64 = D->own_drift64.as<double>();
+    }
+  } else {
+    HJB_HIP(hipMemcpyAsync(D->ctrl_host.data(), P.controls, cb, hipMemcpyDeviceToHost, s));
+    D->ctrl64 = P.controls;
+    D->speed64 = P.speed;
+    D->drift64 = P.drift;
+    D->tp = P.target_part;
+  }
+  if (need32) {
+    D->ctrl32.reset((size_t)P.n_controls * P.dim * sizeof(float));
+    D->speed32.reset(N * sizeof(float));
+    HJB_HIP(launch_scaled_f32(D->ctrl64, D->ctrl32.as<float>(), (size_t)P.n_controls, P.dim, P.step, s));
+    HJB_HIP(launch_f64_to_f32(D->speed64, D->speed32.as<float>(), N, s));
+    if (P.drift) {
+      D->drift32.reset(N * P.dim * sizeof(float));
+      HJB_HIP(launch_scaled_f32(D->drift64, D->drift32.as<float>(), N, P.dim, P.step, s));
+    }
+  }
+  HJB_HIP(hipStreamSynchronize(s));
+  return D;
+}
+
+// ---------------------------------------------------------------- config
+
+static SweepShape default_shape(int dim, bool fp64) {
+  if (dim == 2) return fp64 ? SweepShape{2, 64, 8, 1} : SweepShape{2, 64, 16, 1};
+  return fp64 ? SweepShape{3, 8, 8, 8} : SweepShape{3, 16, 8, 8};
+}
+
+SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double tol,
+                        int32_t max_sweeps) {
+  SolveConfig c;
+  c.fp64 = fp64;
+  c.shape = default_shape(dim, fp64);
+  c.inner_sweeps = dim == 2 ? 48 : 32;
+  c.tol = tol;
+  c.max_rounds = max_sweeps > 0 ? max_sweeps : 1000000;
+  HJB_REQUIRE(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");
+  if (opts) {
+    if (opts->tile[0] > 0) {
+      SweepShape sh{dim, opts->tile[0], opts->tile[1], dim == 3 ? opts->tile[2] : 1};
+      HJB_REQUIRE(sweep_shape_supported(sh.dim, sh.tx, sh.ty, sh.tz),
+                  "unsupported tile shape %dx%dx%d for dim %d", sh.tx, sh.ty, sh.tz, dim);
+      c.shape = sh;
+    }
+    if (opts->inner_sweeps > 0) c.inner_sweeps = opts->inner_sweeps;
+    if (opts->rounds_per_poll > 0) c.rounds_per_poll = opts->rounds_per_poll;
+    c.use_graph = opts->use_graph != 0;
+    c.time_kernels = opts->time_kernels != 0;
+    HJB_REQUIRE(opts->schedule == HJB_SCHED_TILED || opts->schedule == HJB_SCHED_JACOBI,
+                "unknown schedule %d", opts->schedule);
+  }
+  if (c.use_graph) c.rounds_per_poll = std::max(6, (c.rounds_per_poll + 5) / 6 * 6);
+  if (c.time_kernels) c.use_graph = false;
+  return c;
+}
+
+// ---------------------------------------------------------------- engine
+
+ProblemItems build_items(const ProblemDev &P, const int16_t *code, int n_patches, SweepShape sh,
+                         hipStream_t s) {
+  ProblemItems pi;
+  pi.n_patches = n_patches;
+  const int T[3] = {sh.tx, sh.ty, P.dim == 3 ? sh.tz : 1};
+  for (int a = 0; a < 3; ++a) pi.ntile[a] = div_up(P.n[a], T[a]);
+  const int ntiles = pi.ntile[0] * pi.ntile[1] * pi.ntile[2];
+  // one bit per patch plus the last bit of the row for "holds a target node"
+  const int words = (n_patches + 1 + 31) / 32;
+  DBuf bits((size_t)ntiles * words * sizeof(uint32_t));
+  HJB_HIP(launch_fill_u32(bits.as<uint32_t>(), 0u, (size_t)ntiles * words, s));
+  const int32_t tile3[3] = {T[0], T[1], T[2]};
+  const int32_t n3[3] = {P.n[0], P.n[1], P.n[2]};
+  HJB_HIP(launch_tile_bits(P.dim, code, n3, tile3, pi.ntile, words, bits.as<uint32_t>(), s));
+  std::vector<uint32_t> hb((size_t)ntiles * words);
+  HJB_HIP(hipMemcpyAsync(hb.data(), bits.get(), hb.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HJB_HIP(hipStreamSynchronize(s));
+  const int tbit = words * 32 - 1;
+  std::vector<int32_t> imap((size_t)n_patches * ntiles, -1);
+  std::vector<uint8_t> seed_tile(ntiles, 0);
+  const int nt0 = pi.ntile[0], nt1 = pi.ntile[1], nt2 = pi.ntile[2];
+  for (int t = 0; t < ntiles; ++t) {
+    const uint32_t *row = &hb[(size_t)t * words];
+    if (row[tbit >> 5] & (1u << (tbit & 31))) {
+      // a target node reaches (through the 2-node halo) this tile and its neighbours
+      const int tx = t % nt0, ty = (t / nt0) % nt1, tz = t / (nt0 * nt1);
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int x = tx + dx, y = ty + dy, z = tz + dz;
+            if (x < 0 || y < 0 || z < 0 || x >= nt0 || y >= nt1 || z >= nt2) continue;
+            seed_tile[x + nt0 * (y + nt1 * z)] = 1;
+          }
+    }
+    for (int j = 0; j < n_patches; ++j)
+      if (row[j >> 5] & (1u << (j & 31))) {
+        imap[(size_t)j * ntiles + t] = (int32_t)pi.items.size();
+        pi.items.push_back(Item{0, j, t, 0});
+      }
+  }
+  for (size_t i = 0; i < pi.items.size(); ++i)
+    if (seed_tile[pi.items[i].tile]) pi.seeds.push_back((int32_t)i);
+  pi.item_map.reset(std::max<size_t>(imap.size(), 1) * sizeof(int32_t));
+  HJB_HIP(hipMemcpyAsync(pi.item_map.get(), imap.data(), imap.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, s));
+  HJB_HIP(hipStreamSynchronize(s));  // imap is a host temporary
+  return pi;
+}
+
+SweepEngine::SweepEngine(const SolveConfig &cfg, hipStream_t s) : cfg_(cfg), s_(s) {
+  count_.reset(4 * sizeof(uint32_t));
+  host_ = std::make_unique<PinnedBuf>(4096);
+}
+
+SweepEngine::~SweepEngine() {
+  if (graph_) (void)hipGraphExecDestroy(graph_);
+  for (auto e : events_) (void)hipEventDestroy(e);
+}
+
+int SweepEngine::add_problem(const ProblemDev &P, const int16_t *code, const ProblemItems *items,
+                             void *v) {
+  HJB_REQUIRE(cfg_.shape.dim == P.dim, "tile shape dimension mismatch");
+  HJB_REQUIRE(cfg_.fp64 || (P.ctrl32.get() && P.speed32.get()), "FP32 inputs missing");
+  DevProblem d;
+  std::memset(&d, 0, sizeof d);
+  d.dim = P.dim;
+  for (int a = 0; a < 3; ++a) {
+    d.n[a] = P.n[a];
+    d.ntile[a] = items->ntile[a];
+    d.step[a] = P.step[a];
+  }
+  d.nc = P.nc;
+  d.n_patches = items->n_patches;
+  d.has_drift = P.drift ? 1 : 0;
+  d.prob_index = (int)dps_.size();
+  d.beta = P.beta;
+  d.omb = P.omb;
+  d.betaf = (float)P.beta;
+  d.ombf = (float)P.omb;
+  d.ctrl64 = P.ctrl64;
+  d.ctrl32 = P.ctrl32.as<float>();
+  d.speed64 = P.speed64;
+  d.speed32 = P.speed32.as<float>();
+  d.drift64 = P.drift64;
+  d.drift32 = P.drift32.as<float>();
+  d.code = code;
+  d.v = v;
+  d.item_map = items->item_map.as<int32_t>();
+  d.item_base = (int32_t)items_h_.size();
+  bases_.push_back(d.item_base);
+  for (const Item &it : items->items) {
+    Item g = it;
+    g.prob = (int32_t)dps_.size();
+    items_h_.push_back(g);
+  }
+  pitems_.push_back(items);
+  dps_.push_back(d);
+  return (int)dps_.size() - 1;
+}
+
+void SweepEngine::begin(const std::vector<int32_t> *seeds) {
+  const size_t np = dps_.size();
+  counters_.reset(std::max<size_t>(np, 1) * 8 * sizeof(unsigned long long));
+  HJB_HIP(hipMemsetAsync(counters_.get(), 0, counters_.bytes(), s_));
+  for (size_t i = 0; i < np; ++i) {
+    unsigned long long *c = counters_.as<unsigned long long>() + i * 8;
+    dps_[i].residual = c;                                 // [0..2]
+    dps_[i].pactive = reinterpret_cast<uint32_t *>(c + 3);  // 3 x u32 in [3..4]
+    dps_[i].work = c + 5;                                 // [5..6]
+  }
+  probs_d_.reset(std::max<size_t>(np, 1) * sizeof(DevProblem));
+  HJB_HIP(hipMemcpyAsync(probs_d_.get(), dps_.data(), np * sizeof(DevProblem),
+                         hipMemcpyHostToDevice, s_));
+  const size_t ni = std::max<size_t>(items_h_.size(), 1);
+  items_d_.reset(ni * sizeof(Item));
+  HJB_HIP(hipMemcpyAsync(items_d_.get(), items_h_.data(), items_h_.size() * sizeof(Item),
+                         hipMemcpyHostToDevice, s_));
+  for (int i = 0; i < 2; ++i) {
+    lists_[i].reset(ni * sizeof(int32_t));
+    flags_[i].reset(ni * sizeof(uint32_t));
+    HJB_HIP(launch_fill_u32(flags_[i].as<uint32_t>(), 0u, ni, s_));
+  }
+  std::vector<int32_t> sd;
+  if (seeds) {
+    sd = *seeds;
+  } else {
+    for (size_t i = 0; i < np; ++i)
+      for (int32_t l : pitems_[i]->seeds) sd.push_back(bases_[i] + l);
+  }
+  // per-problem queued counts of the first round
+  std::vector<uint32_t> pa(np, 0);
+  for (int32_t g : sd) pa[items_h_[g].prob]++;
+  for (size_t i = 0; i < np; ++i)
+    HJB_HIP(hipMemcpyAsync(dps_[i].pactive, &pa[i], sizeof(uint32_t), hipMemcpyHostToDevice, s_));
+  const uint32_t cnt[4] = {(uint32_t)sd.size(), 0u, 0u, 0u};
+  if (!sd.empty())
+    HJB_HIP(hipMemcpyAsync(lists_[0].get(), sd.data(), sd.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s_));
+  HJB_HIP(hipMemcpyAsync(count_.get(), cnt, sizeof cnt, hipMemcpyHostToDevice, s_));
+  HJB_HIP(hipStreamSynchronize(s_));  // host vectors above are temporaries
+  grid_ = (int)std::min<size_t>(std::max<size_t>(items_h_.size(), 1), 4096);
+  r_ = 0;
+  rounds_ = 0;
+  if (graph_) {
+    (void)hipGraphExecDestroy(graph_);
+    graph_ = nullptr;
+  }
+}
+
+void SweepEngine::launch_round(uint32_t r) {
+  RoundArgs ra;
+  std::memset(&ra, 0, sizeof ra);
+  ra.list_in = lists_[r & 1].as<int32_t>();
+  ra.list_out = lists_[(r + 1) & 1].as<int32_t>();
+  ra.flags_in = flags_[r & 1].as<uint32_t>();
+  ra.flags_out = flags_[(r + 1) & 1].as<uint32_t>();
+  ra.count = count_.as<uint32_t>();
+  ra.work = nullptr;
+  ra.round = r;
+  ra.inner_sweeps = cfg_.inner_sweeps;
+  ra.nprob = (int)dps_.size();
+  ra.tol = cfg_.tol;
+  HJB_HIP(launch_sweep(cfg_.fp64, cfg_.shape, grid_, probs_d_.as<DevProblem>(),
+                       items_d_.as<Item>(), ra, s_));
+}
+
+int SweepEngine::run_rounds(int rounds) {
+  const bool timing = cfg_.time_kernels;
+  // (capture is not possible on the legacy null stream: rounds are then
+  // launched one by one)
+  if (cfg_.use_graph && !timing && s_ != nullptr && rounds % 6 == 0 && r_ % 6 == 0) {
+    // rounds depend on r only through r mod 2 and r mod 3: one captured
+    // block of a multiple of 6 rounds replays for every later block
+    if (!graph_) {
+      hipGraph_t g = nullptr;
+      HJB_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < rounds; ++i) launch_round((uint32_t)i);
+      HJB_HIP(hipStreamEndCapture(s_, &g));
+      HJB_HIP(hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(g);
+    }
+    HJB_HIP(hipGraphLaunch(graph_, s_));
+    r_ += rounds;
+  } else {
+    for (int i = 0; i < rounds; ++i) {
+      if (timing) {
+        while (events_.size() < (size_t)(2 * (kernel_launches_ + 1))) {
+          hipEvent_t e;
+          HJB_HIP(hipEventCreate(&e));
+          events_.push_back(e);
+        }
+        HJB_HIP(hipEventRecord(events_[2 * kernel_launches_], s_));
+      }
+      launch_round(r_);
+      if (timing) {
+        HJB_HIP(hipEventRecord(events_[2 * kernel_launches_ + 1], s_));
+        ++kernel_launches_;
+      }
+      ++r_;
+    }
+  }
+  rounds_ += rounds;
+  uint32_t *h = host_->as<uint32_t>();
+  HJB_HIP(hipMemcpyAsync(h, count_.as<uint32_t>() + (r_ % 3), sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, s_));
+  HJB_HIP(hipStreamSynchronize(s_));
+  return (int)h[0];
+}
+
+int SweepEngine::run() {
+  int status = HJB_OK;
+  while (true) {
+    const int n = (int)std::min<long long>(cfg_.rounds_per_poll, cfg_.max_rounds - rounds_);
+    const int q = run_rounds(std::max(n, 1));
+    if (q == 0) break;
+    if (rounds_ >= cfg_.max_rounds) {
+      status = HJB_ENOCONV;
+      break;
+    }
+  }
+  if (cfg_.time_kernels && kernel_launches_ > 0) {
+    kernel_ms_ = 0.0;
+    for (int i = 0; i < kernel_launches_; ++i) {
+      float ms = 0.0f;
+      HJB_HIP(hipEventElapsedTime(&ms, events_[2 * i], events_[2 * i + 1]));
+      kernel_ms_ += ms;
+    }
+  }
+  return status;
+}
+
+std::vector<int32_t> SweepEngine::queue_now() {
+  uint32_t n = 0;
+  HJB_HIP(hipMemcpyAsync(&n, count_.as<uint32_t>() + (r_ % 3), sizeof n, hipMemcpyDeviceToHost, s_));
+  HJB_HIP(hipStreamSynchronize(s_));
+  std::vector<int32_t> q(n);
+  if (n)
+    HJB_HIP(hipMemcpyAsync(q.data(), lists_[r_ & 1].get(), n * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s_));
+  HJB_HIP(hipStreamSynchronize(s_));
+  return q;
+}
+
+std::vector<uint32_t> SweepEngine::pactive_now() {
+  const size_t np = dps_.size();
+  std::vector<unsigned long long> cnt(np * 8);
+  if (np)
+    HJB_HIP(hipMemcpyAsync(cnt.data(), counters_.get(), np * 8 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s_));
+  HJB_HIP(hipStreamSynchronize(s_));
+  std::vector<uint32_t> out(np);
+  for (size_t i = 0; i < np; ++i)
+    out[i] = reinterpret_cast<const uint32_t *>(&cnt[i * 8 + 3])[r_ % 3];
+  return out;
+}
+
+std::vector<EngineResult> SweepEngine::results() {
+  const size_t np = dps_.size();
+  std::vector<unsigned long long> cnt(np * 8);
+  if (np)
+    HJB_HIP(hipMemcpyAsync(cnt.data(), counters_.get(), np * 8 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s_));
+  HJB_HIP(hipStreamSynchronize(s_));
+  std::vector<EngineResult> out(np);
+  for (size_t i = 0; i < np; ++i) {
+    // residual of the last executed round lives in slot (r - 1) mod 3
+    double rd;
+    std::memcpy(&rd, &cnt[i * 8 + ((r_ + 2) % 3)], sizeof rd);
+    out[i].residual = rd;
+    out[i].work_nodes = cnt[i * 8 + 5];
+    out[i].item_runs = cnt[i * 8 + 6];
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------- Jacobi
+
+int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out, double tol,
+               long long max_sweeps, int poll, bool time_kernels, hipStream_t s, hjb_stats *st) {
+  const size_t N = P.N;
+  const size_t es = fp64 ? sizeof(double) : sizeof(float);
+  DBuf tmp(N * es);
+  DevProblem d;
+  std::memset(&d, 0, sizeof d);
+  d.dim = P.dim;
+  for (int a = 0; a < 3; ++a) {
+    d.n[a] = P.n[a];
+    d.step[a] = P.step[a];
+  }
+  d.nc = P.nc;
+  d.has_drift = P.drift ? 1 : 0;
+  d.beta = P.beta;
+  d.omb = P.omb;
+  d.betaf = (float)P.beta;
+  d.ombf = (float)P.omb;
+  d.ctrl64 = P.ctrl64;
+  d.ctrl32 = P.ctrl32.as<float>();
+  d.speed64 = P.speed64;
+  d.speed32 = P.speed32.as<float>();
+  d.drift64 = P.drift64;
+  d.drift32 = P.drift32.as<float>();
+  d.code = code;
+  DBuf dprob(sizeof(DevProblem));
+  HJB_HIP(hipMemcpyAsync(dprob.get(), &d, sizeof d, hipMemcpyHostToDevice, s));
+  poll = std::max(1, poll);
+  DBuf res((size_t)poll * sizeof(unsigned long long));
+  PinnedBuf hres((size_t)poll * sizeof(unsigned long long));
+  HJB_HIP(launch_init_values(fp64, code, N, v_out, s));
+  void *a = v_out, *b = tmp.get();
+  long long sweeps = 0, executed = 0;
+  int status = HJB_ENOCONV;
+  double last_res = 0.0;
+  std::vector<hipEvent_t> ev;
+  int launches = 0;
+  while (executed < max_sweeps) {
+    HJB_HIP(hipMemsetAsync(res.get(), 0, res.bytes(), s));
+    const int m = (int)std::min<long long>(poll, max_sweeps - executed);
+    for (int i = 0; i < m; ++i) {
+      if (time_kernels) {
+        while (ev.size() < (size_t)(2 * (launches + 1))) {
+          hipEvent_t e;
+          HJB_HIP(hipEventCreate(&e));
+          ev.push_back(e);
+        }
+        HJB_HIP(hipEventRecord(ev[2 * launches], s));
+      }
+      HJB_HIP(launch_jacobi(fp64, P.dim, dprob.as<DevProblem>(), N, a, b,
+                            res.as<unsigned long long>() + i, s));
+      if (time_kernels) {
+        HJB_HIP(hipEventRecord(ev[2 * launches + 1], s));
+        ++launches;
+      }
+      std::swap(a, b);
+    }
+    executed += m;
+    HJB_HIP(hipMemcpyAsync(hres.as<void>(), res.get(), (size_t)m * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s));
+    HJB_HIP(hipStreamSynchronize(s));
+    bool stop = false;
+    for (int i = 0; i < m; ++i) {
+      double rd;
+      std::memcpy(&rd, &hres.as<unsigned long long>()[i], sizeof rd);
+      last_res = rd;
+      if (rd <= tol) {
+        sweeps = executed - m + i + 1;
+        stop = true;
+        break;
+      }
+    }
+    if (stop) {
+      status = HJB_OK;
+      break;
+    }
+    sweeps = executed;
+  }
+  if (a != v_out) HJB_HIP(hipMemcpyAsync(v_out, a, N * es, hipMemcpyDeviceToDevice, s));
+  HJB_HIP(hipStreamSynchronize(s));
+  if (st) {
+    // active non-target nodes: count once on the host side of the caller;
+    // node_updates is filled there
+    st->rounds = (int32_t)executed;
+    st->residual = last_res;
+    st->items = 0;
+    st->item_runs = 0;
+    double ms = 0.0;
+    for (int i = 0; i < launches; ++i) {
+      float t = 0.0f;
+      HJB_HIP(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
+      ms += t;
+    }
+    st->ms_kernel = ms;
+    st->kernel_launches = launches;
+    st->reserved = (int32_t)sweeps;
+  }
+  for (auto e : ev) (void)hipEventDestroy(e);
+  return status;
+}
+
+}  // namespace hjb

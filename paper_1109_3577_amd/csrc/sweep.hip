@@ -1,0 +1,560 @@
+// Value-iteration kernels of the Kruzkov-form semi-Lagrangian scheme
+// (Section 2.1 of the paper, eqs. SLscheme and iterativeSLscheme):
+//
+//   v_p <- min(v_p, beta * min_k I[v](p + s (c_p a_k + w_p)) + 1 - beta)
+//
+// on the non-target nodes of one patch (Step 3.2 of the Patchy Algorithm),
+// of the whole grid (global solve) or of the coarse grid (Step 1).
+//
+// Every update is monotone in the values it reads (linear interpolation in
+// weights form, min, multiply-add by beta > 0), and value iteration starts
+// from above (v = 1 off the target).  Hence any fair order of updates --
+// Jacobi, in-place, tiled, several tiles at once -- decreases towards the
+// same greatest fixed point and stops on the same bits when nothing changes.
+// The kernels exploit this freedom: a tile plus a 2-node halo is staged in
+// LDS, swept in place until it stops changing, written back, and only the
+// tiles next to changed nodes are queued for the next round.
+//
+// FP64 kernels keep every multiply and add separate (the library is built
+// with contraction off) so that they reproduce the plain CPU evaluation bit
+// for bit.  FP32 kernels use fused multiply-adds.
+
+#include "device_math.h"
+#include "hjb_internal.h"
+
+namespace hjb {
+
+// ---------------------------------------------------------------- tiled sweep
+
+template <typename T, int DIM, int TX, int TY, int TZ, int NT, bool DRIFT>
+__device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item,
+                                           const RoundArgs &ra, T *s_v, int *s_int,
+                                           double *s_red) {
+  constexpr int LX = TX + 2 * HALO;
+  constexpr int LY = TY + 2 * HALO;
+  constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
+  constexpr int LN = LX * LY * LZ;
+  constexpr int TN = TX * TY * (DIM == 3 ? TZ : 1);
+  constexpr int NPT = TN / NT;
+  static_assert(TN % NT == 0, "tile must be a multiple of the block");
+
+  const int tid = threadIdx.x;
+  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const int tt = item.tile;
+  const int tix = tt % P.ntile[0];
+  const int tiy = (tt / P.ntile[0]) % P.ntile[1];
+  const int tiz = tt / (P.ntile[0] * P.ntile[1]);
+  const int ox = tix * TX, oy = tiy * TY, oz = (DIM == 3) ? tiz * TZ : 0;
+  const int patch = item.patch;
+  T *__restrict__ v = (T *)P.v;
+  const int16_t *__restrict__ code = P.code;
+
+  // Stage tile + halo: stored value where the node is active in this patch
+  // (target nodes are 0, patch nodes carry v), ghost 1 everywhere else.
+  for (int i = tid; i < LN; i += NT) {
+    const int lx = i % LX;
+    const int ly = (i / LX) % LY;
+    const int lz = i / (LX * LY);
+    const int gx = ox + lx - HALO, gy = oy + ly - HALO, gz = oz + lz - HALO;
+    T val = T(1);
+    bool inb = (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1;
+    if constexpr (DIM == 3) inb = inb && (unsigned)gz < (unsigned)n2;
+    if (inb) {
+      const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0));
+      const int cd = code[g];
+      if (cd == CODE_TARGET) val = T(0);
+      else if (cd == patch) val = v[g];
+    }
+    s_v[i] = val;
+  }
+
+  T cc[NPT];
+  T ww[NPT][DIM];
+  int off[NPT];
+  size_t gid[NPT];
+  bool act[NPT];
+  int nact = 0;
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int i = tid + j * NT;
+    const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+    const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+    bool inb = gx < n0 && gy < n1;
+    if constexpr (DIM == 3) inb = inb && gz < n2;
+    off[j] = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
+    const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0));
+    gid[j] = g;
+    act[j] = inb && code[g] == patch;
+    nact += act[j] ? 1 : 0;
+    if constexpr (sizeof(T) == 4) {
+      cc[j] = act[j] ? P.speed32[g] : 0.0f;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) ww[j][a] = (DRIFT && act[j]) ? P.drift32[g * DIM + a] : 0.0f;
+    } else {
+      cc[j] = act[j] ? P.speed64[g] : 0.0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) ww[j][a] = (DRIFT && act[j]) ? P.drift64[g * DIM + a] : 0.0;
+    }
+  }
+  __syncthreads();
+
+  T old[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) old[j] = s_v[off[j]];
+
+  const T beta = sizeof(T) == 4 ? (T)P.betaf : (T)P.beta;
+  const T omb = sizeof(T) == 4 ? (T)P.ombf : (T)P.omb;
+  const T tolT = (T)ra.tol;
+  const int nc = P.nc;
+  const int K = ra.inner_sweeps;
+  int iters = 0;
+  bool converged = false;
+  for (int it = 0; it < K; ++it) {
+    T mI[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) mI[j] = T(3);
+    for (int k = 0; k < nc; ++k) {
+      T a[DIM];
+      if constexpr (sizeof(T) == 4) {
+        cf32p cp = (cf32p)(P.ctrl32);
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) a[q] = cp[k * DIM + q];
+      } else {
+        cf64p cp = (cf64p)(P.ctrl64);
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) a[q] = cp[k * DIM + q];
+      }
+#pragma unroll
+      for (int j = 0; j < NPT; ++j) {
+        T d[DIM];
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) {
+          if constexpr (sizeof(T) == 4) {
+            d[q] = DRIFT ? __builtin_fmaf(cc[j], a[q], ww[j][q]) : cc[j] * a[q];
+          } else {
+            T g = cc[j] * a[q];
+            if (DRIFT) g = g + ww[j][q];
+            d[q] = P.step[q] * g;
+          }
+        }
+        T I = interp_lds<T, DIM, LX, LY>(s_v, off[j], d);
+        mI[j] = I < mI[j] ? I : mI[j];
+      }
+    }
+    int ch = 0;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      if (act[j]) {
+        // min_k (beta I_k + omb) == beta (min_k I_k) + omb: the map is
+        // monotone, also after rounding.
+        const T cand = Ar<T>::kruzkov(beta, mI[j], omb);
+        const T cur = s_v[off[j]];
+        if (cand < cur) {
+          s_v[off[j]] = cand;
+          if (cur - cand > tolT) ch = 1;
+        }
+      }
+    }
+    ++iters;
+    if (!__syncthreads_or(ch)) {
+      converged = true;
+      break;
+    }
+  }
+
+  // Write back, FP64 residual, bounding box of the changed nodes.
+  double dmax = 0.0;
+  int bx0 = 1 << 30, by0 = 1 << 30, bz0 = 1 << 30, bx1 = -1, by1 = -1, bz1 = -1;
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    if (act[j]) {
+      const T nv = s_v[off[j]];
+      if (nv < old[j]) {
+        v[gid[j]] = nv;
+        const double dd = (double)old[j] - (double)nv;
+        dmax = dd > dmax ? dd : dmax;
+        if (old[j] - nv > tolT) {
+          const int i = tid + j * NT;
+          const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+          bx0 = min(bx0, lx); bx1 = max(bx1, lx);
+          by0 = min(by0, ly); by1 = max(by1, ly);
+          bz0 = min(bz0, lz); bz1 = max(bz1, lz);
+        }
+      }
+    }
+  }
+  if (tid == 0) {
+    s_int[0] = 1 << 30; s_int[1] = 1 << 30; s_int[2] = 1 << 30;
+    s_int[3] = -1; s_int[4] = -1; s_int[5] = -1;
+  }
+  wave_max(dmax);
+  __syncthreads();
+  if ((tid & 63) == 0) s_red[tid >> 6] = dmax;
+  if (bx1 >= 0) {
+    atomicMin(&s_int[0], bx0); atomicMin(&s_int[1], by0); atomicMin(&s_int[2], bz0);
+    atomicMax(&s_int[3], bx1); atomicMax(&s_int[4], by1); atomicMax(&s_int[5], bz1);
+  }
+  __syncthreads();
+  const int cx0 = s_int[0], cy0 = s_int[1], cz0 = s_int[2];
+  const int cx1 = s_int[3], cy1 = s_int[4], cz1 = s_int[5];
+  if (tid == 0) {
+    double m = 0.0;
+    for (int w = 0; w < NT / 64; ++w) m = s_red[w] > m ? s_red[w] : m;
+    if (m > 0.0) atomicMax(&P.residual[ra.round % 3], (unsigned long long)__double_as_longlong(m));
+    atomicAdd(&P.work[1], 1ull);
+  }
+  // node updates: active nodes of the item x iterations
+  {
+    int c = nact;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((tid & 63) == 0 && c > 0) atomicAdd(&P.work[0], (unsigned long long)c * (unsigned long long)iters);
+  }
+
+  // Queue the neighbour items (same patch) whose halo holds a changed node,
+  // and this item again if its in-LDS sweeps did not settle.
+  if (cx1 >= 0) {
+    constexpr int NNB = (DIM == 3) ? 27 : 9;
+    if (tid < NNB) {
+      const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = (DIM == 3) ? tid / 9 - 1 : 0;
+      bool need;
+      if (dx == 0 && dy == 0 && dz == 0) {
+        need = !converged;
+      } else {
+        need = (dx < 0 ? cx0 < HALO : dx > 0 ? cx1 >= TX - HALO : true) &&
+               (dy < 0 ? cy0 < HALO : dy > 0 ? cy1 >= TY - HALO : true) &&
+               (dz < 0 ? cz0 < HALO : dz > 0 ? cz1 >= TZ - HALO : true);
+      }
+      const int nx = tix + dx, ny = tiy + dy, nz = tiz + dz;
+      if (need && nx >= 0 && ny >= 0 && nz >= 0 && nx < P.ntile[0] && ny < P.ntile[1] &&
+          nz < P.ntile[2]) {
+        const int t2 = nx + P.ntile[0] * (ny + P.ntile[1] * nz);
+        const int ntiles = P.ntile[0] * P.ntile[1] * P.ntile[2];
+        const int it2 = P.item_map[(size_t)patch * ntiles + t2];
+        if (it2 >= 0) queue_item(ra, P.item_base + it2, &P.pactive[(ra.round + 1) % 3]);
+      }
+    }
+  }
+}
+
+template <typename T, int DIM, int TX, int TY, int TZ, int NT>
+__global__ void __launch_bounds__(NT)
+k_sweep(const DevProblem *__restrict__ probs, const Item *__restrict__ items, RoundArgs ra) {
+  constexpr int LX = TX + 2 * HALO;
+  constexpr int LY = TY + 2 * HALO;
+  constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
+  __shared__ T s_v[LX * LY * LZ];
+  __shared__ int s_int[8];
+  __shared__ double s_red[NT / 64];
+  const uint32_t r = ra.round;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) ra.count[(r + 2) % 3] = 0u;
+    for (int p = threadIdx.x; p < ra.nprob; p += NT) {
+      probs[p].pactive[(r + 2) % 3] = 0u;
+      probs[p].residual[(r + 2) % 3] = 0ull;
+    }
+  }
+  const uint32_t nin = ra.count[r % 3];
+  for (uint32_t li = blockIdx.x; li < nin; li += gridDim.x) {
+    const int it = ra.list_in[li];
+    const Item item = items[it];
+    const DevProblem &P = probs[item.prob];
+    if (threadIdx.x == 0) ra.flags_in[it] = 0u;
+    if (P.has_drift)
+      sweep_item<T, DIM, TX, TY, TZ, NT, true>(P, item, ra, s_v, s_int, s_red);
+    else
+      sweep_item<T, DIM, TX, TY, TZ, NT, false>(P, item, ra, s_v, s_int, s_red);
+    __syncthreads();
+  }
+}
+
+#define HJB_SHAPES(X)      \
+  X(2, 64, 16, 1, 256)     \
+  X(2, 32, 32, 1, 256)     \
+  X(2, 64, 8, 1, 256)      \
+  X(2, 32, 16, 1, 256)     \
+  X(3, 16, 8, 8, 256)      \
+  X(3, 8, 8, 8, 256)       \
+  X(3, 32, 8, 4, 256)
+
+bool sweep_shape_supported(int dim, int tx, int ty, int tz) {
+#define HJB_CHECK_SHAPE(D, A, B, C, NT) \
+  if (dim == D && tx == A && ty == B && tz == C) return true;
+  HJB_SHAPES(HJB_CHECK_SHAPE)
+#undef HJB_CHECK_SHAPE
+  return false;
+}
+
+hipError_t launch_sweep(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
+                        const Item *items, const RoundArgs &ra, hipStream_t s) {
+#define HJB_LAUNCH_SHAPE(D, A, B, C, NT)                                                    \
+  if (sh.dim == D && sh.tx == A && sh.ty == B && sh.tz == C) {                              \
+    if (fp64)                                                                               \
+      hipLaunchKernelGGL((k_sweep<double, D, A, B, C, NT>), dim3(grid), dim3(NT), 0, s,    \
+                         probs, items, ra);                                                 \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_sweep<float, D, A, B, C, NT>), dim3(grid), dim3(NT), 0, s,     \
+                         probs, items, ra);                                                 \
+    return hipGetLastError();                                                               \
+  }
+  HJB_SHAPES(HJB_LAUNCH_SHAPE)
+#undef HJB_LAUNCH_SHAPE
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- plain Jacobi
+
+// One full-grid Jacobi sweep: vout = min(vin, F(vin)); the plain global solve.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256)
+k_jacobi(const DevProblem *__restrict__ Pp, const T *__restrict__ vin, T *__restrict__ vout,
+         unsigned long long *res_slot) {
+  const DevProblem &P = *Pp;
+  const size_t N = (size_t)P.n[0] * P.n[1] * P.n[2];
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double dd = 0.0;
+  if (g < N) {
+    const int cd = P.code[g];
+    const T old = vin[g];
+    T nv = old;
+    if (cd == CODE_TARGET) {
+      nv = T(0);
+    } else if (cd >= 0) {
+      const int px = (int)(g % P.n[0]);
+      const int py = (int)((g / P.n[0]) % P.n[1]);
+      const int pz = (int)(g / ((size_t)P.n[0] * P.n[1]));
+      T c, w[DIM];
+      if constexpr (sizeof(T) == 4) {
+        c = P.speed32[g];
+        for (int a = 0; a < DIM; ++a) w[a] = P.has_drift ? P.drift32[g * DIM + a] : 0.0f;
+      } else {
+        c = P.speed64[g];
+        for (int a = 0; a < DIM; ++a) w[a] = P.has_drift ? P.drift64[g * DIM + a] : 0.0;
+      }
+      T mI = T(3);
+      for (int k = 0; k < P.nc; ++k) {
+        T d[DIM];
+        for (int q = 0; q < DIM; ++q) {
+          if constexpr (sizeof(T) == 4) {
+            const float a = ((cf32p)P.ctrl32)[k * DIM + q];
+            d[q] = P.has_drift ? __builtin_fmaf(c, a, w[q]) : c * a;
+          } else {
+            const double a = ((cf64p)P.ctrl64)[k * DIM + q];
+            double gg = c * a;
+            if (P.has_drift) gg = gg + w[q];
+            d[q] = P.step[q] * gg;
+          }
+        }
+        const T I = interp_global<T, DIM>(vin, P.n, px, py, pz, d);
+        mI = I < mI ? I : mI;
+      }
+      const T beta = sizeof(T) == 4 ? (T)P.betaf : (T)P.beta;
+      const T omb = sizeof(T) == 4 ? (T)P.ombf : (T)P.omb;
+      const T cand = Ar<T>::kruzkov(beta, mI, omb);
+      nv = cand < old ? cand : old;
+      dd = (double)old - (double)nv;
+    }
+    vout[g] = nv;
+  }
+  wave_max(dd);
+  if ((threadIdx.x & 63) == 0 && dd > 0.0)
+    atomicMax(res_slot, (unsigned long long)__double_as_longlong(dd));
+}
+
+hipError_t launch_jacobi(bool fp64, int dim, const DevProblem *prob_dev, size_t N, const void *vin,
+                         void *vout, unsigned long long *res_slot, hipStream_t s) {
+  const int grid = (int)((N + 255) / 256);
+  if (fp64) {
+    if (dim == 2)
+      hipLaunchKernelGGL((k_jacobi<double, 2>), dim3(grid), dim3(256), 0, s, prob_dev,
+                         (const double *)vin, (double *)vout, res_slot);
+    else
+      hipLaunchKernelGGL((k_jacobi<double, 3>), dim3(grid), dim3(256), 0, s, prob_dev,
+                         (const double *)vin, (double *)vout, res_slot);
+  } else {
+    if (dim == 2)
+      hipLaunchKernelGGL((k_jacobi<float, 2>), dim3(grid), dim3(256), 0, s, prob_dev,
+                         (const float *)vin, (float *)vout, res_slot);
+    else
+      hipLaunchKernelGGL((k_jacobi<float, 3>), dim3(grid), dim3(256), 0, s, prob_dev,
+                         (const float *)vin, (float *)vout, res_slot);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- helpers
+
+// bits[tile][w]: bit j set when the tile holds a non-target node of patch
+// j; bit `words*32-1`... the last bit of the row (index npatch) marks tiles
+// holding a target node.
+__global__ void k_tile_bits(const int16_t *__restrict__ code, int n0, int n1, int n2, int tx,
+                            int ty, int tz, int nt0, int nt1, int words, int npatch,
+                            uint32_t *bits) {
+  const size_t N = (size_t)n0 * n1 * n2;
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int cd = code[g];
+  const int x = (int)(g % n0), y = (int)((g / n0) % n1), z = (int)(g / ((size_t)n0 * n1));
+  const int t = x / tx + nt0 * (y / ty + nt1 * (z / tz));
+  int bit = -1;
+  if (cd == CODE_TARGET) bit = npatch;
+  else if (cd >= 0) bit = cd;
+  if (bit >= 0) atomicOr(&bits[(size_t)t * words + (bit >> 5)], 1u << (bit & 31));
+}
+
+hipError_t launch_tile_bits(int dim, const int16_t *code, const int32_t n[3], const int32_t tile[3],
+                            const int32_t ntile[3], int words, uint32_t *bits, hipStream_t s) {
+  (void)dim;
+  const size_t N = (size_t)n[0] * n[1] * n[2];
+  const int npatch = words * 32 - 1;  // caller sizes words so the last bit is the target bit
+  hipLaunchKernelGGL(k_tile_bits, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, code, n[0],
+                     n[1], n[2], tile[0], tile[1], tile[2], ntile[0], ntile[1], words, npatch, bits);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_init_values(const int16_t *__restrict__ code, size_t N, T *v) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < N) v[g] = code[g] == CODE_TARGET ? T(0) : T(1);
+}
+
+hipError_t launch_init_values(bool fp64, const int16_t *code, size_t N, void *v, hipStream_t s) {
+  const unsigned grid = (unsigned)((N + 255) / 256);
+  if (fp64) hipLaunchKernelGGL(k_init_values<double>, dim3(grid), dim3(256), 0, s, code, N, (double *)v);
+  else hipLaunchKernelGGL(k_init_values<float>, dim3(grid), dim3(256), 0, s, code, N, (float *)v);
+  return hipGetLastError();
+}
+
+__global__ void k_f64_to_f32(const double *__restrict__ src, float *dst, size_t n) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) dst[g] = (float)src[g];
+}
+
+hipError_t launch_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+// dst[r][d] = float(step[d] * src[r][d]) (per-axis scaling of vectors)
+__global__ void k_scaled_f32(const double *__restrict__ src, float *dst, size_t rows, int dim,
+                             double s0, double s1, double s2) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= rows * dim) return;
+  const int d = (int)(g % dim);
+  const double sc = d == 0 ? s0 : (d == 1 ? s1 : s2);
+  dst[g] = (float)(sc * src[g]);
+}
+
+hipError_t launch_scaled_f32(const double *src, float *dst, size_t rows, int dim,
+                             const double step[3], hipStream_t s) {
+  const size_t n = rows * dim;
+  hipLaunchKernelGGL(k_scaled_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst,
+                     rows, dim, step[0], step[1], step[2]);
+  return hipGetLastError();
+}
+
+// code = target ? TARGET : (labels ? (selected(label) ? label : NONE) : 0)
+__global__ void k_make_code(const int16_t *__restrict__ tp, const int16_t *__restrict__ lab,
+                            const uint8_t *__restrict__ sel, size_t N, int16_t *code) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  int16_t c;
+  if (tp[g] >= 0) c = CODE_TARGET;
+  else if (!lab) c = 0;
+  else {
+    const int L = lab[g];
+    c = (L >= 0 && (!sel || sel[L])) ? (int16_t)L : CODE_NONE;
+  }
+  code[g] = c;
+}
+
+hipError_t launch_make_code(const int16_t *target_part, const int16_t *labels,
+                            const uint8_t *select, size_t N, int16_t *code, hipStream_t s) {
+  hipLaunchKernelGGL(k_make_code, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, target_part,
+                     labels, select, N, code);
+  return hipGetLastError();
+}
+
+// Input scan of a device-resident problem: out4 = {max reach x, y, z,
+// max target part}; *bad |= 1 on a non-finite or negative speed / drift.
+__global__ void k_scan(const double *__restrict__ speed, const double *__restrict__ drift,
+                       const int16_t *__restrict__ tp, size_t N, int dim, double ax, double ay,
+                       double az, double s0, double s1, double s2, unsigned long long *out,
+                       int *bad) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double r[3] = {0.0, 0.0, 0.0};
+  double tmax = -1.0;
+  int b = 0;
+  if (g < N) {
+    const double c = speed[g];
+    if (!(c >= 0.0) || !(c < 1e300)) b = 1;
+    const double am[3] = {ax, ay, az};
+    const double st[3] = {s0, s1, s2};
+    for (int d = 0; d < dim; ++d) {
+      double w = drift ? drift[g * dim + d] : 0.0;
+      if (!(w == w) || !(w < 1e300 && w > -1e300)) b = 1;
+      r[d] = st[d] * (c * am[d] + (w < 0 ? -w : w));
+    }
+    tmax = (double)tp[g];
+    if (tp[g] < -1) b = 1;
+  }
+  for (int d = 0; d < 3; ++d) {
+    double x = r[d];
+    wave_max(x);
+    if ((threadIdx.x & 63) == 0 && x > 0.0) atomicMax(&out[d], (unsigned long long)__double_as_longlong(x));
+  }
+  double t = tmax + 2.0;  // >= 0
+  wave_max(t);
+  if ((threadIdx.x & 63) == 0) atomicMax(&out[3], (unsigned long long)__double_as_longlong(t));
+  if (b) atomicOr(bad, 1);
+}
+
+hipError_t launch_scan_problem(const hjb_problem &P, size_t N, const double amax[3],
+                               unsigned long long *out4, int *bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P.speed, P.drift,
+                     P.target_part, N, P.dim, amax[0], amax[1], amax[2], P.step[0], P.step[1],
+                     P.step[2], out4, bad);
+  return hipGetLastError();
+}
+
+__global__ void k_count_active(const int16_t *__restrict__ code, size_t N, unsigned long long *out) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int c = (g < N && code[g] >= 0) ? 1 : 0;
+  for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
+hipError_t launch_count_active(const int16_t *code, size_t N, unsigned long long *out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_count_active, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, code, N, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_fill(T *p, T v, size_t n) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) p[g] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<uint32_t>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i16(int16_t *p, int16_t v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<int16_t>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace hjb

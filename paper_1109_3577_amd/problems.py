@@ -165,15 +165,16 @@ def _ball_sectors_2d(X, Y, centre, r, R):
 
 
 def eikonal_2d(n: int = 101, nc: int = 32, r: float = 0.1, R: int = 1,
-               centre=(0.0, 0.0), fp32: bool = False, name: str = "eikonal2d") -> Problem:
+               centre=(0.0, 0.0), fp32: bool = False, name: str = "eikonal2d",
+               h: Optional[float] = None) -> Problem:
     """f = a, A = N_c unit directions, target = ball of radius r, [-1,1]^2,
-    h = k.  The target is split into R equal-angle sectors."""
+    h = k unless given.  The target is split into R equal-angle sectors."""
     lo, hi = (-1.0, -1.0), (1.0, 1.0)
     k = 2.0 / (n - 1)
     X, Y = grid_coords(2, (n, n), lo, hi)
     tp = _ball_sectors_2d(X, Y, centre, r, R)
-    return _make(2, (n, n), k, unit_controls_2d(nc), np.ones(n * n), None, tp, R, fp32, name,
-                 meta=dict(r=r, centre=tuple(centre), c=1.0))
+    return _make(2, (n, n), k if h is None else h, unit_controls_2d(nc), np.ones(n * n), None, tp,
+                 R, fp32, name, meta=dict(r=r, centre=tuple(centre), c=1.0))
 
 
 def config1() -> Problem:
