@@ -42,9 +42,13 @@
  *     target nodes carry no feedback (255);
  *   - colours: target nodes are fixed (1 on their own part, 0 elsewhere),
  *     non-target nodes start at 0 and rise as phi <- max(phi, I[phi]) until
- *     nothing changes; the label is the part with the largest colour, lowest
- *     part index on ties, -1 if every colour is 0 (node never reached,
- *     cf. Section 4.6 on unreachable regions);
+ *     nothing changes, where an interpolated colour below 1e-9 counts as 0
+ *     (the paper allows a very rough stopping rule for this iteration since
+ *     only the projection of the colours is used; the floor keeps the
+ *     supports of the colours compact and the map stays monotone); the label
+ *     is the part with the largest colour, lowest part index on ties, -1 if
+ *     every colour is 0 (node never reached, cf. Section 4.6 on unreachable
+ *     regions);
  *   - merge: target 0, label -1 gives 1, else the value of patch label.
  */
 #include <math.h>
@@ -54,6 +58,10 @@
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+/* Colours below this floor are set to zero (reading of the rough stopping
+ * rule of Step 3.1: colours matter only through their final projection). */
+#define ORC_COLOUR_FLOOR 1e-9
 
 #define ORC_OK 0
 #define ORC_EINVAL 1
@@ -372,6 +380,7 @@ int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sw
       double disp[3];
       orc_displacement(F, q, fb[q], disp);
       double I = orc_interp(F, phi, NULL, x, y, z, disp, 0.0);
+      if (I < ORC_COLOUR_FLOOR) I = 0.0;
       double nv = I > phi[q] ? I : phi[q];
       if (nv != phi[q]) changed = 1;
       pn[q] = nv;

@@ -61,6 +61,10 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
   return status;
 }
 
+// In-tile sweeps of one colour-transport tile activation before it is
+// queued again.
+constexpr int kTraceInnerSweeps = 16;
+
 // Steps 2 and 3.1: prolongation, feedback, chunked colour transport, labels.
 std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const CoarseHandle &C,
                                                   hipStream_t s) {
@@ -126,60 +130,61 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   HJB_HIP(hipStreamSynchronize(s));
   const double t1 = now_ms();
 
-  // Colour transport, CH parts at a time.
-  const int CH = trace_chunk_capacity(dim);
+  // Colour transport of all parts in one pass (Step 3.1), then labels.
+  HJB_REQUIRE(H.n_parts <= trace_max_parts(), "at most %d target parts are supported (got %d)",
+              trace_max_parts(), H.n_parts);
   const int ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
-  DBuf phi((size_t)CH * N * sizeof(double)), best(N * sizeof(double));
+  a.n_parts = H.n_parts;
+  a.words = (H.n_parts + 31) / 32;
+  DBuf phi((size_t)H.n_parts * N * sizeof(double));
+  DBuf masks((size_t)ntiles * a.words * sizeof(uint32_t));
   DBuf lists[2], flags[2], count(4 * sizeof(uint32_t)), work(2 * sizeof(unsigned long long));
   for (int i = 0; i < 2; ++i) {
     lists[i].reset((size_t)ntiles * sizeof(int32_t));
     flags[i].reset((size_t)ntiles * sizeof(uint32_t));
+    HJB_HIP(launch_fill_u32(flags[i].as<uint32_t>(), 0u, ntiles, s));
   }
-  HJB_HIP(launch_fill_f64(best.as<double>(), 0.0, N, s));
-  HJB_HIP(launch_fill_i16(H.labels.as<int16_t>(), (int16_t)-1, N, s));
-  HJB_HIP(hipMemsetAsync(work.get(), 0, work.bytes(), s));
-  PinnedBuf host(64);
   a.phi = phi.as<double>();
+  a.masks = masks.as<uint32_t>();
+  HJB_HIP(launch_fill_f64(a.phi, 0.0, (size_t)H.n_parts * N, s));
+  HJB_HIP(launch_fill_u32(a.masks, 0u, (size_t)ntiles * a.words, s));
+  HJB_HIP(launch_fill_u32(count.as<uint32_t>(), 0u, 4, s));
+  HJB_HIP(hipMemsetAsync(work.get(), 0, work.bytes(), s));
+  HJB_HIP(launch_trace_init(dim, a, s));
+  PinnedBuf host(64);
+  RoundArgs ra;
+  std::memset(&ra, 0, sizeof ra);
+  ra.count = count.as<uint32_t>();
+  ra.work = work.as<unsigned long long>();
+  ra.inner_sweeps = kTraceInnerSweeps;
+  // seeding appends to list[0]/count[0] as if it were round -1 (== 2 mod 3)
+  ra.list_out = lists[0].as<int32_t>();
+  ra.flags_out = flags[0].as<uint32_t>();
+  ra.round = 2;
+  HJB_HIP(launch_trace_seed(dim, a, ra, s));
   const int grid = std::min(ntiles, 4096);
   const int rpp = 4;
   long long rounds = 0;
-  for (int part0 = 0; part0 < H.n_parts; part0 += CH) {
-    a.chunk = std::min(CH, H.n_parts - part0);
-    a.part0 = part0;
-    HJB_HIP(launch_trace_init(dim, a, s));
-    for (int i = 0; i < 2; ++i) HJB_HIP(launch_fill_u32(flags[i].as<uint32_t>(), 0u, ntiles, s));
-    HJB_HIP(launch_fill_u32(count.as<uint32_t>(), 0u, 4, s));
-    RoundArgs ra;
-    std::memset(&ra, 0, sizeof ra);
-    ra.count = count.as<uint32_t>();
-    ra.work = work.as<unsigned long long>();
-    // seeding appends to list[0]/count[0] as if it were round -1 (== 2 mod 3)
-    ra.list_out = lists[0].as<int32_t>();
-    ra.flags_out = flags[0].as<uint32_t>();
-    ra.round = 2;
-    HJB_HIP(launch_trace_seed(dim, a, ra, s));
-    uint32_t r = 0;
-    while (true) {
-      for (int i = 0; i < rpp; ++i, ++r) {
-        ra.list_in = lists[r & 1].as<int32_t>();
-        ra.list_out = lists[(r + 1) & 1].as<int32_t>();
-        ra.flags_in = flags[r & 1].as<uint32_t>();
-        ra.flags_out = flags[(r + 1) & 1].as<uint32_t>();
-        ra.round = r;
-        HJB_HIP(launch_trace(dim, grid, a, ra, nullptr, s));
-      }
-      rounds += rpp;
-      HJB_HIP(hipMemcpyAsync(host.as<uint32_t>(), count.as<uint32_t>() + (r % 3), sizeof(uint32_t),
-                             hipMemcpyDeviceToHost, s));
-      HJB_HIP(hipStreamSynchronize(s));
-      if (host.as<uint32_t>()[0] == 0) break;
-      HJB_REQUIRE(rounds < 100000000, "colour transport did not settle");
+  uint32_t r = 0;
+  while (true) {
+    for (int i = 0; i < rpp; ++i, ++r) {
+      ra.list_in = lists[r & 1].as<int32_t>();
+      ra.list_out = lists[(r + 1) & 1].as<int32_t>();
+      ra.flags_in = flags[r & 1].as<uint32_t>();
+      ra.flags_out = flags[(r + 1) & 1].as<uint32_t>();
+      ra.round = r;
+      HJB_HIP(launch_trace(dim, grid, a, ra, s));
     }
-    HJB_HIP(launch_label_update(a, best.as<double>(), H.labels.as<int16_t>(), s));
+    rounds += rpp;
+    HJB_HIP(hipMemcpyAsync(host.as<uint32_t>(), count.as<uint32_t>() + (r % 3), sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    HJB_HIP(hipStreamSynchronize(s));
+    if (host.as<uint32_t>()[0] == 0) break;
+    HJB_REQUIRE(rounds < 10000000, "colour transport did not settle");
   }
   DBuf unreached(sizeof(uint32_t) * 2);
   HJB_HIP(launch_fill_u32(unreached.as<uint32_t>(), 0u, 1, s));
-  HJB_HIP(launch_label_final(F.tp, N, H.labels.as<int16_t>(), unreached.as<uint32_t>(), s));
+  HJB_HIP(launch_labels(dim, a, H.labels.as<int16_t>(), unreached.as<uint32_t>(), s));
   HJB_HIP(launch_make_code(F.tp, H.labels.as<int16_t>(), nullptr, N, H.code.as<int16_t>(), s));
   uint32_t un = 0;
   unsigned long long w[2] = {0, 0};
@@ -190,7 +195,9 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   std::memset(&H.st, 0, sizeof H.st);
   H.st.ms_prolong_feedback = t1 - t0;
   H.st.ms_trace = t2 - t1;
-  H.st.trace_node_updates = (int64_t)w[1] * TT[0] * TT[1] * TT[2];
+  // tile activations x parts loaded x tile nodes (upper bound of the
+  // per-node colour updates of one in-tile sweep)
+  H.st.trace_node_updates = (int64_t)w[0] * TT[0] * TT[1] * TT[2];
   H.st.unreached = (int32_t)un;
   H.st.rounds = (int32_t)rounds;
   H.st.item_runs = (int64_t)w[1];

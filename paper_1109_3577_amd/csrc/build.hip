@@ -115,28 +115,49 @@ hipError_t launch_feedback(int dim, const TraceArgs &a, const double *u0, uint8_
 }
 
 // ---------------------------------------------------------------- tracing
+//
+// All parts are transported in one pass.  phi[j][N] holds every part's
+// colour (zero-initialised, so any value read is a valid lower bound), and
+// mask[tile][w] has bit j set once part j is nonzero somewhere in the tile.
+// An activation loads only the parts whose bit is set in its tile or a
+// neighbouring tile (the others are zero in its whole stencil region and
+// stay zero); each part's transport is independent of the others, so
+// processing a subset changes no bit of any colour.
 
-// Trace tile shapes and chunk widths (fields per pass), sized for <= 64 KB
-// of LDS per workgroup.
-constexpr int TR2_TX = 32, TR2_TY = 16, TR2_CH = 8;
-constexpr int TR3_TX = 8, TR3_TY = 8, TR3_TZ = 8, TR3_CH = 4;
+// Interpolated colours below this floor count as zero: only the projection
+// of the colours is used (the paper lets this iteration stop very roughly),
+// and the floor keeps every part's support compact.  The map stays monotone.
+constexpr double kColourFloor = 1e-9;
+
+constexpr int TR2_TX = 32, TR2_TY = 8, TR2_CL = 8;
+constexpr int TR3_TX = 8, TR3_TY = 8, TR3_TZ = 8, TR3_CL = 4;
 constexpr int TR_NT = 256;
+constexpr int kMaxTraceWords = 32;  // up to 1024 parts
 
-int trace_chunk_capacity(int dim) { return dim == 2 ? TR2_CH : TR3_CH; }
+int trace_chunk_capacity(int dim) { return dim == 2 ? TR2_CL : TR3_CL; }
+int trace_max_parts() { return kMaxTraceWords * 32; }
 SweepShape trace_shape(int dim) {
   return dim == 2 ? SweepShape{2, TR2_TX, TR2_TY, 1} : SweepShape{3, TR3_TX, TR3_TY, TR3_TZ};
 }
 
-__global__ void k_trace_init(TraceArgs a) {
+// phi = 1 on the target nodes of their own part (the rest of phi is zero
+// from a fill), and the part bit of the node's tile.
+__global__ void k_trace_init(TraceArgs a, int tx, int ty, int tz) {
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= a.N) return;
   const int tp = a.target_part[g];
-  for (int f = 0; f < a.chunk; ++f) a.phi[(size_t)f * a.N + g] = (tp == a.part0 + f) ? 1.0 : 0.0;
+  if (tp < 0) return;
+  a.phi[(size_t)tp * a.N + g] = 1.0;
+  const int x = (int)(g % a.n[0]), y = (int)((g / a.n[0]) % a.n[1]);
+  const int z = (int)(g / ((size_t)a.n[0] * a.n[1]));
+  const int t = x / tx + a.ntile[0] * (y / ty + a.ntile[1] * (z / tz));
+  atomicOr(&a.masks[(size_t)t * a.words + (tp >> 5)], 1u << (tp & 31));
 }
 
 hipError_t launch_trace_init(int dim, const TraceArgs &a, hipStream_t s) {
-  (void)dim;
-  hipLaunchKernelGGL(k_trace_init, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
+  const SweepShape sh = trace_shape(dim);
+  hipLaunchKernelGGL(k_trace_init, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, sh.tx,
+                     sh.ty, sh.tz);
   return hipGetLastError();
 }
 
@@ -147,7 +168,7 @@ __device__ __forceinline__ void queue_tile(const RoundArgs &ra, int item) {
   }
 }
 
-template <int DIM, int TX, int TY, int TZ, int NT, int CH>
+template <int DIM, int TX, int TY, int TZ, int NT, int CL>
 __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
   constexpr int LX = TX + 2 * HALO;
   constexpr int LY = TY + 2 * HALO;
@@ -156,15 +177,20 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
   constexpr int TN = TX * TY * (DIM == 3 ? TZ : 1);
   constexpr int NPT = TN / NT;
   static_assert(TN % NT == 0, "tile must be a multiple of the block");
-  __shared__ double s_phi[CH * LN];
+  __shared__ double s_phi[CL * LN];
+  __shared__ uint32_t s_act[kMaxTraceWords];
+  __shared__ int s_list[kMaxTraceWords * 32];
+  __shared__ int s_nact;
   __shared__ int s_int[8];
+  __shared__ int s_nz[CL];
 
   const int tid = threadIdx.x;
   const uint32_t r = ra.round;
   if (blockIdx.x == 0 && tid == 0) ra.count[(r + 2) % 3] = 0u;
   const uint32_t nin = ra.count[r % 3];
   const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-  const int chunk = a.chunk;
+  const int W = a.words;
+  const int K = ra.inner_sweeps;
 
   for (uint32_t li = blockIdx.x; li < nin; li += gridDim.x) {
     const int tt = ra.list_in[li];
@@ -174,19 +200,35 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
     const int tiz = tt / (a.ntile[0] * a.ntile[1]);
     const int ox = tix * TX, oy = tiy * TY, oz = (DIM == 3) ? tiz * TZ : 0;
 
-    for (int i = tid; i < LN; i += NT) {
-      const int lx = i % LX, ly = (i / LX) % LY, lz = i / (LX * LY);
-      const int gx = ox + lx - HALO, gy = oy + ly - HALO, gz = oz + lz - HALO;
-      bool inb = (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1;
-      if (DIM == 3) inb = inb && (unsigned)gz < (unsigned)n2;
-      const size_t g = inb ? (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0)) : 0;
-#pragma unroll
-      for (int f = 0; f < CH; ++f)
-        s_phi[f * LN + i] = (inb && f < chunk) ? a.phi[(size_t)f * a.N + g] : 0.0;
+    // Parts present in the stencil region: OR of the neighbourhood masks.
+    for (int w = tid; w < W; w += NT) s_act[w] = 0u;
+    __syncthreads();
+    constexpr int NNB = (DIM == 3) ? 27 : 9;
+    for (int i = tid; i < NNB * W; i += NT) {
+      const int nb = i / W, w = i % W;
+      const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = (DIM == 3) ? nb / 9 - 1 : 0;
+      const int nx = tix + dx, ny = tiy + dy, nz = tiz + dz;
+      if (nx < 0 || ny < 0 || nz < 0 || nx >= a.ntile[0] || ny >= a.ntile[1] || nz >= a.ntile[2])
+        continue;
+      const uint32_t m = a.masks[(size_t)(nx + a.ntile[0] * (ny + a.ntile[1] * nz)) * W + w];
+      if (m) atomicOr(&s_act[w], m);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int c = 0;
+      for (int w = 0; w < W; ++w) {
+        uint32_t b = s_act[w];
+        while (b) {
+          const int j = __builtin_ctz(b);
+          b &= b - 1u;
+          s_list[c++] = w * 32 + j;
+        }
+      }
+      s_nact = c;
     }
 
-    // Per owned node: fixed foot point of its feedback control.
-    int base[NPT];
+    // Per owned node: fixed foot point of its feedback control (FP64).
+    int base[NPT], own[NPT];
     double t0[NPT], t1[NPT], t2[NPT];
     bool act[NPT];
     size_t gid[NPT];
@@ -200,8 +242,8 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
       const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0));
       gid[j] = g;
       act[j] = inb && a.target_part[g] < 0;
-      const int off = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
-      base[j] = off;
+      own[j] = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
+      base[j] = own[j];
       t0[j] = t1[j] = t2[j] = 0.0;
       if (act[j]) {
         double d[DIM];
@@ -209,7 +251,7 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
         const double f0 = __builtin_floor(d[0]), f1 = __builtin_floor(d[1]);
         t0[j] = d[0] - f0;
         t1[j] = d[1] - f1;
-        int o = off + (int)f0 + (int)f1 * LX;
+        int o = own[j] + (int)f0 + (int)f1 * LX;
         if (DIM == 3) {
           const double f2 = __builtin_floor(d[2]);
           t2[j] = d[2] - f2;
@@ -218,129 +260,142 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
         base[j] = o;
       }
     }
+    if (tid < 8) s_int[tid] = tid < 3 ? (1 << 30) : -1;
     __syncthreads();
+    const int nact = s_nact;
+    bool converged_all = true;
+    int bx0 = 1 << 30, by0 = 1 << 30, bz0 = 1 << 30, bx1 = -1, by1 = -1, bz1 = -1;
 
-    double old[NPT][CH];
+    for (int g0 = 0; g0 < nact; g0 += CL) {
+      const int nf = min(CL, nact - g0);
+      for (int i = tid; i < LN; i += NT) {
+        const int lx = i % LX, ly = (i / LX) % LY, lz = i / (LX * LY);
+        const int gx = ox + lx - HALO, gy = oy + ly - HALO, gz = oz + lz - HALO;
+        bool inb = (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1;
+        if (DIM == 3) inb = inb && (unsigned)gz < (unsigned)n2;
+        const size_t g =
+            inb ? (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0)) : 0;
 #pragma unroll
-    for (int j = 0; j < NPT; ++j) {
-      const int i = tid + j * NT;
-      const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
-      const int off = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
+        for (int f = 0; f < CL; ++f)
+          if (f < nf) s_phi[f * LN + i] = inb ? a.phi[(size_t)s_list[g0 + f] * a.N + g] : 0.0;
+      }
+      if (tid < CL) s_nz[tid] = 0;
+      __syncthreads();
+      double old[NPT][CL];
 #pragma unroll
-      for (int f = 0; f < CH; ++f) old[j][f] = s_phi[f * LN + off];
-    }
+      for (int j = 0; j < NPT; ++j)
+#pragma unroll
+        for (int f = 0; f < CL; ++f) old[j][f] = f < nf ? s_phi[f * LN + own[j]] : 0.0;
 
-    bool converged = false;
-    for (int it = 0; it < 4096; ++it) {
-      int ch = 0;
+      bool converged = false;
+      for (int it = 0; it < K; ++it) {
+        int ch = 0;
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+          if (!act[j]) continue;
+          const int o = base[j];
+#pragma unroll
+          for (int f = 0; f < CL; ++f) {
+            if (f >= nf) break;
+            const double *sp = s_phi + f * LN;
+            double r0 = Ar<double>::lin(t0[j], sp[o], sp[o + 1]);
+            double r1 = Ar<double>::lin(t0[j], sp[o + LX], sp[o + LX + 1]);
+            double I = Ar<double>::lin(t1[j], r0, r1);
+            if (DIM == 3) {
+              const int oz = o + LX * LY;
+              double q0 = Ar<double>::lin(t0[j], sp[oz], sp[oz + 1]);
+              double q1 = Ar<double>::lin(t0[j], sp[oz + LX], sp[oz + LX + 1]);
+              double I1 = Ar<double>::lin(t1[j], q0, q1);
+              I = Ar<double>::lin(t2[j], I, I1);
+            }
+            if (I < kColourFloor) I = 0.0;
+            if (I > sp[own[j]]) {
+              s_phi[f * LN + own[j]] = I;
+              ch = 1;
+            }
+          }
+        }
+        if (!__syncthreads_or(ch)) {
+          converged = true;
+          break;
+        }
+      }
+      if (!converged) converged_all = false;
+
 #pragma unroll
       for (int j = 0; j < NPT; ++j) {
         if (!act[j]) continue;
         const int i = tid + j * NT;
         const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
-        const int off = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
-        const int o = base[j];
+        bool changed = false;
 #pragma unroll
-        for (int f = 0; f < CH; ++f) {
-          if (f >= chunk) break;
-          const double *sp = s_phi + f * LN;
-          double r0 = Ar<double>::lin(t0[j], sp[o], sp[o + 1]);
-          double r1 = Ar<double>::lin(t0[j], sp[o + LX], sp[o + LX + 1]);
-          double I = Ar<double>::lin(t1[j], r0, r1);
-          if (DIM == 3) {
-            const int oz = o + LX * LY;
-            double q0 = Ar<double>::lin(t0[j], sp[oz], sp[oz + 1]);
-            double q1 = Ar<double>::lin(t0[j], sp[oz + LX], sp[oz + LX + 1]);
-            double I1 = Ar<double>::lin(t1[j], q0, q1);
-            I = Ar<double>::lin(t2[j], I, I1);
-          }
-          if (I > sp[off]) {
-            s_phi[f * LN + off] = I;
-            ch = 1;
+        for (int f = 0; f < CL; ++f) {
+          if (f >= nf) break;
+          const double nv = s_phi[f * LN + own[j]];
+          if (nv != old[j][f]) {
+            a.phi[(size_t)s_list[g0 + f] * a.N + gid[j]] = nv;
+            changed = true;
+            if (old[j][f] == 0.0) s_nz[f] = 1;
           }
         }
+        if (changed) {
+          bx0 = min(bx0, lx); bx1 = max(bx1, lx);
+          by0 = min(by0, ly); by1 = max(by1, ly);
+          bz0 = min(bz0, lz); bz1 = max(bz1, lz);
+        }
       }
-      if (!__syncthreads_or(ch)) {
-        converged = true;
-        break;
+      __syncthreads();
+      if (tid < nf && s_nz[tid]) {
+        const int part = s_list[g0 + tid];
+        atomicOr(&a.masks[(size_t)tt * W + (part >> 5)], 1u << (part & 31));
       }
+      __syncthreads();  // LDS is refilled by the next group
     }
 
-    int bx0 = 1 << 30, by0 = 1 << 30, bz0 = 1 << 30, bx1 = -1, by1 = -1, bz1 = -1;
-#pragma unroll
-    for (int j = 0; j < NPT; ++j) {
-      if (!act[j]) continue;
-      const int i = tid + j * NT;
-      const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
-      const int off = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
-      bool changed = false;
-#pragma unroll
-      for (int f = 0; f < CH; ++f) {
-        if (f >= chunk) break;
-        const double nv = s_phi[f * LN + off];
-        if (nv != old[j][f]) {
-          a.phi[(size_t)f * a.N + gid[j]] = nv;
-          changed = true;
-        }
-      }
-      if (changed) {
-        bx0 = min(bx0, lx); bx1 = max(bx1, lx);
-        by0 = min(by0, ly); by1 = max(by1, ly);
-        bz0 = min(bz0, lz); bz1 = max(bz1, lz);
-      }
-    }
-    if (tid == 0) {
-      s_int[0] = 1 << 30; s_int[1] = 1 << 30; s_int[2] = 1 << 30;
-      s_int[3] = -1; s_int[4] = -1; s_int[5] = -1;
-    }
-    __syncthreads();
     if (bx1 >= 0) {
       atomicMin(&s_int[0], bx0); atomicMin(&s_int[1], by0); atomicMin(&s_int[2], bz0);
       atomicMax(&s_int[3], bx1); atomicMax(&s_int[4], by1); atomicMax(&s_int[5], bz1);
     }
-    __syncthreads();
+    const int conv_all = __syncthreads_and(converged_all ? 1 : 0);
     const int cx0 = s_int[0], cy0 = s_int[1], cz0 = s_int[2];
     const int cx1 = s_int[3], cy1 = s_int[4], cz1 = s_int[5];
-    if (cx1 >= 0) {
-      constexpr int NNB = (DIM == 3) ? 27 : 9;
-      if (tid < NNB) {
-        const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = (DIM == 3) ? tid / 9 - 1 : 0;
-        bool need;
-        if (dx == 0 && dy == 0 && dz == 0) need = !converged;
-        else
-          need = (dx < 0 ? cx0 < HALO : dx > 0 ? cx1 >= TX - HALO : true) &&
-                 (dy < 0 ? cy0 < HALO : dy > 0 ? cy1 >= TY - HALO : true) &&
-                 (dz < 0 ? cz0 < HALO : dz > 0 ? cz1 >= TZ - HALO : true);
-        const int nx = tix + dx, ny = tiy + dy, nz = tiz + dz;
-        if (need && nx >= 0 && ny >= 0 && nz >= 0 && nx < a.ntile[0] && ny < a.ntile[1] &&
-            nz < a.ntile[2])
-          queue_tile(ra, nx + a.ntile[0] * (ny + a.ntile[1] * nz));
-      }
+    if (cx1 >= 0 && tid < NNB) {
+      const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = (DIM == 3) ? tid / 9 - 1 : 0;
+      bool need;
+      if (dx == 0 && dy == 0 && dz == 0) need = !conv_all;
+      else
+        need = (dx < 0 ? cx0 < HALO : dx > 0 ? cx1 >= TX - HALO : true) &&
+               (dy < 0 ? cy0 < HALO : dy > 0 ? cy1 >= TY - HALO : true) &&
+               (dz < 0 ? cz0 < HALO : dz > 0 ? cz1 >= TZ - HALO : true);
+      const int nx = tix + dx, ny = tiy + dy, nz = tiz + dz;
+      if (need && nx >= 0 && ny >= 0 && nz >= 0 && nx < a.ntile[0] && ny < a.ntile[1] &&
+          nz < a.ntile[2])
+        queue_tile(ra, nx + a.ntile[0] * (ny + a.ntile[1] * nz));
     }
-    if (tid == 0) atomicAdd(&ra.work[1], 1ull);
+    if (tid == 0) {
+      atomicAdd(&ra.work[1], 1ull);
+      atomicAdd(&ra.work[0], (unsigned long long)nact);
+    }
     __syncthreads();
   }
 }
 
-hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &ra,
-                        const int32_t *item_map_identity, hipStream_t s) {
-  (void)item_map_identity;
+hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &ra, hipStream_t s) {
+  if (a.words > kMaxTraceWords) return hipErrorInvalidValue;
   if (dim == 2)
-    hipLaunchKernelGGL((k_trace<2, TR2_TX, TR2_TY, 1, TR_NT, TR2_CH>), dim3(grid), dim3(TR_NT), 0,
+    hipLaunchKernelGGL((k_trace<2, TR2_TX, TR2_TY, 1, TR_NT, TR2_CL>), dim3(grid), dim3(TR_NT), 0,
                        s, a, ra);
   else
-    hipLaunchKernelGGL((k_trace<3, TR3_TX, TR3_TY, TR3_TZ, TR_NT, TR3_CH>), dim3(grid),
+    hipLaunchKernelGGL((k_trace<3, TR3_TX, TR3_TY, TR3_TZ, TR_NT, TR3_CL>), dim3(grid),
                        dim3(TR_NT), 0, s, a, ra);
   return hipGetLastError();
 }
 
-// Queue, for round 0 of a chunk, every tile within reach of a target node of
-// the chunk's parts (only those tiles can change first).
+// Queue, for round 0, every tile within reach of a target node.
 __global__ void k_trace_seed(TraceArgs a, int tx, int ty, int tz, RoundArgs ra) {
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= a.N) return;
-  const int tp = a.target_part[g];
-  if (tp < a.part0 || tp >= a.part0 + a.chunk) return;
+  if (a.target_part[g] < 0) return;
   const int x = (int)(g % a.n[0]), y = (int)((g / a.n[0]) % a.n[1]);
   const int z = (int)(g / ((size_t)a.n[0] * a.n[1]));
   const int dz0 = a.n[2] > 1 ? -1 : 0, dz1 = a.n[2] > 1 ? 1 : 0;
@@ -362,46 +417,48 @@ hipError_t launch_trace_seed(int dim, const TraceArgs &a, const RoundArgs &ra, h
 
 // ---------------------------------------------------------------- labels
 
-__global__ void k_label_update(TraceArgs a, double *best, int16_t *labels) {
-  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= a.N) return;
-  if (a.target_part[g] >= 0) return;
-  double b = best[g];
-  int L = labels[g];
-  for (int f = 0; f < a.chunk; ++f) {
-    const double p = a.phi[(size_t)f * a.N + g];
-    if (p > b) {
-      b = p;
-      L = a.part0 + f;
-    }
-  }
-  best[g] = b;
-  labels[g] = (int16_t)L;
-}
-
-hipError_t launch_label_update(const TraceArgs &a, double *best, int16_t *labels, hipStream_t s) {
-  hipLaunchKernelGGL(k_label_update, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, best,
-                     labels);
-  return hipGetLastError();
-}
-
-__global__ void k_label_final(const int16_t *__restrict__ tp, size_t N, int16_t *labels,
-                              uint32_t *unreached) {
+// Label of every node (eq. proiezionecolore with Remark 3.1): its part on
+// the target; elsewhere the part with the largest colour, lowest index on
+// ties (ascending scan, strict >), -1 when every colour is zero.  Only the
+// parts set in the node's tile mask can be nonzero there.
+__global__ void k_labels(TraceArgs a, int tx, int ty, int tz, int16_t *labels, uint32_t *unreached) {
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   int u = 0;
-  if (g < N) {
-    if (tp[g] >= 0) labels[g] = tp[g];
-    else if (labels[g] < 0) u = 1;
+  if (g < a.N) {
+    const int tp = a.target_part[g];
+    if (tp >= 0) {
+      labels[g] = (int16_t)tp;
+    } else {
+      const int x = (int)(g % a.n[0]), y = (int)((g / a.n[0]) % a.n[1]);
+      const int z = (int)(g / ((size_t)a.n[0] * a.n[1]));
+      const size_t t = (size_t)(x / tx + a.ntile[0] * (y / ty + a.ntile[1] * (z / tz)));
+      double best = 0.0;
+      int L = -1;
+      for (int w = 0; w < a.words; ++w) {
+        uint32_t b = a.masks[t * a.words + w];
+        while (b) {
+          const int j = w * 32 + __builtin_ctz(b);
+          b &= b - 1u;
+          const double p = a.phi[(size_t)j * a.N + g];
+          if (p > best) {
+            best = p;
+            L = j;
+          }
+        }
+      }
+      labels[g] = (int16_t)L;
+      u = L < 0;
+    }
   }
-  // one atomic per wave
   for (int o = 32; o >= 1; o >>= 1) u += __shfl_xor(u, o, 64);
   if ((threadIdx.x & 63) == 0 && u) atomicAdd(unreached, (uint32_t)u);
 }
 
-hipError_t launch_label_final(const int16_t *target_part, size_t N, int16_t *labels,
-                              uint32_t *unreached, hipStream_t s) {
-  hipLaunchKernelGGL(k_label_final, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, target_part,
-                     N, labels, unreached);
+hipError_t launch_labels(int dim, const TraceArgs &a, int16_t *labels, uint32_t *unreached,
+                         hipStream_t s) {
+  const SweepShape sh = trace_shape(dim);
+  hipLaunchKernelGGL(k_labels, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, sh.tx,
+                     sh.ty, sh.tz, labels, unreached);
   return hipGetLastError();
 }
 

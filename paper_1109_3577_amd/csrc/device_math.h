@@ -21,10 +21,11 @@ struct Ar;
 
 template <>
 struct Ar<float> {
-  // (1 - t) lo + t hi in weights form; monotone in lo and hi.
+  // (1 - t) lo + t hi in weights form: lo (1 - t) is one correctly rounded
+  // fma, then t hi is fused on top.  Monotone in lo and hi, and exactly 1
+  // when lo = hi = 1.
   static __device__ __forceinline__ float lin(float t, float lo, float hi) {
-    float omt = 1.0f - t;
-    return __builtin_fmaf(t, hi, omt * lo);
+    return __builtin_fmaf(t, hi, __builtin_fmaf(-t, lo, lo));
   }
   static __device__ __forceinline__ float kruzkov(float b, float I, float omb) {
     return __builtin_fmaf(b, I, omb);
@@ -50,7 +51,46 @@ struct Ar<double> {
 // Interpolate the LDS tile at base + d (d in cells, |d| < 2).  Corners
 // enumerate x fastest; nesting x, then y, then z.
 template <typename T, int DIM, int LX, int LY>
+__device__ __forceinline__ T interp_lds(const T *s, int base, const T *d);
+
+// FP32: cell index by floor-convert, local coordinate by fract, 24-bit
+// index arithmetic.  (fract clamps its result below 1, so a displacement a
+// hair below an integer lands on t = 1 - 2^-24 of the lower cell instead
+// of t = 1: the same value up to the last bit; every FP32 kernel uses this
+// one evaluation.)
+template <int DIM, int LX, int LY>
+__device__ __forceinline__ float interp_lds_f32(const float *s, int base, const float *d) {
+  const int i0 = (int)__builtin_floorf(d[0]);
+  const int i1 = (int)__builtin_floorf(d[1]);
+  const float t0 = __builtin_amdgcn_fractf(d[0]);
+  const float t1 = __builtin_amdgcn_fractf(d[1]);
+  // byte offset of the lower corner: one 24-bit multiply-add, one shift-add
+  int ob = __mul24(i1, LX * 4) + (base << 2);
+  float t2 = 0.0f;
+  if constexpr (DIM == 3) {
+    const int i2 = (int)__builtin_floorf(d[2]);
+    t2 = __builtin_amdgcn_fractf(d[2]);
+    ob += __mul24(i2, LX * LY * 4);
+  }
+  ob += i0 << 2;
+  const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(s) + ob);
+  const float r0 = Ar<float>::lin(t0, p[0], p[1]);
+  const float r1 = Ar<float>::lin(t0, p[LX], p[LX + 1]);
+  const float y0 = Ar<float>::lin(t1, r0, r1);
+  if constexpr (DIM == 2) {
+    return y0;
+  } else {
+    const float *q = p + LX * LY;
+    const float q0 = Ar<float>::lin(t0, q[0], q[1]);
+    const float q1 = Ar<float>::lin(t0, q[LX], q[LX + 1]);
+    const float y1 = Ar<float>::lin(t1, q0, q1);
+    return Ar<float>::lin(t2, y0, y1);
+  }
+}
+
+template <typename T, int DIM, int LX, int LY>
 __device__ __forceinline__ T interp_lds(const T *s, int base, const T *d) {
+  if constexpr (sizeof(T) == 4) return interp_lds_f32<DIM, LX, LY>(s, base, d);
   T f0 = Ar<T>::flr(d[0]), f1 = Ar<T>::flr(d[1]);
   T t0 = d[0] - f0, t1 = d[1] - f1;
   int o = base + (int)f0 + (int)f1 * LX;

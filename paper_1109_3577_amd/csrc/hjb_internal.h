@@ -87,15 +87,16 @@ struct TraceArgs {
   int32_t ntile[3];
   int32_t nc;
   int32_t has_drift;
-  int32_t chunk;     // number of fields in this chunk (<= CH)
-  int32_t part0;     // part index of field 0
+  int32_t n_parts;   // R
+  int32_t words;     // mask words per tile, ceil(R / 32)
   double step[3];
   const double *ctrl64;
   const double *speed64;
   const double *drift64;
   const int16_t *target_part;
   const uint8_t *feedback;
-  double *phi;       // [CH][N]
+  double *phi;       // [R][N], zero-initialised
+  uint32_t *masks;   // [ntiles][words]: parts nonzero somewhere in the tile
   size_t N;
 };
 
@@ -128,13 +129,12 @@ hipError_t launch_feedback(int dim, const TraceArgs &a, const double *u0, uint8_
                            hipStream_t s);
 hipError_t launch_trace_init(int dim, const TraceArgs &a, hipStream_t s);
 int trace_chunk_capacity(int dim);
+int trace_max_parts();
 SweepShape trace_shape(int dim);
-hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &ra,
-                        const int32_t *item_map_identity, hipStream_t s);
+hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &ra, hipStream_t s);
 hipError_t launch_trace_seed(int dim, const TraceArgs &a, const RoundArgs &ra, hipStream_t s);
-hipError_t launch_label_update(const TraceArgs &a, double *best, int16_t *labels, hipStream_t s);
-hipError_t launch_label_final(const int16_t *target_part, size_t N, int16_t *labels,
-                              uint32_t *unreached, hipStream_t s);
+hipError_t launch_labels(int dim, const TraceArgs &a, int16_t *labels, uint32_t *unreached,
+                         hipStream_t s);
 hipError_t launch_count_active(const int16_t *code, size_t N, unsigned long long *out,
                                hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);

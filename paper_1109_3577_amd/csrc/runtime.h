@@ -123,6 +123,8 @@ struct ProblemDev {
   // FP32 copies (s_d folded into controls and drift)
   DBuf ctrl32, speed32, drift32;
   std::vector<double> ctrl_host;  // controls on the host
+  std::vector<double> ctrl64_pad;  // host staging of the padded tables
+  std::vector<float> ctrl32_pad;
 };
 
 // Checks every documented requirement of an hjb_problem; throws HJB_EINVAL.

@@ -250,13 +250,10 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
   D->ctrl_host.resize((size_t)P.n_controls * P.dim);
   if (P.mem == HJB_MEM_HOST) {
     std::memcpy(D->ctrl_host.data(), P.controls, cb);
-    D->own_ctrl64.reset(cb);
     D->own_speed64.reset(N * sizeof(double));
     D->own_tp.reset(N * sizeof(int16_t));
-    HJB_HIP(hipMemcpyAsync(D->own_ctrl64.get(), P.controls, cb, hipMemcpyHostToDevice, s));
     HJB_HIP(hipMemcpyAsync(D->own_speed64.get(), P.speed, N * sizeof(double), hipMemcpyHostToDevice, s));
     HJB_HIP(hipMemcpyAsync(D->own_tp.get(), P.target_part, N * sizeof(int16_t), hipMemcpyHostToDevice, s));
-    D->ctrl64 = D->own_ctrl64.as<double>();
     D->speed64 = D->own_speed64.as<double>();
     D->tp = D->own_tp.as<int16_t>();
     if (P.drift) {
@@ -267,15 +264,32 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
     }
   } else {
     HJB_HIP(hipMemcpyAsync(D->ctrl_host.data(), P.controls, cb, hipMemcpyDeviceToHost, s));
-    D->ctrl64 = P.controls;
+    HJB_HIP(hipStreamSynchronize(s));
     D->speed64 = P.speed;
     D->drift64 = P.drift;
     D->tp = P.target_part;
   }
+  // Control tables with one extra row (a copy of row 0) so that kernels can
+  // fetch control k+1 while they evaluate control k.  FP32 rows carry
+  // s_d * a_kd rounded to FP32.
+  const int nc = P.n_controls, dim = P.dim;
+  D->ctrl64_pad.resize((size_t)(nc + 1) * dim);
+  D->ctrl32_pad.resize((size_t)(nc + 1) * dim);
+  for (int k = 0; k <= nc; ++k)
+    for (int d = 0; d < dim; ++d) {
+      const double a = D->ctrl_host[(size_t)(k < nc ? k : 0) * dim + d];
+      D->ctrl64_pad[(size_t)k * dim + d] = a;
+      D->ctrl32_pad[(size_t)k * dim + d] = (float)(P.step[d] * a);
+    }
+  D->own_ctrl64.reset(D->ctrl64_pad.size() * sizeof(double));
+  HJB_HIP(hipMemcpyAsync(D->own_ctrl64.get(), D->ctrl64_pad.data(),
+                         D->ctrl64_pad.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  D->ctrl64 = D->own_ctrl64.as<double>();
   if (need32) {
-    D->ctrl32.reset((size_t)P.n_controls * P.dim * sizeof(float));
+    D->ctrl32.reset(D->ctrl32_pad.size() * sizeof(float));
+    HJB_HIP(hipMemcpyAsync(D->ctrl32.get(), D->ctrl32_pad.data(),
+                           D->ctrl32_pad.size() * sizeof(float), hipMemcpyHostToDevice, s));
     D->speed32.reset(N * sizeof(float));
-    HJB_HIP(launch_scaled_f32(D->ctrl64, D->ctrl32.as<float>(), (size_t)P.n_controls, P.dim, P.step, s));
     HJB_HIP(launch_f64_to_f32(D->speed64, D->speed32.as<float>(), N, s));
     if (P.drift) {
       D->drift32.reset(N * P.dim * sizeof(float));
@@ -289,8 +303,8 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
 // ---------------------------------------------------------------- config
 
 static SweepShape default_shape(int dim, bool fp64) {
-  if (dim == 2) return fp64 ? SweepShape{2, 64, 8, 1} : SweepShape{2, 64, 16, 1};
-  return fp64 ? SweepShape{3, 8, 8, 8} : SweepShape{3, 16, 8, 8};
+  if (dim == 2) return SweepShape{2, 64, 8, 1};
+  return fp64 ? SweepShape{3, 8, 8, 8} : SweepShape{3, 8, 8, 8};
 }
 
 SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double tol,
@@ -298,7 +312,7 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
   SolveConfig c;
   c.fp64 = fp64;
   c.shape = default_shape(dim, fp64);
-  c.inner_sweeps = dim == 2 ? 48 : 32;
+  c.inner_sweeps = dim == 2 ? 12 : 4;
   c.tol = tol;
   c.max_rounds = max_sweeps > 0 ? max_sweeps : 1000000;
   HJB_REQUIRE(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");

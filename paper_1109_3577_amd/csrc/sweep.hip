@@ -19,6 +19,8 @@
 // with contraction off) so that they reproduce the plain CPU evaluation bit
 // for bit.  FP32 kernels use fused multiply-adds.
 
+#include <algorithm>
+
 #include "device_math.h"
 #include "hjb_internal.h"
 
@@ -113,16 +115,27 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
     T mI[NPT];
 #pragma unroll
     for (int j = 0; j < NPT; ++j) mI[j] = T(3);
+    // controls are read through the scalar cache; the table holds one
+    // extra row so that the next control can be fetched ahead
+    T an[DIM];
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) an[q] = ((cf32p)P.ctrl32)[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) an[q] = ((cf64p)P.ctrl64)[q];
+    }
+#pragma unroll 2
     for (int k = 0; k < nc; ++k) {
       T a[DIM];
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) a[q] = an[q];
       if constexpr (sizeof(T) == 4) {
-        cf32p cp = (cf32p)(P.ctrl32);
 #pragma unroll
-        for (int q = 0; q < DIM; ++q) a[q] = cp[k * DIM + q];
+        for (int q = 0; q < DIM; ++q) an[q] = ((cf32p)P.ctrl32)[(k + 1) * DIM + q];
       } else {
-        cf64p cp = (cf64p)(P.ctrl64);
 #pragma unroll
-        for (int q = 0; q < DIM; ++q) a[q] = cp[k * DIM + q];
+        for (int q = 0; q < DIM; ++q) an[q] = ((cf64p)P.ctrl64)[(k + 1) * DIM + q];
       }
 #pragma unroll
       for (int j = 0; j < NPT; ++j) {
@@ -137,8 +150,9 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
             d[q] = P.step[q] * g;
           }
         }
-        T I = interp_lds<T, DIM, LX, LY>(s_v, off[j], d);
-        mI[j] = I < mI[j] ? I : mI[j];
+        const T I = interp_lds<T, DIM, LX, LY>(s_v, off[j], d);
+        if constexpr (sizeof(T) == 4) mI[j] = __builtin_fminf(mI[j], I);
+        else mI[j] = I < mI[j] ? I : mI[j];
       }
     }
     int ch = 0;
@@ -385,30 +399,38 @@ hipError_t launch_jacobi(bool fp64, int dim, const DevProblem *prob_dev, size_t 
 // ---------------------------------------------------------------- helpers
 
 // bits[tile][w]: bit j set when the tile holds a non-target node of patch
-// j; bit `words*32-1`... the last bit of the row (index npatch) marks tiles
-// holding a target node.
-__global__ void k_tile_bits(const int16_t *__restrict__ code, int n0, int n1, int n2, int tx,
-                            int ty, int tz, int nt0, int nt1, int words, int npatch,
-                            uint32_t *bits) {
-  const size_t N = (size_t)n0 * n1 * n2;
-  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= N) return;
-  const int cd = code[g];
-  const int x = (int)(g % n0), y = (int)((g / n0) % n1), z = (int)(g / ((size_t)n0 * n1));
-  const int t = x / tx + nt0 * (y / ty + nt1 * (z / tz));
-  int bit = -1;
-  if (cd == CODE_TARGET) bit = npatch;
-  else if (cd >= 0) bit = cd;
-  if (bit >= 0) atomicOr(&bits[(size_t)t * words + (bit >> 5)], 1u << (bit & 31));
+// j; the last bit of the row (index words*32-1) marks tiles holding a
+// target node.  One workgroup per tile ORs into an LDS row, then stores it.
+constexpr int kMaxBitWords = 1024;
+
+__global__ void __launch_bounds__(256)
+k_tile_bits(const int16_t *__restrict__ code, int n0, int n1, int n2, int tx, int ty, int tz,
+            int nt0, int nt1, int words, uint32_t *bits) {
+  __shared__ uint32_t row[kMaxBitWords];
+  const int t = blockIdx.x;
+  const int ox = (t % nt0) * tx, oy = ((t / nt0) % nt1) * ty, oz = (t / (nt0 * nt1)) * tz;
+  for (int w = threadIdx.x; w < words; w += blockDim.x) row[w] = 0u;
+  __syncthreads();
+  const int tbit = words * 32 - 1;
+  const int cnt = tx * ty * tz;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int x = ox + i % tx, y = oy + (i / tx) % ty, z = oz + i / (tx * ty);
+    if (x >= n0 || y >= n1 || z >= n2) continue;
+    const int cd = code[(size_t)x + (size_t)n0 * ((size_t)y + (size_t)n1 * z)];
+    const int bit = cd == CODE_TARGET ? tbit : cd;
+    if (bit >= 0) atomicOr(&row[bit >> 5], 1u << (bit & 31));
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < words; w += blockDim.x) bits[(size_t)t * words + w] = row[w];
 }
 
 hipError_t launch_tile_bits(int dim, const int16_t *code, const int32_t n[3], const int32_t tile[3],
                             const int32_t ntile[3], int words, uint32_t *bits, hipStream_t s) {
   (void)dim;
-  const size_t N = (size_t)n[0] * n[1] * n[2];
-  const int npatch = words * 32 - 1;  // caller sizes words so the last bit is the target bit
-  hipLaunchKernelGGL(k_tile_bits, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, code, n[0],
-                     n[1], n[2], tile[0], tile[1], tile[2], ntile[0], ntile[1], words, npatch, bits);
+  if (words > kMaxBitWords) return hipErrorInvalidValue;
+  const int ntiles = ntile[0] * ntile[1] * ntile[2];
+  hipLaunchKernelGGL(k_tile_bits, dim3((unsigned)ntiles), dim3(256), 0, s, code, n[0], n[1], n[2],
+                     tile[0], tile[1], tile[2], ntile[0], ntile[1], words, bits);
   return hipGetLastError();
 }
 
@@ -475,45 +497,56 @@ hipError_t launch_make_code(const int16_t *target_part, const int16_t *labels,
   return hipGetLastError();
 }
 
-// Input scan of a device-resident problem: out4 = {max reach x, y, z,
-// max target part}; *bad |= 1 on a non-finite or negative speed / drift.
-__global__ void k_scan(const double *__restrict__ speed, const double *__restrict__ drift,
-                       const int16_t *__restrict__ tp, size_t N, int dim, double ax, double ay,
-                       double az, double s0, double s1, double s2, unsigned long long *out,
-                       int *bad) {
-  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double r[3] = {0.0, 0.0, 0.0};
-  double tmax = -1.0;
+// Input scan of a device-resident problem: out[0..2] = max displacement
+// bound per axis, out[3] = max target part + 2 (FP64 bits, non-negative);
+// *bad = 1 on a non-finite or negative speed, non-finite drift or a target
+// part below -1.  Block reduction, one atomic per block and quantity.
+__global__ void __launch_bounds__(256)
+k_scan(const double *__restrict__ speed, const double *__restrict__ drift,
+       const int16_t *__restrict__ tp, size_t N, int dim, double ax, double ay, double az,
+       double s0, double s1, double s2, unsigned long long *out, int *bad) {
+  __shared__ double red[4][4];
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  double r[4] = {0.0, 0.0, 0.0, 0.0};
   int b = 0;
-  if (g < N) {
+  const double am[3] = {ax, ay, az};
+  const double st[3] = {s0, s1, s2};
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < N;
+       g += (size_t)gridDim.x * blockDim.x) {
     const double c = speed[g];
     if (!(c >= 0.0) || !(c < 1e300)) b = 1;
-    const double am[3] = {ax, ay, az};
-    const double st[3] = {s0, s1, s2};
     for (int d = 0; d < dim; ++d) {
-      double w = drift ? drift[g * dim + d] : 0.0;
-      if (!(w == w) || !(w < 1e300 && w > -1e300)) b = 1;
-      r[d] = st[d] * (c * am[d] + (w < 0 ? -w : w));
+      const double w = drift ? drift[g * dim + d] : 0.0;
+      if (!(w < 1e300 && w > -1e300)) b = 1;
+      const double x = st[d] * (c * am[d] + (w < 0 ? -w : w));
+      r[d] = x > r[d] ? x : r[d];
     }
-    tmax = (double)tp[g];
+    const double t = (double)tp[g] + 2.0;
+    r[3] = t > r[3] ? t : r[3];
     if (tp[g] < -1) b = 1;
   }
-  for (int d = 0; d < 3; ++d) {
-    double x = r[d];
+  __syncthreads();
+  if (b) sbad = 1;
+  for (int q = 0; q < 4; ++q) {
+    double x = r[q];
     wave_max(x);
-    if ((threadIdx.x & 63) == 0 && x > 0.0) atomicMax(&out[d], (unsigned long long)__double_as_longlong(x));
+    if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = x;
   }
-  double t = tmax + 2.0;  // >= 0
-  wave_max(t);
-  if ((threadIdx.x & 63) == 0) atomicMax(&out[3], (unsigned long long)__double_as_longlong(t));
-  if (b) atomicOr(bad, 1);
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double m = 0.0;
+    for (int w = 0; w < 4; ++w) m = red[threadIdx.x][w] > m ? red[threadIdx.x][w] : m;
+    if (m > 0.0) atomicMax(&out[threadIdx.x], (unsigned long long)__double_as_longlong(m));
+  }
+  if (threadIdx.x == 0 && sbad) atomicOr(bad, 1);
 }
 
 hipError_t launch_scan_problem(const hjb_problem &P, size_t N, const double amax[3],
                                unsigned long long *out4, int *bad, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P.speed, P.drift,
-                     P.target_part, N, P.dim, amax[0], amax[1], amax[2], P.step[0], P.step[1],
-                     P.step[2], out4, bad);
+  const unsigned grid = (unsigned)std::min<size_t>((N + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_scan, dim3(grid), dim3(256), 0, s, P.speed, P.drift, P.target_part, N,
+                     P.dim, amax[0], amax[1], amax[2], P.step[0], P.step[1], P.step[2], out4, bad);
   return hipGetLastError();
 }
 

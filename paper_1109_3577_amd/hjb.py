@@ -223,9 +223,9 @@ class Coarse:
         return out
 
     def free(self):
-        if self.h:
+        if self.h and lib is not None:
             lib.hjb_coarse_free(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         self.free()
@@ -254,9 +254,9 @@ class Patches:
         return self._get(lib.hjb_patches_u0, np.float64)
 
     def free(self):
-        if self.h:
+        if self.h and lib is not None:
             lib.hjb_patches_free(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         self.free()
@@ -353,9 +353,9 @@ class Batch:
         return out, st.as_dict()
 
     def free(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.hjb_batch_free(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         self.free()
@@ -425,9 +425,9 @@ class Server:
         return out, st.as_dict()
 
     def free(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.hjb_server_free(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         self.free()

@@ -326,15 +326,23 @@ def test_labels_line_strips(orc, pr):
 
 def test_colour_partition_of_unity(orc, pr):
     """The colour transport is linear in the target data, so the colours of
-    the R parts sum to the colour of the whole target, 1 where reached."""
+    the R parts sum to the colour of the whole target, 1 where reached; the
+    floor that zeroes colours below 1e-9 only removes a sliver of that mass
+    (at most R * 1e-9 per step along a characteristic)."""
     P = pr.eikonal_2d(65, 32, 0.2, 8)
     Pc = pr.eikonal_2d(33, 32, 0.2, 8)
     vc, _ = orc.solve_global(Pc)
     fb = orc.feedback(P, orc.prolong(Pc, vc, P))
     lab, s, _ = orc.labels(P, fb, want_sum=True)
     m = P.target_part < 0
-    assert np.abs(s[m] - 1.0).max() < 1e-12
+    assert s[m].max() <= 1.0 + 1e-12
+    assert s[m].min() >= 1.0 - 1e-7
     assert np.all(lab >= 0)
+    f, c = pr.variable_speed_3d(1, 33, 9, 98, 4, 4, 0.25, True)
+    vc, _ = orc.solve_global(c)
+    lab, s, _ = orc.labels(f, orc.feedback(f, orc.prolong(c, vc, f)), want_sum=True)
+    m = f.target_part < 0
+    assert s[m].max() <= 1.0 + 1e-12 and s[m].min() >= 1.0 - 1e-6
 
 
 def test_labels_follow_sectors(orc, pr):
