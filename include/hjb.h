@@ -132,8 +132,10 @@ typedef struct {
   int32_t inner_sweeps;    /* max in-LDS sweeps per tile activation */
   int32_t rounds_per_poll; /* sweep rounds enqueued between host polls */
   int32_t schedule;        /* HJB_SCHED_* (hjb_solve_global only) */
-  int32_t time_kernels;    /* 1: HIP events around every sweep launch */
+  int32_t time_kernels;    /* 1: HIP events around each polled block of
+                              sweep launches (kernel time in hjb_stats) */
   int32_t use_graph;       /* 1: replay the polled rounds as a hipGraph */
+  int32_t threads;         /* workgroup size of the sweep kernel: 256 or 512 */
   const uint8_t *patch_select; /* host [n_parts] 0/1, NULL = all patches
                                   (hjb_solve_patches only): nodes of
                                   unselected patches are left at 1 */

@@ -105,8 +105,9 @@ inline int div_up(int a, int b) { return (a + b - 1) / b; }
 // Launchers (defined in the .hip translation units).
 struct SweepShape {
   int dim, tx, ty, tz;
+  int nt = 256;  // workgroup size
 };
-bool sweep_shape_supported(int dim, int tx, int ty, int tz);
+bool sweep_shape_supported(int dim, int tx, int ty, int tz, int nt);
 hipError_t launch_sweep(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
                         const Item *items, const RoundArgs &ra, hipStream_t s);
 hipError_t launch_jacobi(bool fp64, int dim, const DevProblem *prob_dev, size_t N, const void *vin,

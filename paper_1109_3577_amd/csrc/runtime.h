@@ -213,6 +213,7 @@ class SweepEngine {
   uint32_t r_ = 0;
   double kernel_ms_ = 0.0;
   int kernel_launches_ = 0;
+  int kernel_blocks_ = 0;
   int grid_ = 1;
   hipGraphExec_t graph_ = nullptr;
   std::vector<hipEvent_t> events_;

@@ -303,8 +303,9 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
 // ---------------------------------------------------------------- config
 
 static SweepShape default_shape(int dim, bool fp64) {
-  if (dim == 2) return SweepShape{2, 64, 8, 1};
-  return fp64 ? SweepShape{3, 8, 8, 8} : SweepShape{3, 8, 8, 8};
+  (void)fp64;
+  if (dim == 2) return SweepShape{2, 64, 8, 1, 512};
+  return SweepShape{3, 8, 8, 8, 256};
 }
 
 SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double tol,
@@ -318,11 +319,14 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
   HJB_REQUIRE(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");
   if (opts) {
     if (opts->tile[0] > 0) {
-      SweepShape sh{dim, opts->tile[0], opts->tile[1], dim == 3 ? opts->tile[2] : 1};
-      HJB_REQUIRE(sweep_shape_supported(sh.dim, sh.tx, sh.ty, sh.tz),
-                  "unsupported tile shape %dx%dx%d for dim %d", sh.tx, sh.ty, sh.tz, dim);
-      c.shape = sh;
+      c.shape.tx = opts->tile[0];
+      c.shape.ty = opts->tile[1];
+      c.shape.tz = dim == 3 ? opts->tile[2] : 1;
     }
+    if (opts->threads > 0) c.shape.nt = opts->threads;
+    HJB_REQUIRE(sweep_shape_supported(c.shape.dim, c.shape.tx, c.shape.ty, c.shape.tz, c.shape.nt),
+                "unsupported tile shape %dx%dx%d with %d threads for dim %d", c.shape.tx,
+                c.shape.ty, c.shape.tz, c.shape.nt, dim);
     if (opts->inner_sweeps > 0) c.inner_sweeps = opts->inner_sweeps;
     if (opts->rounds_per_poll > 0) c.rounds_per_poll = opts->rounds_per_poll;
     c.use_graph = opts->use_graph != 0;
@@ -331,7 +335,6 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
                 "unknown schedule %d", opts->schedule);
   }
   if (c.use_graph) c.rounds_per_poll = std::max(6, (c.rounds_per_poll + 5) / 6 * 6);
-  if (c.time_kernels) c.use_graph = false;
   return c;
 }
 
@@ -507,7 +510,7 @@ int SweepEngine::run_rounds(int rounds) {
   const bool timing = cfg_.time_kernels;
   // (capture is not possible on the legacy null stream: rounds are then
   // launched one by one)
-  if (cfg_.use_graph && !timing && s_ != nullptr && rounds % 6 == 0 && r_ % 6 == 0) {
+  if (cfg_.use_graph && s_ != nullptr && rounds % 6 == 0 && r_ % 6 == 0) {
     // rounds depend on r only through r mod 2 and r mod 3: one captured
     // block of a multiple of 6 rounds replays for every later block
     if (!graph_) {
@@ -518,24 +521,40 @@ int SweepEngine::run_rounds(int rounds) {
       HJB_HIP(hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0));
       (void)hipGraphDestroy(g);
     }
+    if (timing) {
+      while (events_.size() < (size_t)(2 * (kernel_blocks_ + 1))) {
+        hipEvent_t e;
+        HJB_HIP(hipEventCreate(&e));
+        events_.push_back(e);
+      }
+      HJB_HIP(hipEventRecord(events_[2 * kernel_blocks_], s_));
+    }
     HJB_HIP(hipGraphLaunch(graph_, s_));
+    if (timing) {
+      HJB_HIP(hipEventRecord(events_[2 * kernel_blocks_ + 1], s_));
+      ++kernel_blocks_;
+      kernel_launches_ += rounds;
+    }
     r_ += rounds;
   } else {
+    // Kernel time: one event pair around the block of rounds (the block
+    // holds nothing but sweep launches).
+    if (timing) {
+      while (events_.size() < (size_t)(2 * (kernel_blocks_ + 1))) {
+        hipEvent_t e;
+        HJB_HIP(hipEventCreate(&e));
+        events_.push_back(e);
+      }
+      HJB_HIP(hipEventRecord(events_[2 * kernel_blocks_], s_));
+    }
     for (int i = 0; i < rounds; ++i) {
-      if (timing) {
-        while (events_.size() < (size_t)(2 * (kernel_launches_ + 1))) {
-          hipEvent_t e;
-          HJB_HIP(hipEventCreate(&e));
-          events_.push_back(e);
-        }
-        HJB_HIP(hipEventRecord(events_[2 * kernel_launches_], s_));
-      }
       launch_round(r_);
-      if (timing) {
-        HJB_HIP(hipEventRecord(events_[2 * kernel_launches_ + 1], s_));
-        ++kernel_launches_;
-      }
       ++r_;
+    }
+    if (timing) {
+      HJB_HIP(hipEventRecord(events_[2 * kernel_blocks_ + 1], s_));
+      ++kernel_blocks_;
+      kernel_launches_ += rounds;
     }
   }
   rounds_ += rounds;
@@ -557,9 +576,9 @@ int SweepEngine::run() {
       break;
     }
   }
-  if (cfg_.time_kernels && kernel_launches_ > 0) {
+  if (cfg_.time_kernels && kernel_blocks_ > 0) {
     kernel_ms_ = 0.0;
-    for (int i = 0; i < kernel_launches_; ++i) {
+    for (int i = 0; i < kernel_blocks_; ++i) {
       float ms = 0.0f;
       HJB_HIP(hipEventElapsedTime(&ms, events_[2 * i], events_[2 * i + 1]));
       kernel_ms_ += ms;

@@ -287,13 +287,19 @@ k_sweep(const DevProblem *__restrict__ probs, const Item *__restrict__ items, Ro
   X(2, 32, 32, 1, 256)     \
   X(2, 64, 8, 1, 256)      \
   X(2, 32, 16, 1, 256)     \
+  X(2, 64, 8, 1, 512)      \
+  X(2, 32, 16, 1, 512)     \
+  X(2, 64, 16, 1, 512)     \
+  X(2, 32, 32, 1, 512)     \
   X(3, 16, 8, 8, 256)      \
   X(3, 8, 8, 8, 256)       \
-  X(3, 32, 8, 4, 256)
+  X(3, 32, 8, 4, 256)      \
+  X(3, 8, 8, 8, 512)       \
+  X(3, 16, 8, 8, 512)
 
-bool sweep_shape_supported(int dim, int tx, int ty, int tz) {
+bool sweep_shape_supported(int dim, int tx, int ty, int tz, int nt) {
 #define HJB_CHECK_SHAPE(D, A, B, C, NT) \
-  if (dim == D && tx == A && ty == B && tz == C) return true;
+  if (dim == D && tx == A && ty == B && tz == C && nt == NT) return true;
   HJB_SHAPES(HJB_CHECK_SHAPE)
 #undef HJB_CHECK_SHAPE
   return false;
@@ -302,7 +308,7 @@ bool sweep_shape_supported(int dim, int tx, int ty, int tz) {
 hipError_t launch_sweep(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
                         const Item *items, const RoundArgs &ra, hipStream_t s) {
 #define HJB_LAUNCH_SHAPE(D, A, B, C, NT)                                                    \
-  if (sh.dim == D && sh.tx == A && sh.ty == B && sh.tz == C) {                              \
+  if (sh.dim == D && sh.tx == A && sh.ty == B && sh.tz == C && sh.nt == NT) {               \
     if (fp64)                                                                               \
       hipLaunchKernelGGL((k_sweep<double, D, A, B, C, NT>), dim3(grid), dim3(NT), 0, s,    \
                          probs, items, ra);                                                 \

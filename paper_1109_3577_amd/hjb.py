@@ -55,7 +55,7 @@ class hjb_stats(C.Structure):
 class hjb_solve_opts(C.Structure):
     _fields_ = [("tile", C.c_int32 * 3), ("inner_sweeps", C.c_int32),
                 ("rounds_per_poll", C.c_int32), ("schedule", C.c_int32),
-                ("time_kernels", C.c_int32), ("use_graph", C.c_int32),
+                ("time_kernels", C.c_int32), ("use_graph", C.c_int32), ("threads", C.c_int32),
                 ("patch_select", C.c_void_p)]
 
 
@@ -193,7 +193,8 @@ def _as_problem(p, device=False) -> Problem:
 
 
 def make_opts(tile=None, inner_sweeps=0, rounds_per_poll=0, schedule=HJB_SCHED_TILED,
-              time_kernels=False, use_graph=False, patch_select=None) -> hjb_solve_opts:
+              time_kernels=False, use_graph=False, patch_select=None,
+              threads=0) -> hjb_solve_opts:
     o = hjb_solve_opts()
     if tile is not None:
         for k, t in enumerate(tile):
@@ -203,6 +204,7 @@ def make_opts(tile=None, inner_sweeps=0, rounds_per_poll=0, schedule=HJB_SCHED_T
     o.schedule = int(schedule)
     o.time_kernels = int(bool(time_kernels))
     o.use_graph = int(bool(use_graph))
+    o.threads = int(threads)
     if patch_select is not None:
         sel = np.ascontiguousarray(patch_select, dtype=np.uint8)
         o._sel = sel

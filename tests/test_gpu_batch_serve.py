@@ -1,0 +1,114 @@
+"""Batched solves and the continuous-batching server through the C ABI.
+
+Both pack work items of many problems into shared sweep rounds.  Every
+update is monotone and items write only their own patch of their own
+problem, so each result must equal, bit for bit, the same problem solved
+alone -- whatever else is in the mix, and whenever it joins."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1109_3577_amd import hjb
+    return hjb
+
+
+def _alone(H, f, c, precision):
+    import torch
+    ch = H.hjb_coarse_solve(c)
+    ph = H.hjb_build_patches(f, ch)
+    v = torch.empty(f.N, dtype=torch.float32 if precision == H.HJB_F32 else torch.float64,
+                    device="cuda")
+    H.hjb_solve_patches(f, ph, precision, v)
+    return v.cpu().numpy(), ph.labels()
+
+
+def _mixed_problems(pr, k=6):
+    """Uneven 2D problems (sizes, controls, parts, drift) plus 3D ones."""
+    ss = np.random.SeedSequence(11).spawn(k)
+    probs = [pr.batched_problem(s, i, (65, 200)) for i, s in enumerate(ss)]
+    probs.append(pr.variable_speed_3d(3, 29, 9, 98, 2, 4, 0.3, True, "b3d"))
+    probs.append(pr.variable_speed_2d(9, 97, 17, 32, 16, 0.1, True))
+    return probs
+
+
+def test_batch_equals_alone_fp32(H, pr):
+    probs = _mixed_problems(pr)
+    b = H.hjb_batch_create([f for f, _ in probs], [c for _, c in probs], H.HJB_F32)
+    st = H.hjb_batch_run(b)
+    assert st["status"] == H.HJB_OK and st["updates"] > 0
+    for i, (f, c) in enumerate(probs):
+        got, sti = H.hjb_batch_result(b, i)
+        ref, _ = _alone(H, f, c, H.HJB_F32)
+        assert np.array_equal(got, ref), i
+        assert sti["updates"] > 0
+
+
+def test_batch_equals_oracle_fp64(H, orc, pr):
+    probs = _mixed_problems(pr, 3)[:3]
+    b = H.hjb_batch_create([f for f, _ in probs], [c for _, c in probs], H.HJB_F64)
+    H.hjb_batch_run(b)
+    for i, (f, c) in enumerate(probs):
+        got, _ = H.hjb_batch_result(b, i)
+        assert np.array_equal(got, orc.patchy(f, c)["v"]), i
+
+
+def test_server_same_alone_and_in_mix(H, pr):
+    """Requests arrive while others are live; each finishes with the bits
+    of its solve alone, and the HBM budget bounds what is admitted."""
+    probs = _mixed_problems(pr, 5)
+    S = H.hjb_server_create(2 << 30, H.HJB_F32)
+    tickets = {}
+    done = {}
+    pending = list(enumerate(probs))
+    steps = 0
+    while pending or len(done) < len(probs):
+        if pending:  # one new request per step, while earlier ones run
+            i, (f, c) = pending.pop(0)
+            tickets[i] = S.submit(f, c)
+        live, queued = S.step(2)
+        steps += 1
+        for i, t in list(tickets.items()):
+            if i in done:
+                continue
+            v, st = S.poll(t)
+            if v is not None:
+                done[i] = (v, st)
+        assert steps < 10000
+    for i, (f, c) in enumerate(probs):
+        ref, _ = _alone(H, f, c, H.HJB_F32)
+        assert np.array_equal(done[i][0], ref), i
+        assert done[i][1]["status"] == H.HJB_OK
+
+
+def test_server_admission_by_budget(H, pr):
+    """A request larger than the whole budget is refused up front; with a
+    budget for one request at a time, requests run one after the other."""
+    f, c = pr.variable_speed_2d(0, 129, 17, 16, 4, 0.1, True)
+    S = H.hjb_server_create(1 << 20, H.HJB_F32)
+    with pytest.raises(H.HjbError) as e:
+        S.submit(f, c)
+    assert e.value.status == H.HJB_EINVAL
+    # one 129^2 request holds about 2.7 MB (values, inputs, labels and the
+    # transient colour/feedback buffers of its build step)
+    S = H.hjb_server_create(4 << 20, H.HJB_F32)
+    t1 = S.submit(f, c)
+    t2 = S.submit(f, c)
+    live, queued = S.step(1)
+    assert live == 1 and queued == 1
+    out = {}
+    for _ in range(2000):
+        for t in (t1, t2):
+            if t not in out:
+                v, _ = S.poll(t)
+                if v is not None:
+                    out[t] = v
+        if len(out) == 2:
+            break
+        S.step(4)
+    assert np.array_equal(out[t1], out[t2])
