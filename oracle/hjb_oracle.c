@@ -353,6 +353,30 @@ int orc_feedback(const orc_problem *F, const double *u0, uint8_t *fb) {
   return ORC_OK;
 }
 
+/* Public: the discrete feedback at a list of nodes only (as orc_feedback),
+ * so that a large grid can be checked node by node. */
+int orc_feedback_at(const orc_problem *F, const double *u0, const long long *idx, long long count,
+                    uint8_t *fb) {
+  if (orc_check(F) || F->n_controls > 255) return ORC_EINVAL;
+  long long nx = F->n[0], ny = F->n[1];
+#pragma omp parallel for schedule(static)
+  for (long long i = 0; i < count; ++i) {
+    long long q = idx[i];
+    long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
+    if (F->target_part[q] >= 0) { fb[i] = 255; continue; }
+    double best = INFINITY;
+    int bk = 0;
+    for (int k = 0; k < F->n_controls; ++k) {
+      double disp[3];
+      orc_displacement(F, q, k, disp);
+      double I = orc_interp(F, u0, NULL, x, y, z, disp, 1.0);
+      if (I < best) { best = I; bk = k; }
+    }
+    fb[i] = (uint8_t)bk;
+  }
+  return ORC_OK;
+}
+
 /* Public: Step 3.1 for one part j -- colour transport with the frozen
  * feedback, eq. HJBridotta_discreta, iterated (Jacobi) from below to the
  * exact fixed point.  phi [N] is output. */

@@ -58,6 +58,7 @@ def lib():
         L.orc_solve_global.argtypes = [vp, d, i32, vp, vp, vp, vp]
         L.orc_prolong.argtypes = [vp, vp, vp, vp]
         L.orc_feedback.argtypes = [vp, vp, vp]
+        L.orc_feedback_at.argtypes = [vp, vp, vp, C.c_longlong, vp]
         L.orc_trace_part.argtypes = [vp, vp, i32, i32, vp, vp]
         L.orc_labels.argtypes = [vp, vp, i32, vp, vp, vp]
         L.orc_solve_patches.argtypes = [vp, vp, d, i32, i32, vp, vp, vp]
@@ -163,6 +164,16 @@ def feedback(fine, u0: np.ndarray):
     u0 = np.ascontiguousarray(u0, dtype=np.float64).ravel()
     fb = np.empty(fine.N, dtype=np.uint8)
     _check(lib().orc_feedback(H.ref, _p(u0), _p(fb)), "feedback")
+    return fb
+
+
+def feedback_at(fine, u0: np.ndarray, idx: np.ndarray):
+    """Step 2 feedback at the listed nodes only."""
+    H = _Held(fine)
+    u0 = np.ascontiguousarray(u0, dtype=np.float64).ravel()
+    idx = np.ascontiguousarray(idx, dtype=np.int64).ravel()
+    fb = np.empty(idx.shape[0], dtype=np.uint8)
+    _check(lib().orc_feedback_at(H.ref, _p(u0), _p(idx), idx.shape[0], _p(fb)), "feedback_at")
     return fb
 
 
