@@ -122,7 +122,8 @@ typedef struct {
   double ms_prolong_feedback;
   double ms_trace;
   int64_t trace_node_updates;
-  int32_t unreached;       /* nodes with label -1 */
+  int32_t unreached;       /* nodes no colour reached; they took their
+                              neighbours' label (Remark 3.1) */
   int32_t reserved;
 } hjb_stats;
 

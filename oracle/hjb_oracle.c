@@ -41,14 +41,20 @@
  *     interpolated value I[U^(0)] (raw I, before the affine Kruzkov map);
  *     target nodes carry no feedback (255);
  *   - colours: target nodes are fixed (1 on their own part, 0 elsewhere),
- *     non-target nodes start at 0 and rise as phi <- max(phi, I[phi]) until
- *     nothing changes, where an interpolated colour below 1e-9 counts as 0
- *     (the paper allows a very rough stopping rule for this iteration since
- *     only the projection of the colours is used; the floor keeps the
- *     supports of the colours compact and the map stays monotone); the label
- *     is the part with the largest colour, lowest part index on ties, -1 if
- *     every colour is 0 (node never reached, cf. Section 4.6 on unreachable
- *     regions);
+ *     non-target nodes start at 0 and rise as phi <- max(phi, beta I[phi])
+ *     until nothing changes.  The factor beta = exp(-h) is the scheme's own
+ *     per-step factor in the Kruzkov variable: a colour is the share of
+ *     exp(-T) that part j carries along the frozen feedback, and the colour
+ *     map is a beta-contraction (without it, near-closed loops of the
+ *     frozen feedback -- rotating drifts produce them -- make the iteration
+ *     contract arbitrarily slowly).  A colour below 1e-9 counts as 0 (the
+ *     paper allows a very rough stopping rule here since only the
+ *     projection of the colours is used; the floor keeps the supports
+ *     compact).  Both maps are monotone.  The label is the part with the
+ *     largest colour, lowest part index on ties; nodes whose colours are all
+ *     0 then take the smallest label among their nearest labelled nodes
+ *     (Remark 3.1: uncovered nodes get the colour of their neighbours), so
+ *     -1 remains only where no node is labelled at all;
  *   - merge: target 0, label -1 gives 1, else the value of patch label.
  */
 #include <math.h>
@@ -378,8 +384,9 @@ int orc_feedback_at(const orc_problem *F, const double *u0, const long long *idx
 }
 
 /* Public: Step 3.1 for one part j -- colour transport with the frozen
- * feedback, eq. HJBridotta_discreta, iterated (Jacobi) from below to the
- * exact fixed point.  phi [N] is output. */
+ * feedback, eq. HJBridotta_discreta with the per-step factor beta,
+ * iterated (Jacobi) from below to the exact fixed point.  phi [N] is
+ * output. */
 int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sweeps, double *phi,
                    int *sweeps_out) {
   if (orc_check(F)) return ORC_EINVAL;
@@ -404,8 +411,9 @@ int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sw
       double disp[3];
       orc_displacement(F, q, fb[q], disp);
       double I = orc_interp(F, phi, NULL, x, y, z, disp, 0.0);
-      if (I < ORC_COLOUR_FLOOR) I = 0.0;
-      double nv = I > phi[q] ? I : phi[q];
+      double bI = F->beta * I;
+      if (bI < ORC_COLOUR_FLOOR) bI = 0.0;
+      double nv = bI > phi[q] ? bI : phi[q];
       if (nv != phi[q]) changed = 1;
       pn[q] = nv;
     }
@@ -419,12 +427,52 @@ int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sw
   return rc;
 }
 
+/* Remark 3.1: nodes no colour reached take the colour of their neighbours.
+ * Jacobi layers: an unlabelled node with labelled neighbours (8 in 2D, 26
+ * in 3D) takes the smallest of their labels; repeat until no node changes.
+ * The result is the lowest label among the nearest labelled nodes.
+ * *filled (optional) receives the number of nodes that were unlabelled. */
+int orc_fill_labels(const orc_problem *F, int16_t *labels, long long *filled) {
+  long long N = orc_N(F), nx = F->n[0], ny = F->n[1], nz = F->n[2];
+  int16_t *next = (int16_t *)malloc(sizeof(int16_t) * (size_t)N);
+  if (!next) return ORC_ENOMEM;
+  long long before = 0;
+  for (long long q = 0; q < N; ++q) before += labels[q] < 0;
+  int dz0 = nz > 1 ? -1 : 0, dz1 = nz > 1 ? 1 : 0;
+  for (;;) {
+    int changed = 0;
+    memcpy(next, labels, sizeof(int16_t) * (size_t)N);
+    for (long long q = 0; q < N; ++q) {
+      if (labels[q] >= 0) continue;
+      long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
+      int best = -1;
+      for (int dz = dz0; dz <= dz1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            long long X = x + dx, Y = y + dy, Z = z + dz;
+            if (X < 0 || Y < 0 || Z < 0 || X >= nx || Y >= ny || Z >= nz) continue;
+            int L = labels[X + nx * (Y + ny * Z)];
+            if (L >= 0 && (best < 0 || L < best)) best = L;
+          }
+      if (best >= 0) {
+        next[q] = (int16_t)best;
+        changed = 1;
+      }
+    }
+    memcpy(labels, next, sizeof(int16_t) * (size_t)N);
+    if (!changed) break;
+  }
+  free(next);
+  if (filled) *filled = before;
+  return ORC_OK;
+}
+
 /* Public: Step 3.1 for all parts, then the labels (projection/assembly,
  * eq. proiezionecolore with Remark 3.1): label = target part on target
  * nodes; elsewhere the part with the largest colour (lowest index on ties),
  * -1 where every colour is 0.  phi_sum (optional) receives sum_j phi^j. */
 int orc_labels(const orc_problem *F, const uint8_t *fb, int max_sweeps, int16_t *labels,
-               double *phi_sum, int *max_trace_sweeps) {
+               double *phi_sum, int *max_trace_sweeps, long long *unreached) {
   if (orc_check(F) || F->n_parts < 1) return ORC_EINVAL;
   long long N = orc_N(F);
   double *phi = (double *)malloc(sizeof(double) * (size_t)N);
@@ -451,6 +499,7 @@ int orc_labels(const orc_problem *F, const uint8_t *fb, int max_sweeps, int16_t 
   if (max_trace_sweeps) *max_trace_sweeps = mx;
   free(phi);
   free(best);
+  if (rc == ORC_OK) rc = orc_fill_labels(F, labels, unreached);
   return rc;
 }
 

@@ -60,7 +60,7 @@ def lib():
         L.orc_feedback.argtypes = [vp, vp, vp]
         L.orc_feedback_at.argtypes = [vp, vp, vp, C.c_longlong, vp]
         L.orc_trace_part.argtypes = [vp, vp, i32, i32, vp, vp]
-        L.orc_labels.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.orc_labels.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.orc_solve_patches.argtypes = [vp, vp, d, i32, i32, vp, vp, vp]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
@@ -188,16 +188,26 @@ def trace_part(fine, fb: np.ndarray, part: int, max_sweeps: int = 1_000_000):
     return phi, sw.value
 
 
-def labels(fine, fb: np.ndarray, max_sweeps: int = 1_000_000, want_sum: bool = False):
-    """Step 3.1 for every part plus the projection/assembly into labels."""
+def labels(fine, fb: np.ndarray, max_sweeps: int = 1_000_000, want_sum: bool = False,
+           want_unreached: bool = False):
+    """Step 3.1 for every part plus the projection/assembly into labels
+    (with the Remark 3.1 fill of nodes no colour reached).  want_sum adds
+    (sum of colours, max sweeps of a part); want_unreached adds the number of
+    nodes no colour reached before the fill."""
     H = _Held(fine)
     fb = np.ascontiguousarray(fb, dtype=np.uint8).ravel()
     lab = np.empty(fine.N, dtype=np.int16)
     s = np.empty(fine.N, dtype=np.float64) if want_sum else None
     mx = C.c_int(0)
-    _check(lib().orc_labels(H.ref, _p(fb), int(max_sweeps), _p(lab), _p(s), C.byref(mx)),
-           "labels")
-    return (lab, s, mx.value) if want_sum else lab
+    un = C.c_longlong(0)
+    _check(lib().orc_labels(H.ref, _p(fb), int(max_sweeps), _p(lab), _p(s), C.byref(mx),
+                            C.byref(un)), "labels")
+    out = (lab,)
+    if want_sum:
+        out = out + (s, mx.value)
+    if want_unreached:
+        out = out + (un.value,)
+    return out if len(out) > 1 else lab
 
 
 def solve_patches(fine, labels_: np.ndarray, tol: float = 0.0, max_sweeps: int = 1_000_000,

@@ -120,6 +120,7 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   }
   a.nc = F.nc;
   a.has_drift = F.drift ? 1 : 0;
+  a.beta = F.beta;
   a.ctrl64 = F.ctrl64;
   a.speed64 = F.speed64;
   a.drift64 = F.drift64;
@@ -180,16 +181,36 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
                            hipMemcpyDeviceToHost, s));
     HJB_HIP(hipStreamSynchronize(s));
     if (host.as<uint32_t>()[0] == 0) break;
-    HJB_REQUIRE(rounds < 10000000, "colour transport did not settle");
+    HJB_REQUIRE(rounds < 4000000, "colour transport did not settle");
   }
   DBuf unreached(sizeof(uint32_t) * 2);
   HJB_HIP(launch_fill_u32(unreached.as<uint32_t>(), 0u, 1, s));
   HJB_HIP(launch_labels(dim, a, H.labels.as<int16_t>(), unreached.as<uint32_t>(), s));
-  HJB_HIP(launch_make_code(F.tp, H.labels.as<int16_t>(), nullptr, N, H.code.as<int16_t>(), s));
   uint32_t un = 0;
   unsigned long long w[2] = {0, 0};
   HJB_HIP(hipMemcpyAsync(&un, unreached.get(), sizeof un, hipMemcpyDeviceToHost, s));
   HJB_HIP(hipMemcpyAsync(w, work.get(), sizeof w, hipMemcpyDeviceToHost, s));
+  HJB_HIP(hipStreamSynchronize(s));
+  if (un > 0) {
+    // Remark 3.1 fill of the nodes no colour reached, layer by layer
+    DBuf tmp(N * sizeof(int16_t));
+    int16_t *cur = H.labels.as<int16_t>(), *nxt = tmp.as<int16_t>();
+    const int32_t n3[3] = {F.n[0], F.n[1], F.n[2]};
+    uint32_t *flag = unreached.as<uint32_t>() + 1;
+    uint32_t *hflag = host.as<uint32_t>();
+    for (long long layer = 0;; ++layer) {
+      HJB_HIP(launch_fill_u32(flag, 0u, 1, s));
+      HJB_HIP(launch_label_fill(n3, cur, nxt, flag, s));
+      HJB_HIP(hipMemcpyAsync(hflag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      HJB_HIP(hipStreamSynchronize(s));
+      std::swap(cur, nxt);
+      if (hflag[0] == 0) break;
+      HJB_REQUIRE(layer < (long long)N, "label fill did not settle");
+    }
+    if (cur != H.labels.as<int16_t>())
+      HJB_HIP(hipMemcpyAsync(H.labels.get(), cur, N * sizeof(int16_t), hipMemcpyDeviceToDevice, s));
+  }
+  HJB_HIP(launch_make_code(F.tp, H.labels.as<int16_t>(), nullptr, N, H.code.as<int16_t>(), s));
   HJB_HIP(hipStreamSynchronize(s));
   const double t2 = now_ms();
   std::memset(&H.st, 0, sizeof H.st);

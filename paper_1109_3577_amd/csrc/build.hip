@@ -124,9 +124,14 @@ hipError_t launch_feedback(int dim, const TraceArgs &a, const double *u0, uint8_
 // stay zero); each part's transport is independent of the others, so
 // processing a subset changes no bit of any colour.
 
-// Interpolated colours below this floor count as zero: only the projection
-// of the colours is used (the paper lets this iteration stop very roughly),
-// and the floor keeps every part's support compact.  The map stays monotone.
+// Colour update phi <- max(phi, beta I[phi]): beta = exp(-h) is the
+// scheme's per-step factor in the Kruzkov variable, so a colour is the
+// share of exp(-T) part j carries along the frozen feedback and the map is a
+// beta-contraction (undamped, near-closed loops of the frozen feedback make
+// the iteration contract arbitrarily slowly).  Colours below the floor count
+// as zero: only their projection is used (the paper lets this iteration stop
+// very roughly), and the floor keeps each part's support compact.  Both
+// maps are monotone.
 constexpr double kColourFloor = 1e-9;
 
 constexpr int TR2_TX = 32, TR2_TY = 8, TR2_CL = 8;
@@ -308,6 +313,7 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
               double I1 = Ar<double>::lin(t1[j], q0, q1);
               I = Ar<double>::lin(t2[j], I, I1);
             }
+            I = a.beta * I;
             if (I < kColourFloor) I = 0.0;
             if (I > sp[own[j]]) {
               s_phi[f * LN + own[j]] = I;
@@ -459,6 +465,44 @@ hipError_t launch_labels(int dim, const TraceArgs &a, int16_t *labels, uint32_t 
   const SweepShape sh = trace_shape(dim);
   hipLaunchKernelGGL(k_labels, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, sh.tx,
                      sh.ty, sh.tz, labels, unreached);
+  return hipGetLastError();
+}
+
+// Remark 3.1: a node no colour reached takes the smallest label among its
+// labelled neighbours (8 in 2D, 26 in 3D).  One Jacobi layer per launch;
+// repeated until nothing changes, the result is the lowest label among the
+// nearest labelled nodes, independent of the launch schedule.
+__global__ void k_label_fill(int n0, int n1, int n2, const int16_t *__restrict__ in, int16_t *out,
+                             uint32_t *changed) {
+  const size_t N = (size_t)n0 * n1 * n2;
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  int L = in[g];
+  if (L < 0) {
+    const int x = (int)(g % n0), y = (int)((g / n0) % n1), z = (int)(g / ((size_t)n0 * n1));
+    const int dz0 = n2 > 1 ? -1 : 0, dz1 = n2 > 1 ? 1 : 0;
+    int best = -1;
+    for (int dz = dz0; dz <= dz1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int X = x + dx, Y = y + dy, Z = z + dz;
+          if (X < 0 || Y < 0 || Z < 0 || X >= n0 || Y >= n1 || Z >= n2) continue;
+          const int M = in[(size_t)X + (size_t)n0 * ((size_t)Y + (size_t)n1 * Z)];
+          if (M >= 0 && (best < 0 || M < best)) best = M;
+        }
+    if (best >= 0) {
+      L = best;
+      *changed = 1u;
+    }
+  }
+  out[g] = (int16_t)L;
+}
+
+hipError_t launch_label_fill(const int32_t n[3], const int16_t *in, int16_t *out,
+                             uint32_t *changed, hipStream_t s) {
+  const size_t N = (size_t)n[0] * n[1] * n[2];
+  hipLaunchKernelGGL(k_label_fill, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, n[0], n[1],
+                     n[2], in, out, changed);
   return hipGetLastError();
 }
 

@@ -90,6 +90,7 @@ struct TraceArgs {
   int32_t n_parts;   // R
   int32_t words;     // mask words per tile, ceil(R / 32)
   double step[3];
+  double beta;       // per-step factor of the colour transport
   const double *ctrl64;
   const double *speed64;
   const double *drift64;
@@ -136,6 +137,8 @@ hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &
 hipError_t launch_trace_seed(int dim, const TraceArgs &a, const RoundArgs &ra, hipStream_t s);
 hipError_t launch_labels(int dim, const TraceArgs &a, int16_t *labels, uint32_t *unreached,
                          hipStream_t s);
+hipError_t launch_label_fill(const int32_t n[3], const int16_t *in, int16_t *out,
+                             uint32_t *changed, hipStream_t s);
 hipError_t launch_count_active(const int16_t *code, size_t N, unsigned long long *out,
                                hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
