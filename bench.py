@@ -45,7 +45,114 @@ def parse():
     ap.add_argument("--no-global", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=100)
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--mode", choices=("solve", "batch", "serve", "copy"), default="solve",
+                    help="solve: the 1025^2 patchy problem (default, the headline line); "
+                         "batch: many uneven problems in shared rounds; serve: Poisson "
+                         "request stream through the continuous-batching server")
+    ap.add_argument("--count", type=int, default=0, help="problems (batch) / requests (serve)")
+    ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / capacity")
     return ap.parse_args()
+
+
+def bench_copy(args):
+    """A plain device-to-device copy of known size, for calibrating the HBM
+    byte counters (FETCH_SIZE / WRITE_SIZE) of the profiler."""
+    import torch
+    nbytes = args.count or (256 << 20)
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "copies": 3}))
+
+
+def bench_batch(args):
+    """Uneven 2D problems (grid side 65..769, 16..64 controls, 4..32 parts,
+    seeded-sign drift) solved together, against the same problems solved one
+    after the other with the plain global GPU solve."""
+    import numpy as np
+    import torch
+
+    from paper_1109_3577_amd import autotune, hjb, problems
+
+    count = args.count or 512
+    t = time.perf_counter()
+    probs = problems.config4(count)
+    print(f"[bench] generated {count} problems in {time.perf_counter() - t:.1f} s",
+          file=sys.stderr, flush=True)
+    fines = [hjb.Problem(f, device=True) for f, _ in probs]
+    coarses = [hjb.Problem(c, device=True) for _, c in probs]
+    choice, _ = autotune.tune_batch(fines, coarses, hjb.HJB_F32, args.tol, sample=16)
+    opts = autotune.opts_from(choice)
+    t = time.perf_counter()
+    b = hjb.hjb_batch_create(fines, coarses, hjb.HJB_F32, args.tol, 0, opts)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t
+    t = time.perf_counter()
+    st = b.run()
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t
+    nodes = sum(p.N for p in fines)
+    # baseline: the plain global solve of every problem, one after the other
+    t = time.perf_counter()
+    gupd = 0
+    for f in fines:
+        v = torch.empty(f.N, dtype=torch.float32, device="cuda")
+        g = hjb.hjb_solve_global(f, hjb.HJB_F32, v, args.tol, 0,
+                                 hjb.make_opts(schedule=hjb.HJB_SCHED_JACOBI, rounds_per_poll=8))
+        gupd += g["updates"]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    print(json.dumps({
+        "metric": "batched patchy solve: node-control updates/s and wall time vs sequential "
+                  "plain solves", "mode": "batch", "problems": count, "nodes": nodes,
+        "autotuned": choice, "prepare_s": t_prep, "sweep_s": t_run,
+        "batch_total_s": t_prep + t_run, "updates": st["updates"],
+        "updates_per_s": st["updates"] / t_run, "items": st["items"], "rounds": st["rounds"],
+        "sequential_plain_global_s": t_seq, "sequential_plain_updates": gupd,
+        "speedup_vs_sequential_plain": t_seq / (t_prep + t_run)}))
+
+
+def bench_serve(args):
+    """Poisson stream of solve requests through the continuous-batching
+    server: 80% 2D (side 129..1025; half eikonal with 16 parts, half the
+    batched generator), 20% 3D (side 65..193, the 3D generator)."""
+    import numpy as np
+    import torch
+
+    from paper_1109_3577_amd import problems, serve
+
+    count = args.count or 300
+    t = time.perf_counter()
+    reqs = []
+    for r in problems.serving_stream(count, 1.0, seed=0):
+        reqs.append(r)
+        if len(reqs) % 25 == 0:
+            print(f"[bench] generated {len(reqs)}/{count} requests", file=sys.stderr, flush=True)
+    print(f"[bench] generated {count} requests in {time.perf_counter() - t:.1f} s",
+          file=sys.stderr, flush=True)
+    budget = int(0.8 * torch.cuda.mem_get_info()[0])
+    cap = serve.run(reqs[: max(20, count // 5)], budget, tol=args.tol, closed_loop=True,
+                    verbose=True)
+    print(f"[bench] capacity {cap['requests_per_s']:.2f} requests/s", file=sys.stderr, flush=True)
+    rate = args.load * cap["requests_per_s"]
+    # re-time the same requests on a Poisson clock at the chosen rate
+    rng = np.random.default_rng(1)
+    tt = 0.0
+    for r in reqs:
+        tt += float(rng.exponential(1.0 / rate))
+        r.arrival_s = tt
+    res = serve.run(reqs, budget, tol=args.tol, verbose=True)
+    n3 = sum(1 for r in reqs if r.fine.dim == 3)
+    print(json.dumps({
+        "metric": "serving: p50/p99 latency and node-control updates/s at a fixed Poisson rate",
+        "mode": "serve", "requests": count, "requests_3d": n3,
+        "capacity_requests_per_s": cap["requests_per_s"], "arrival_rate_per_s": rate,
+        "load": args.load, "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
+        "mean_ms": res["mean_ms"], "requests_per_s": res["requests_per_s"],
+        "updates_per_s": res["updates_per_s"], "wall_s": res["wall_s"]}))
 
 
 def main():
@@ -61,6 +168,12 @@ def main():
     from paper_1109_3577_amd import hjb, problems
 
     torch.cuda.set_device(0)
+    if args.mode == "batch":
+        return bench_batch(args)
+    if args.mode == "serve":
+        return bench_serve(args)
+    if args.mode == "copy":
+        return bench_copy(args)
     stream = torch.cuda.Stream()
     fine_src, coarse_src = problems.config2(args.seed, args.n, args.ncoarse)
     fine = hjb.Problem(fine_src, device=True)

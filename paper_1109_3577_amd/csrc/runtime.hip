@@ -318,16 +318,27 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
   c.max_rounds = max_sweeps > 0 ? max_sweeps : 1000000;
   HJB_REQUIRE(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");
   if (opts) {
-    if (opts->tile[0] > 0) {
+    // A tile shape names its dimension (tile[2] > 1 only in 3D); a batch
+    // or server with both kinds applies it to the matching engine only.
+    const bool tile3 = opts->tile[2] > 1;
+    if (opts->tile[0] > 0 && tile3 == (dim == 3)) {
       c.shape.tx = opts->tile[0];
       c.shape.ty = opts->tile[1];
       c.shape.tz = dim == 3 ? opts->tile[2] : 1;
+      if (opts->threads > 0) c.shape.nt = opts->threads;
+      HJB_REQUIRE(sweep_shape_supported(c.shape.dim, c.shape.tx, c.shape.ty, c.shape.tz,
+                                        c.shape.nt),
+                  "unsupported tile shape %dx%dx%d with %d threads for dim %d", c.shape.tx,
+                  c.shape.ty, c.shape.tz, c.shape.nt, dim);
+    } else if (opts->tile[0] <= 0 && opts->threads > 0 &&
+               sweep_shape_supported(c.shape.dim, c.shape.tx, c.shape.ty, c.shape.tz,
+                                     opts->threads)) {
+      c.shape.nt = opts->threads;
     }
-    if (opts->threads > 0) c.shape.nt = opts->threads;
-    HJB_REQUIRE(sweep_shape_supported(c.shape.dim, c.shape.tx, c.shape.ty, c.shape.tz, c.shape.nt),
-                "unsupported tile shape %dx%dx%d with %d threads for dim %d", c.shape.tx,
-                c.shape.ty, c.shape.tz, c.shape.nt, dim);
-    if (opts->inner_sweeps > 0) c.inner_sweeps = opts->inner_sweeps;
+    if (opts->tile[0] > 0 && tile3 == (dim == 3) && opts->inner_sweeps > 0)
+      c.inner_sweeps = opts->inner_sweeps;
+    else if (opts->tile[0] <= 0 && opts->inner_sweeps > 0)
+      c.inner_sweeps = opts->inner_sweeps;
     if (opts->rounds_per_poll > 0) c.rounds_per_poll = opts->rounds_per_poll;
     c.use_graph = opts->use_graph != 0;
     c.time_kernels = opts->time_kernels != 0;
