@@ -32,6 +32,40 @@ PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes/clk x clock = 3
 PEAK_HBM = 8.0e12
 
 
+# Sources of the tiled sweep kernel; HBM counters recorded for it count only
+# while these files are unchanged.
+SWEEP_SOURCES = ("paper_1109_3577_amd/csrc/sweep.hip", "paper_1109_3577_amd/csrc/device_math.h",
+                 "paper_1109_3577_amd/csrc/hjb_internal.h")
+PMC_SUMMARY = "profiles/k_sweep_f32_2d_1025_pmc.md"
+
+
+def sweep_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary:
+    (FETCH_SIZE x fetch factor + WRITE_SIZE x write factor), the factors being
+    what the same counters read for a copy of known size.  None when there is
+    no record for this kernel or its sources changed since it was taken."""
+    path = os.path.join(ROOT, PMC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("pmc: "):
+                rec = json.loads(line[5:])
+                if rec.get("kernel") == kernel and rec.get("source_hash") == sweep_source_hash():
+                    return (rec["fetch_kib_per_dispatch"] * 1024.0 * rec["fetch_factor"]
+                            + rec["write_kib_per_dispatch"] * 1024.0 * rec["write_factor"])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,18 +280,26 @@ def main():
                              "coarse": coarse_upd // args.steps},
     }
 
-    # Dominant kernel: the FP32 tiled sweep, HIP events around every launch.
+    # Dominant kernel: the FP32 tiled sweep, HIP events around every block of
+    # launches on the solve's stream.
     if launches:
         ops = VALU_OPS_PER_UPDATE[2] * solve_upd
         achieved = ops / (kernel_ms * 1e-3)
+        s0 = sts[0][0]
+        kernel = "k_sweep<float, 2, %d, %d, %d, %d>" % (*s0["tile"], s0["threads"])
+        avg_s = kernel_ms * 1e-3 / launches
+        traffic = recorded_traffic(kernel)
         out["roofline"] = {
-            "bound": "alu", "kernel": "k_sweep<float,2,64,16,1,256>",
+            "bound": "alu", "kernel": kernel,
             "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
             "unit": "TOP/s (VALU lane-ops)", "frac": achieved / PEAK_VALU_LANE_OPS,
-            "traffic": None,
-            "avg_launch_us": kernel_ms * 1e3 / launches, "launches": launches,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch",
+            "hbm_gbps": None if traffic is None else traffic / avg_s / 1e9,
+            "avg_launch_us": avg_s * 1e6, "launches": launches,
             "ops_per_update": VALU_OPS_PER_UPDATE[2],
             "updates_per_launch": solve_upd / launches,
+            "inner_sweeps": s0["inner_sweeps"],
         }
 
     # Plain global GPU solve of the same fine problem (full-grid Jacobi,
@@ -272,7 +314,7 @@ def main():
             gt = hjb.hjb_solve_global(fine, hjb.HJB_F32, vt, args.tol, 0, None, stream)
             torch.cuda.synchronize()
             E = (v.double() - vg.double()).abs()
-        out["global"] = {"jacobi_ms": gj["ms_wall"], "jacobi_sweeps": gj["reserved"],
+        out["global"] = {"jacobi_ms": gj["ms_wall"], "jacobi_sweeps": gj["sweeps"],
                          "jacobi_updates": gj["updates"], "tiled_ms": gt["ms_wall"],
                          "tiled_updates": gt["updates"],
                          "speedup_patchy_step_vs_jacobi": gj["ms_wall"] / ms_per_step,

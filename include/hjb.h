@@ -124,6 +124,11 @@ typedef struct {
   int64_t trace_node_updates;
   int32_t unreached;       /* nodes no colour reached; they took their
                               neighbours' label (Remark 3.1) */
+  int32_t sweeps;          /* HJB_SCHED_JACOBI: whole-grid sweeps executed */
+  /* launch configuration of the sweep kernel that ran (tiled solves) */
+  int32_t tile[3];
+  int32_t threads;
+  int32_t inner_sweeps;
   int32_t reserved;
 } hjb_stats;
 

@@ -57,6 +57,11 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
     st->kernel_launches = eng.kernel_launches();
     st->status = status;
     st->ms_wall = now_ms() - t0;
+    st->tile[0] = cfg.shape.tx;
+    st->tile[1] = cfg.shape.ty;
+    st->tile[2] = cfg.shape.tz;
+    st->threads = cfg.shape.nt;
+    st->inner_sweeps = cfg.inner_sweeps;
   }
   return status;
 }

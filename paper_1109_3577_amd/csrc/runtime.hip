@@ -739,7 +739,7 @@ int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out,
     }
     st->ms_kernel = ms;
     st->kernel_launches = launches;
-    st->reserved = (int32_t)sweeps;
+    st->sweeps = (int32_t)sweeps;
   }
   for (auto e : ev) (void)hipEventDestroy(e);
   return status;

@@ -46,10 +46,15 @@ class hjb_stats(C.Structure):
                 ("kernel_launches", C.c_int32), ("status", C.c_int32),
                 ("ms_prolong_feedback", C.c_double), ("ms_trace", C.c_double),
                 ("trace_node_updates", C.c_int64), ("unreached", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("sweeps", C.c_int32), ("tile", C.c_int32 * 3), ("threads", C.c_int32),
+                ("inner_sweeps", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {}
+        for name, _ in self._fields_:
+            x = getattr(self, name)
+            out[name] = list(x) if name == "tile" else x
+        return out
 
 
 class hjb_solve_opts(C.Structure):
