@@ -134,7 +134,11 @@ typedef struct {
 
 /* Tuning options; NULL or zero fields select the defaults. */
 typedef struct {
-  int32_t tile[3];         /* tile shape in nodes (supported shapes only) */
+  int32_t tile[3];         /* tile shape in nodes; supported (tile, threads):
+                              2D 16x16 and 32x8 with 256; 64x8, 32x16,
+                              64x16 and 32x32 with 256 or 512;
+                              3D 8x8x8 with 256 or 512, 16x8x8 with 256 or
+                              512, 32x8x4 with 256 */
   int32_t inner_sweeps;    /* max in-LDS sweeps per tile activation */
   int32_t rounds_per_poll; /* sweep rounds enqueued between host polls */
   int32_t schedule;        /* HJB_SCHED_* (hjb_solve_global only) */

@@ -17,8 +17,8 @@ from typing import Dict, Optional, Sequence, Tuple
 from . import hjb
 
 CANDIDATES = {
-    2: [((64, 8, 1), 512), ((64, 8, 1), 256), ((32, 16, 1), 512), ((64, 16, 1), 512),
-        ((32, 32, 1), 512)],
+    2: [((32, 8, 1), 256), ((16, 16, 1), 256), ((64, 8, 1), 512), ((32, 16, 1), 512),
+        ((32, 16, 1), 256), ((32, 32, 1), 512)],
     3: [((8, 8, 8), 256), ((8, 8, 8), 512), ((16, 8, 8), 512)],
 }
 SWEEPS = {2: (8, 12, 16, 24), 3: (2, 4, 8)}

@@ -68,7 +68,6 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
 
 // In-tile sweeps of one colour-transport tile activation before it is
 // queued again.
-constexpr int kTraceInnerSweeps = 16;
 
 // Steps 2 and 3.1: prolongation, feedback, chunked colour transport, labels.
 std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const CoarseHandle &C,
@@ -144,7 +143,8 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   a.words = (H.n_parts + 31) / 32;
   DBuf phi((size_t)H.n_parts * N * sizeof(double));
   DBuf masks((size_t)ntiles * a.words * sizeof(uint32_t));
-  DBuf lists[2], flags[2], count(4 * sizeof(uint32_t)), work(2 * sizeof(unsigned long long));
+  DBuf lists[2], flags[2], count(4 * sizeof(uint32_t)),
+      work(2 * kSlots * sizeof(unsigned long long));
   for (int i = 0; i < 2; ++i) {
     lists[i].reset((size_t)ntiles * sizeof(int32_t));
     flags[i].reset((size_t)ntiles * sizeof(uint32_t));
@@ -162,14 +162,14 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   std::memset(&ra, 0, sizeof ra);
   ra.count = count.as<uint32_t>();
   ra.work = work.as<unsigned long long>();
-  ra.inner_sweeps = kTraceInnerSweeps;
+  ra.inner_sweeps = trace_inner_sweeps(dim);
   // seeding appends to list[0]/count[0] as if it were round -1 (== 2 mod 3)
   ra.list_out = lists[0].as<int32_t>();
   ra.flags_out = flags[0].as<uint32_t>();
   ra.round = 2;
   HJB_HIP(launch_trace_seed(dim, a, ra, s));
   const int grid = std::min(ntiles, 4096);
-  const int rpp = 4;
+  const int rpp = 16;  // rounds between host polls (an empty round is a few us)
   long long rounds = 0;
   uint32_t r = 0;
   while (true) {
@@ -192,10 +192,15 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   HJB_HIP(launch_fill_u32(unreached.as<uint32_t>(), 0u, 1, s));
   HJB_HIP(launch_labels(dim, a, H.labels.as<int16_t>(), unreached.as<uint32_t>(), s));
   uint32_t un = 0;
-  unsigned long long w[2] = {0, 0};
+  unsigned long long ws[2 * kSlots];
   HJB_HIP(hipMemcpyAsync(&un, unreached.get(), sizeof un, hipMemcpyDeviceToHost, s));
-  HJB_HIP(hipMemcpyAsync(w, work.get(), sizeof w, hipMemcpyDeviceToHost, s));
+  HJB_HIP(hipMemcpyAsync(ws, work.get(), sizeof ws, hipMemcpyDeviceToHost, s));
   HJB_HIP(hipStreamSynchronize(s));
+  unsigned long long w[2] = {0, 0};
+  for (int k = 0; k < kSlots; ++k) {
+    w[0] += ws[k];
+    w[1] += ws[kSlots + k];
+  }
   if (un > 0) {
     // Remark 3.1 fill of the nodes no colour reached, layer by layer
     DBuf tmp(N * sizeof(int16_t));
@@ -244,7 +249,21 @@ std::unique_ptr<CoarseHandle> coarse_solve_impl(const hjb_problem *coarse, doubl
   h->v.reset(P->N * sizeof(double));
   DBuf code(P->N * sizeof(int16_t));
   HJB_HIP(launch_make_code(P->tp, nullptr, nullptr, P->N, code.as<int16_t>(), s));
-  *status = engine_solve(*P, code.as<int16_t>(), 1, h->v.get(), true, nullptr, tol, max_sweeps, s,
+  // The coarse grid is small (tens of nodes a side): small tiles keep the
+  // per-round latency down.
+  hjb_solve_opts eo;
+  std::memset(&eo, 0, sizeof eo);
+  const hjb_solve_opts *op = nullptr;
+  if (P->dim == 2) {
+    eo.tile[0] = 16;
+    eo.tile[1] = 16;
+    eo.tile[2] = 1;
+    eo.threads = 256;
+    eo.inner_sweeps = 8;
+    eo.rounds_per_poll = 16;
+    op = &eo;
+  }
+  *status = engine_solve(*P, code.as<int16_t>(), 1, h->v.get(), true, op, tol, max_sweeps, s,
                          &h->st, t0);
   return h;
 }

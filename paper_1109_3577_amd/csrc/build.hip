@@ -134,15 +134,21 @@ hipError_t launch_feedback(int dim, const TraceArgs &a, const double *u0, uint8_
 // maps are monotone.
 constexpr double kColourFloor = 1e-9;
 
-constexpr int TR2_TX = 32, TR2_TY = 8, TR2_CL = 8;
-constexpr int TR3_TX = 8, TR3_TY = 8, TR3_TZ = 8, TR3_CL = 4;
-constexpr int TR_NT = 256;
+// Colour-transport tiles: 2D 32 x 16 nodes, 512 threads, 8 FP64 fields per
+// LDS group, up to 32 in-tile sweeps per activation; 3D 8 x 8 x 8, 256
+// threads, 4 fields, 16 sweeps.  (The front of the colours moves about one
+// cell per sweep; the per-node work is one foot point, so sweeps are cheap
+// and a tile is swept until it settles or its budget ends.)
+constexpr int TR2_TX = 32, TR2_TY = 16, TR2_NT = 512, TR2_CL = 8, TR2_K = 32;
+constexpr int TR3_TX = 8, TR3_TY = 8, TR3_TZ = 8, TR3_NT = 256, TR3_CL = 4, TR3_K = 16;
 constexpr int kMaxTraceWords = 32;  // up to 1024 parts
 
 int trace_chunk_capacity(int dim) { return dim == 2 ? TR2_CL : TR3_CL; }
 int trace_max_parts() { return kMaxTraceWords * 32; }
+int trace_inner_sweeps(int dim) { return dim == 2 ? TR2_K : TR3_K; }
 SweepShape trace_shape(int dim) {
-  return dim == 2 ? SweepShape{2, TR2_TX, TR2_TY, 1} : SweepShape{3, TR3_TX, TR3_TY, TR3_TZ};
+  return dim == 2 ? SweepShape{2, TR2_TX, TR2_TY, 1, TR2_NT}
+                  : SweepShape{3, TR3_TX, TR3_TY, TR3_TZ, TR3_NT};
 }
 
 // phi = 1 on the target nodes of their own part (the rest of phi is zero
@@ -358,29 +364,40 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
       __syncthreads();  // LDS is refilled by the next group
     }
 
-    if (bx1 >= 0) {
+    // changed-node box: reduced within each wave, merged by one LDS atomic
+    // per wave
+    wave_min_i(bx0); wave_min_i(by0); wave_min_i(bz0);
+    wave_max_i(bx1); wave_max_i(by1); wave_max_i(bz1);
+    if ((tid & 63) == 0 && bx1 >= 0) {
       atomicMin(&s_int[0], bx0); atomicMin(&s_int[1], by0); atomicMin(&s_int[2], bz0);
       atomicMax(&s_int[3], bx1); atomicMax(&s_int[4], by1); atomicMax(&s_int[5], bz1);
     }
     const int conv_all = __syncthreads_and(converged_all ? 1 : 0);
     const int cx0 = s_int[0], cy0 = s_int[1], cz0 = s_int[2];
     const int cx1 = s_int[3], cy1 = s_int[4], cz1 = s_int[5];
-    if (cx1 >= 0 && tid < NNB) {
-      const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = (DIM == 3) ? tid / 9 - 1 : 0;
-      bool need;
-      if (dx == 0 && dy == 0 && dz == 0) need = !conv_all;
-      else
-        need = (dx < 0 ? cx0 < HALO : dx > 0 ? cx1 >= TX - HALO : true) &&
-               (dy < 0 ? cy0 < HALO : dy > 0 ? cy1 >= TY - HALO : true) &&
-               (dz < 0 ? cz0 < HALO : dz > 0 ? cz1 >= TZ - HALO : true);
-      const int nx = tix + dx, ny = tiy + dy, nz = tiz + dz;
-      if (need && nx >= 0 && ny >= 0 && nz >= 0 && nx < a.ntile[0] && ny < a.ntile[1] &&
-          nz < a.ntile[2])
-        queue_tile(ra, nx + a.ntile[0] * (ny + a.ntile[1] * nz));
+    if (cx1 >= 0 && tid < 64) {
+      int qt = -1;
+      if (tid < NNB) {
+        const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = (DIM == 3) ? tid / 9 - 1 : 0;
+        bool need;
+        if (dx == 0 && dy == 0 && dz == 0) need = !conv_all;
+        else
+          need = (dx < 0 ? cx0 < HALO : dx > 0 ? cx1 >= TX - HALO : true) &&
+                 (dy < 0 ? cy0 < HALO : dy > 0 ? cy1 >= TY - HALO : true) &&
+                 (dz < 0 ? cz0 < HALO : dz > 0 ? cz1 >= TZ - HALO : true);
+        const int nx = tix + dx, ny = tiy + dy, nz = tiz + dz;
+        if (need && nx >= 0 && ny >= 0 && nz >= 0 && nx < a.ntile[0] && ny < a.ntile[1] &&
+            nz < a.ntile[2]) {
+          const int t2 = nx + a.ntile[0] * (ny + a.ntile[1] * nz);
+          if (atomicCAS(&ra.flags_out[t2], 0u, 1u) == 0u) qt = t2;
+        }
+      }
+      queue_items(ra, qt, nullptr);
     }
     if (tid == 0) {
-      atomicAdd(&ra.work[1], 1ull);
-      atomicAdd(&ra.work[0], (unsigned long long)nact);
+      const int slot = blockIdx.x % kSlots;
+      atomicAdd(&ra.work[kSlots + slot], 1ull);
+      atomicAdd(&ra.work[slot], (unsigned long long)nact);
     }
     __syncthreads();
   }
@@ -389,11 +406,11 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
 hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &ra, hipStream_t s) {
   if (a.words > kMaxTraceWords) return hipErrorInvalidValue;
   if (dim == 2)
-    hipLaunchKernelGGL((k_trace<2, TR2_TX, TR2_TY, 1, TR_NT, TR2_CL>), dim3(grid), dim3(TR_NT), 0,
-                       s, a, ra);
+    hipLaunchKernelGGL((k_trace<2, TR2_TX, TR2_TY, 1, TR2_NT, TR2_CL>), dim3(grid), dim3(TR2_NT),
+                       0, s, a, ra);
   else
-    hipLaunchKernelGGL((k_trace<3, TR3_TX, TR3_TY, TR3_TZ, TR_NT, TR3_CL>), dim3(grid),
-                       dim3(TR_NT), 0, s, a, ra);
+    hipLaunchKernelGGL((k_trace<3, TR3_TX, TR3_TY, TR3_TZ, TR3_NT, TR3_CL>), dim3(grid),
+                       dim3(TR3_NT), 0, s, a, ra);
   return hipGetLastError();
 }
 

@@ -48,70 +48,90 @@ struct Ar<double> {
   static __device__ __forceinline__ double flr(double x) { return __builtin_floor(x); }
 };
 
-// Interpolate the LDS tile at base + d (d in cells, |d| < 2).  Corners
-// enumerate x fastest; nesting x, then y, then z.
-template <typename T, int DIM, int LX, int LY>
-__device__ __forceinline__ T interp_lds(const T *s, int base, const T *d);
+// a * b + c on 24-bit unsigned operands in one instruction.  Written out so
+// that the compiler keeps the multiply-add (two instructions with the final
+// shift-add of the byte address) instead of distributing the word-to-byte
+// shift over both terms (three instructions).
+__device__ __forceinline__ int mad_u24(int a, int b, int c) {
+  int r;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
 
-// FP32: cell index by floor-convert, local coordinate by fract, 24-bit
-// index arithmetic.  (fract clamps its result below 1, so a displacement a
-// hair below an integer lands on t = 1 - 2^-24 of the lower cell instead
-// of t = 1: the same value up to the last bit; every FP32 kernel uses this
-// one evaluation.)
-template <int DIM, int LX, int LY>
-__device__ __forceinline__ float interp_lds_f32(const float *s, int base, const float *d) {
-  const int i0 = (int)__builtin_floorf(d[0]);
-  const int i1 = (int)__builtin_floorf(d[1]);
-  const float t0 = __builtin_amdgcn_fractf(d[0]);
-  const float t1 = __builtin_amdgcn_fractf(d[1]);
-  // byte offset of the lower corner: one 24-bit multiply-add, one shift-add
-  int ob = __mul24(i1, LX * 4) + (base << 2);
+// LDS interpolation.  Corners enumerate x fastest; nesting x, then y, then
+// z.  LXS is the row stride of the LDS tile (words), LY its rows.
+//
+// FP32 foot point in offset form: the foot-point fma yields y = d + 2 in
+// [0, 4) (|d| < 2 is checked on the host), so the cell is a plain
+// float-to-int conversion (truncation is floor on y >= 0) and the local
+// coordinate is fract(y), exact on [0, 4).  The offset costs one rounding of
+// the displacement at 2^-22 cells; every FP32 kernel uses this evaluation.
+// `b2` is the LDS word index of the node minus 2 cells along every axis, so
+// the lower corner is b2 + y0 + LXS y1 (+ LXS LY y2).
+template <int DIM, int LXS, int LY>
+__device__ __forceinline__ float interp_lds_f32(const float *s, int b2, const float *y) {
+  const int i0 = (int)y[0];
+  const int i1 = (int)y[1];
+  const float t0 = __builtin_amdgcn_fractf(y[0]);
+  const float t1 = __builtin_amdgcn_fractf(y[1]);
+  int o = mad_u24(i1, LXS, i0);
   float t2 = 0.0f;
   if constexpr (DIM == 3) {
-    const int i2 = (int)__builtin_floorf(d[2]);
-    t2 = __builtin_amdgcn_fractf(d[2]);
-    ob += __mul24(i2, LX * LY * 4);
+    const int i2 = (int)y[2];
+    t2 = __builtin_amdgcn_fractf(y[2]);
+    o = mad_u24(i2, LXS * LY, o);
   }
-  ob += i0 << 2;
-  const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(s) + ob);
+  const float *p = s + (b2 + o);
   const float r0 = Ar<float>::lin(t0, p[0], p[1]);
-  const float r1 = Ar<float>::lin(t0, p[LX], p[LX + 1]);
+  const float r1 = Ar<float>::lin(t0, p[LXS], p[LXS + 1]);
   const float y0 = Ar<float>::lin(t1, r0, r1);
   if constexpr (DIM == 2) {
     return y0;
   } else {
-    const float *q = p + LX * LY;
+    const float *q = p + LXS * LY;
     const float q0 = Ar<float>::lin(t0, q[0], q[1]);
-    const float q1 = Ar<float>::lin(t0, q[LX], q[LX + 1]);
+    const float q1 = Ar<float>::lin(t0, q[LXS], q[LXS + 1]);
     const float y1 = Ar<float>::lin(t1, q0, q1);
     return Ar<float>::lin(t2, y0, y1);
   }
 }
 
-template <typename T, int DIM, int LX, int LY>
-__device__ __forceinline__ T interp_lds(const T *s, int base, const T *d) {
-  if constexpr (sizeof(T) == 4) return interp_lds_f32<DIM, LX, LY>(s, base, d);
-  T f0 = Ar<T>::flr(d[0]), f1 = Ar<T>::flr(d[1]);
-  T t0 = d[0] - f0, t1 = d[1] - f1;
-  int o = base + (int)f0 + (int)f1 * LX;
-  T f2 = T(0), t2 = T(0);
+// FP64: displacement d (cells), cell floor(d), local coordinate d - floor(d),
+// each multiply and add separate, as in the CPU evaluation.  `base` is the
+// LDS word index of the node itself.
+template <int DIM, int LXS, int LY>
+__device__ __forceinline__ double interp_lds_f64(const double *s, int base, const double *d) {
+  double f0 = Ar<double>::flr(d[0]), f1 = Ar<double>::flr(d[1]);
+  double t0 = d[0] - f0, t1 = d[1] - f1;
+  int o = base + (int)f0 + (int)f1 * LXS;
+  double f2 = 0.0, t2 = 0.0;
   if constexpr (DIM == 3) {
-    f2 = Ar<T>::flr(d[2]);
+    f2 = Ar<double>::flr(d[2]);
     t2 = d[2] - f2;
-    o += (int)f2 * (LX * LY);
+    o += (int)f2 * (LXS * LY);
   }
-  T r0 = Ar<T>::lin(t0, s[o], s[o + 1]);
-  T r1 = Ar<T>::lin(t0, s[o + LX], s[o + LX + 1]);
-  T y0 = Ar<T>::lin(t1, r0, r1);
+  double r0 = Ar<double>::lin(t0, s[o], s[o + 1]);
+  double r1 = Ar<double>::lin(t0, s[o + LXS], s[o + LXS + 1]);
+  double y0 = Ar<double>::lin(t1, r0, r1);
   if constexpr (DIM == 2) {
     return y0;
   } else {
-    const int oz = o + LX * LY;
-    T q0 = Ar<T>::lin(t0, s[oz], s[oz + 1]);
-    T q1 = Ar<T>::lin(t0, s[oz + LX], s[oz + LX + 1]);
-    T y1 = Ar<T>::lin(t1, q0, q1);
-    return Ar<T>::lin(t2, y0, y1);
+    const int oz = o + LXS * LY;
+    double q0 = Ar<double>::lin(t0, s[oz], s[oz + 1]);
+    double q1 = Ar<double>::lin(t0, s[oz + LXS], s[oz + LXS + 1]);
+    double y1 = Ar<double>::lin(t1, q0, q1);
+    return Ar<double>::lin(t2, y0, y1);
   }
+}
+
+__device__ __forceinline__ void wave_min_i(int &x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
+}
+
+__device__ __forceinline__ void wave_max_i(int &x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
 }
 
 template <typename T>
@@ -123,28 +143,57 @@ __device__ __forceinline__ void wave_max(T &x) {
   }
 }
 
-__device__ __forceinline__ void queue_item(const RoundArgs &ra, int item, uint32_t *pactive_next) {
-  if (atomicCAS(&ra.flags_out[item], 0u, 1u) == 0u) {
-    uint32_t idx = atomicAdd(&ra.count[(ra.round + 1) % 3], 1u);
-    ra.list_out[idx] = item;
-    atomicAdd(pactive_next, 1u);
+// Appends the items claimed by the lanes of one wave (it >= 0: this lane
+// won the item's flag) to the next round's list: one atomic reserves the
+// slots of the whole wave, and the problem's queued count grows by as many.
+// Every lane of the wave must call it.
+__device__ __forceinline__ void queue_items(const RoundArgs &ra, int it, uint32_t *pactive_next) {
+  const unsigned long long m = __ballot(it >= 0);
+  if (m == 0ull) return;
+  const int n = __popcll(m);
+  const int lane = threadIdx.x & 63;
+  const int first = __ffsll((long long)m) - 1;
+  uint32_t base = 0u;
+  if (lane == first) {
+    base = atomicAdd(&ra.count[(ra.round + 1) % 3], (uint32_t)n);
+    if (pactive_next) atomicAdd(pactive_next, (uint32_t)n);
+  }
+  base = __shfl(base, first, 64);
+  if (it >= 0) {
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    ra.list_out[base + rank] = it;
   }
 }
 
-// Interpolate a global-memory grid at p + d, ghost 1 outside the box (every
-// box node active).  Same nesting as the LDS variant.
+// Interpolate a global-memory grid at the foot point, ghost 1 outside the
+// box (every box node active).  Same nesting and the same per-precision
+// foot-point evaluation as the LDS variants: FP32 takes y = d + 2, FP64
+// takes d.
 template <typename T, int DIM>
 __device__ __forceinline__ T interp_global(const T *__restrict__ v, const int n[3], int px, int py,
                                            int pz, const T *d) {
-  T f0 = Ar<T>::flr(d[0]), f1 = Ar<T>::flr(d[1]);
-  T t0 = d[0] - f0, t1 = d[1] - f1;
-  const int x0 = px + (int)f0, y0 = py + (int)f1;
-  T f2 = T(0), t2 = T(0);
-  int z0 = 0;
-  if constexpr (DIM == 3) {
-    f2 = Ar<T>::flr(d[2]);
-    t2 = d[2] - f2;
-    z0 = pz + (int)f2;
+  int x0, y0, z0 = 0;
+  T t0, t1, t2 = T(0);
+  if constexpr (sizeof(T) == 4) {
+    x0 = px + (int)d[0] - 2;
+    y0 = py + (int)d[1] - 2;
+    t0 = __builtin_amdgcn_fractf(d[0]);
+    t1 = __builtin_amdgcn_fractf(d[1]);
+    if constexpr (DIM == 3) {
+      z0 = pz + (int)d[2] - 2;
+      t2 = __builtin_amdgcn_fractf(d[2]);
+    }
+  } else {
+    T f0 = Ar<T>::flr(d[0]), f1 = Ar<T>::flr(d[1]);
+    t0 = d[0] - f0;
+    t1 = d[1] - f1;
+    x0 = px + (int)f0;
+    y0 = py + (int)f1;
+    if constexpr (DIM == 3) {
+      T f2 = Ar<T>::flr(d[2]);
+      t2 = d[2] - f2;
+      z0 = pz + (int)f2;
+    }
   }
   auto at = [&](int x, int y, int z) -> T {
     bool inb = (unsigned)x < (unsigned)n[0] && (unsigned)y < (unsigned)n[1];

@@ -23,6 +23,11 @@ namespace hjb {
 constexpr int HALO = 2;  // foot points lie within 2 cells (checked on input)
 constexpr int16_t CODE_TARGET = -2;
 constexpr int16_t CODE_NONE = -1;
+// Statistics and residual counters are spread over kSlots addresses (slot =
+// workgroup index mod kSlots) so that the workgroups of a round do not all
+// update one address; the host reduces the slots.
+constexpr int kSlots = 16;
+constexpr int kCounterWords = 3 * kSlots + 2 + 2 * kSlots;  // u64 words per problem
 
 // Per-problem parameters as the kernels see them.  Lives in device memory
 // (an array of these for a batch).  Pointers are device pointers.
@@ -38,8 +43,9 @@ struct DevProblem {
   double beta, omb;     // FP64 Kruzkov constants
   double step[3];       // FP64 h / k_d
   float betaf, ombf;    // FP32 Kruzkov constants
-  const double *ctrl64; // [nc][dim] a_k (FP64, as given)
-  const float *ctrl32;  // [nc][dim] s_d * a_kd rounded to FP32
+  const double *ctrl64; // [rows][dim] a_k (FP64, as given); rows = round4(nc) + 4,
+                        // rows past nc repeat the last control
+  const float *ctrl32;  // [rows][dim] s_d * a_kd rounded to FP32
   const double *speed64;
   const float *speed32;
   const double *drift64;  // [N][dim] or null
@@ -49,9 +55,9 @@ struct DevProblem {
   const int32_t *item_map;  // [n_patches][ntiles]: local item id or -1
   int32_t item_base;        // global id of local item 0
   int32_t pad1;
-  unsigned long long *residual;  // [3] per-round max decrease (FP64 bits)
+  unsigned long long *residual;  // [3][kSlots] per-round max decrease (FP64 bits)
   uint32_t *pactive;             // [3] per-round count of queued items
-  unsigned long long *work;      // [2] node updates, item runs
+  unsigned long long *work;      // [2][kSlots] node updates, item runs
 };
 
 struct Item {
@@ -73,7 +79,7 @@ struct RoundArgs {
   uint32_t *flags_in;
   uint32_t *flags_out;
   uint32_t *count;            // [3]
-  unsigned long long *work;   // [2]: node updates, item runs
+  unsigned long long *work;   // [2][kSlots]: node updates, item runs (colour transport)
   uint32_t round;
   int32_t inner_sweeps;
   int32_t nprob;
@@ -133,6 +139,7 @@ hipError_t launch_trace_init(int dim, const TraceArgs &a, hipStream_t s);
 int trace_chunk_capacity(int dim);
 int trace_max_parts();
 SweepShape trace_shape(int dim);
+int trace_inner_sweeps(int dim);
 hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &ra, hipStream_t s);
 hipError_t launch_trace_seed(int dim, const TraceArgs &a, const RoundArgs &ra, hipStream_t s);
 hipError_t launch_labels(int dim, const TraceArgs &a, int16_t *labels, uint32_t *unreached,

@@ -138,7 +138,7 @@ struct SolveConfig {
   bool fp64 = false;
   SweepShape shape{2, 64, 16, 1};
   int inner_sweeps = 48;
-  int rounds_per_poll = 6;
+  int rounds_per_poll = 16;
   bool use_graph = false;
   bool time_kernels = false;
   double tol = 0.0;

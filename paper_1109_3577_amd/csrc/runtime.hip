@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -269,15 +270,18 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
     D->drift64 = P.drift;
     D->tp = P.target_part;
   }
-  // Control tables with one extra row (a copy of row 0) so that kernels can
-  // fetch control k+1 while they evaluate control k.  FP32 rows carry
+  // Control tables padded to a whole number of groups of 4 plus one more
+  // group, the extra rows repeating the last control: the sweep reads the
+  // controls four at a time and fetches the next group ahead, and a repeated
+  // control leaves the minimum over the set unchanged.  FP32 rows carry
   // s_d * a_kd rounded to FP32.
   const int nc = P.n_controls, dim = P.dim;
-  D->ctrl64_pad.resize((size_t)(nc + 1) * dim);
-  D->ctrl32_pad.resize((size_t)(nc + 1) * dim);
-  for (int k = 0; k <= nc; ++k)
+  const int rows = ((nc + 3) & ~3) + 4;
+  D->ctrl64_pad.resize((size_t)rows * dim);
+  D->ctrl32_pad.resize((size_t)rows * dim);
+  for (int k = 0; k < rows; ++k)
     for (int d = 0; d < dim; ++d) {
-      const double a = D->ctrl_host[(size_t)(k < nc ? k : 0) * dim + d];
+      const double a = D->ctrl_host[(size_t)(k < nc ? k : nc - 1) * dim + d];
       D->ctrl64_pad[(size_t)k * dim + d] = a;
       D->ctrl32_pad[(size_t)k * dim + d] = (float)(P.step[d] * a);
     }
@@ -304,7 +308,7 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
 
 static SweepShape default_shape(int dim, bool fp64) {
   (void)fp64;
-  if (dim == 2) return SweepShape{2, 64, 8, 1, 512};
+  if (dim == 2) return SweepShape{2, 32, 8, 1, 256};
   return SweepShape{3, 8, 8, 8, 256};
 }
 
@@ -313,7 +317,7 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
   SolveConfig c;
   c.fp64 = fp64;
   c.shape = default_shape(dim, fp64);
-  c.inner_sweeps = dim == 2 ? 12 : 4;
+  c.inner_sweeps = dim == 2 ? 8 : 4;
   c.tol = tol;
   c.max_rounds = max_sweeps > 0 ? max_sweeps : 1000000;
   HJB_REQUIRE(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");
@@ -453,13 +457,13 @@ int SweepEngine::add_problem(const ProblemDev &P, const int16_t *code, const Pro
 
 void SweepEngine::begin(const std::vector<int32_t> *seeds) {
   const size_t np = dps_.size();
-  counters_.reset(std::max<size_t>(np, 1) * 8 * sizeof(unsigned long long));
+  counters_.reset(std::max<size_t>(np, 1) * kCounterWords * sizeof(unsigned long long));
   HJB_HIP(hipMemsetAsync(counters_.get(), 0, counters_.bytes(), s_));
   for (size_t i = 0; i < np; ++i) {
-    unsigned long long *c = counters_.as<unsigned long long>() + i * 8;
-    dps_[i].residual = c;                                 // [0..2]
-    dps_[i].pactive = reinterpret_cast<uint32_t *>(c + 3);  // 3 x u32 in [3..4]
-    dps_[i].work = c + 5;                                 // [5..6]
+    unsigned long long *c = counters_.as<unsigned long long>() + i * kCounterWords;
+    dps_[i].residual = c;                                             // [3][kSlots]
+    dps_[i].pactive = reinterpret_cast<uint32_t *>(c + 3 * kSlots);   // 3 x u32
+    dps_[i].work = c + 3 * kSlots + 2;                                // [2][kSlots]
   }
   probs_d_.reset(std::max<size_t>(np, 1) * sizeof(DevProblem));
   HJB_HIP(hipMemcpyAsync(probs_d_.get(), dps_.data(), np * sizeof(DevProblem),
@@ -612,32 +616,43 @@ std::vector<int32_t> SweepEngine::queue_now() {
 
 std::vector<uint32_t> SweepEngine::pactive_now() {
   const size_t np = dps_.size();
-  std::vector<unsigned long long> cnt(np * 8);
+  const size_t W = kCounterWords;
+  std::vector<unsigned long long> cnt(np * W);
   if (np)
-    HJB_HIP(hipMemcpyAsync(cnt.data(), counters_.get(), np * 8 * sizeof(unsigned long long),
+    HJB_HIP(hipMemcpyAsync(cnt.data(), counters_.get(), np * W * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, s_));
   HJB_HIP(hipStreamSynchronize(s_));
   std::vector<uint32_t> out(np);
   for (size_t i = 0; i < np; ++i)
-    out[i] = reinterpret_cast<const uint32_t *>(&cnt[i * 8 + 3])[r_ % 3];
+    out[i] = reinterpret_cast<const uint32_t *>(&cnt[i * W + 3 * kSlots])[r_ % 3];
   return out;
 }
 
 std::vector<EngineResult> SweepEngine::results() {
   const size_t np = dps_.size();
-  std::vector<unsigned long long> cnt(np * 8);
+  const size_t W = kCounterWords;
+  std::vector<unsigned long long> cnt(np * W);
   if (np)
-    HJB_HIP(hipMemcpyAsync(cnt.data(), counters_.get(), np * 8 * sizeof(unsigned long long),
+    HJB_HIP(hipMemcpyAsync(cnt.data(), counters_.get(), np * W * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, s_));
   HJB_HIP(hipStreamSynchronize(s_));
   std::vector<EngineResult> out(np);
   for (size_t i = 0; i < np; ++i) {
-    // residual of the last executed round lives in slot (r - 1) mod 3
+    const unsigned long long *c = &cnt[i * W];
+    // residual of the last executed round lives in row (r - 1) mod 3; the
+    // FP64 bits of non-negative values order like the values
+    unsigned long long rb = 0;
+    for (int k = 0; k < kSlots; ++k) rb = std::max(rb, c[((r_ + 2) % 3) * kSlots + k]);
     double rd;
-    std::memcpy(&rd, &cnt[i * 8 + ((r_ + 2) % 3)], sizeof rd);
+    std::memcpy(&rd, &rb, sizeof rd);
     out[i].residual = rd;
-    out[i].work_nodes = cnt[i * 8 + 5];
-    out[i].item_runs = cnt[i * 8 + 6];
+    unsigned long long wn = 0, ir = 0;
+    for (int k = 0; k < kSlots; ++k) {
+      wn += c[3 * kSlots + 2 + k];
+      ir += c[3 * kSlots + 2 + kSlots + k];
+    }
+    out[i].work_nodes = wn;
+    out[i].item_runs = ir;
   }
   return out;
 }

@@ -28,19 +28,42 @@ namespace hjb {
 
 // ---------------------------------------------------------------- tiled sweep
 
+// LDS row stride of a tile: FP32 2D rows are padded to 8 words mod 32 so
+// that the four rows of a half-wave brick fall on distinct banks.
+template <typename T, int DIM, int LX>
+constexpr int lds_stride() {
+  return (DIM == 2 && sizeof(T) == 4) ? LX + ((8 - LX % 32) + 32) % 32 : LX;
+}
+
+// Work of one wave is a brick of 64 nodes: 8 x 8 in 2D, 4 x 4 x 4 in 3D.
+template <int DIM>
+struct Brick {
+  static constexpr int X = DIM == 2 ? 8 : 4;
+  static constexpr int Y = DIM == 2 ? 8 : 4;
+  static constexpr int Z = DIM == 2 ? 1 : 4;
+};
+
 template <typename T, int DIM, int TX, int TY, int TZ, int NT, bool DRIFT>
 __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item,
                                            const RoundArgs &ra, T *s_v, int *s_int,
-                                           double *s_red) {
+                                           double *s_red, unsigned long long *s_wrk,
+                                           uint32_t *s_msk) {
   constexpr int LX = TX + 2 * HALO;
   constexpr int LY = TY + 2 * HALO;
   constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
+  constexpr int LXS = lds_stride<T, DIM, LX>();
   constexpr int LN = LX * LY * LZ;
   constexpr int TN = TX * TY * (DIM == 3 ? TZ : 1);
-  constexpr int NPT = TN / NT;
-  static_assert(TN % NT == 0, "tile must be a multiple of the block");
+  constexpr int NPT = TN / NT;  // bricks per wave
+  constexpr int NW = NT / 64;
+  constexpr int BX = Brick<DIM>::X, BY = Brick<DIM>::Y, BZ = Brick<DIM>::Z;
+  constexpr int NBX = TX / BX, NBY = TY / BY, NBZ = (DIM == 3) ? TZ / BZ : 1;
+  static_assert(TN % NT == 0 && NT % 64 == 0, "tile must be a multiple of the block");
+  static_assert(TX % BX == 0 && TY % BY == 0 && (DIM == 2 || TZ % BZ == 0), "brick tiling");
+  static_assert(NBX * NBY * NBZ <= 32, "brick mask is one word");
 
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const int tt = item.tile;
   const int tix = tt % P.ntile[0];
@@ -52,7 +75,8 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
   const int16_t *__restrict__ code = P.code;
 
   // Stage tile + halo: stored value where the node is active in this patch
-  // (target nodes are 0, patch nodes carry v), ghost 1 everywhere else.
+  // (target nodes are 0, patch nodes carry v), ghost 1 everywhere else.  The
+  // code and the value are fetched together.
   for (int i = tid; i < LN; i += NT) {
     const int lx = i % LX;
     const int ly = (i / LX) % LY;
@@ -64,39 +88,60 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
     if (inb) {
       const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0));
       const int cd = code[g];
-      if (cd == CODE_TARGET) val = T(0);
-      else if (cd == patch) val = v[g];
+      const T vg = v[g];
+      val = cd == CODE_TARGET ? T(0) : (cd == patch ? vg : T(1));
     }
-    s_v[i] = val;
+    s_v[lx + LXS * (ly + LY * lz)] = val;
   }
 
+  // This thread's nodes: lane `lane` of brick `wave + j NW`, j < NPT.
   T cc[NPT];
   T ww[NPT][DIM];
   int off[NPT];
   size_t gid[NPT];
   bool act[NPT];
-  int nact = 0;
+  uint32_t nbm[NPT];  // bricks whose change can reach brick j
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int i = tid + j * NT;
-    const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+    const int b = wave + j * NW;
+    const int bx = b % NBX, by = (b / NBX) % NBY, bz = b / (NBX * NBY);
+    const int lx = bx * BX + lane % BX;
+    const int ly = by * BY + (lane / BX) % BY;
+    const int lz = bz * BZ + lane / (BX * BY);
+    uint32_t m = 0u;
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int x = bx + dx, y = by + dy, z = bz + dz;
+          if (x >= 0 && x < NBX && y >= 0 && y < NBY && z >= 0 && z < NBZ)
+            m |= 1u << (x + NBX * (y + NBY * z));
+        }
+    nbm[j] = m;
     const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
     bool inb = gx < n0 && gy < n1;
     if constexpr (DIM == 3) inb = inb && gz < n2;
-    off[j] = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
+    off[j] = (lx + HALO) + LXS * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
     const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0));
     gid[j] = g;
     act[j] = inb && code[g] == patch;
-    nact += act[j] ? 1 : 0;
     if constexpr (sizeof(T) == 4) {
+      // offset foot point: y = c a + (w + 2)
       cc[j] = act[j] ? P.speed32[g] : 0.0f;
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) ww[j][a] = (DRIFT && act[j]) ? P.drift32[g * DIM + a] : 0.0f;
+      for (int q = 0; q < DIM; ++q)
+        ww[j][q] = ((DRIFT && act[j]) ? P.drift32[g * DIM + q] : 0.0f) + 2.0f;
     } else {
       cc[j] = act[j] ? P.speed64[g] : 0.0;
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) ww[j][a] = (DRIFT && act[j]) ? P.drift64[g * DIM + a] : 0.0;
+      for (int q = 0; q < DIM; ++q) ww[j][q] = (DRIFT && act[j]) ? P.drift64[g * DIM + q] : 0.0;
     }
+  }
+  // brick-change masks, three in rotation: sweep s reads the mask of sweep
+  // s - 1, ORs its own into slot s % 3 and clears the slot of sweep s + 1
+  if (tid == 0) {
+    s_msk[0] = 0u;
+    s_msk[1] = 0u;
+    s_msk[2] = ~0u;  // "changed before sweep 0": every brick is swept first
   }
   __syncthreads();
 
@@ -107,94 +152,117 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
   const T beta = sizeof(T) == 4 ? (T)P.betaf : (T)P.beta;
   const T omb = sizeof(T) == 4 ? (T)P.ombf : (T)P.omb;
   const T tolT = (T)ra.tol;
-  const int nc = P.nc;
+  const int ng = (P.nc + 3) >> 2;  // groups of 4 controls (table is padded)
   const int K = ra.inner_sweeps;
-  int iters = 0;
+  unsigned long long upd = 0;
   bool converged = false;
   for (int it = 0; it < K; ++it) {
-    T mI[NPT];
+    const uint32_t prev = s_msk[(it + 2) % 3];
+    if (tid == 0) s_msk[(it + 1) % 3] = 0u;
+    uint32_t mine = 0u;
 #pragma unroll
-    for (int j = 0; j < NPT; ++j) mI[j] = T(3);
-    // controls are read through the scalar cache; the table holds one
-    // extra row so that the next control can be fetched ahead
-    T an[DIM];
-    if constexpr (sizeof(T) == 4) {
-#pragma unroll
-      for (int q = 0; q < DIM; ++q) an[q] = ((cf32p)P.ctrl32)[q];
-    } else {
-#pragma unroll
-      for (int q = 0; q < DIM; ++q) an[q] = ((cf64p)P.ctrl64)[q];
-    }
-#pragma unroll 2
-    for (int k = 0; k < nc; ++k) {
-      T a[DIM];
-#pragma unroll
-      for (int q = 0; q < DIM; ++q) a[q] = an[q];
+    for (int j = 0; j < NPT; ++j) {
+      // Skip the brick when nothing within its reach changed in the last
+      // sweep: its update would read the same values and change nothing.
+      if ((prev & nbm[j]) == 0u) continue;
+      upd += act[j] ? 1u : 0u;
+      T mI = T(3);
       if constexpr (sizeof(T) == 4) {
+        const int b2 = off[j] - 2 - 2 * LXS - (DIM == 3 ? 2 * LXS * LY : 0);
+        for (int g4 = 0; g4 < ng; ++g4) {
+          float a[4 * DIM];
 #pragma unroll
-        for (int q = 0; q < DIM; ++q) an[q] = ((cf32p)P.ctrl32)[(k + 1) * DIM + q];
+          for (int q = 0; q < 4 * DIM; ++q) a[q] = ((cf32p)P.ctrl32)[g4 * 4 * DIM + q];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            float y[DIM];
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) y[q] = __builtin_fmaf(cc[j], a[u * DIM + q], ww[j][q]);
+            mI = __builtin_fminf(mI, interp_lds_f32<DIM, LXS, LY>(s_v, b2, y));
+          }
+        }
       } else {
+        for (int k = 0; k < 4 * ng; ++k) {
+          T d[DIM];
 #pragma unroll
-        for (int q = 0; q < DIM; ++q) an[q] = ((cf64p)P.ctrl64)[(k + 1) * DIM + q];
-      }
-#pragma unroll
-      for (int j = 0; j < NPT; ++j) {
-        T d[DIM];
-#pragma unroll
-        for (int q = 0; q < DIM; ++q) {
-          if constexpr (sizeof(T) == 4) {
-            d[q] = DRIFT ? __builtin_fmaf(cc[j], a[q], ww[j][q]) : cc[j] * a[q];
-          } else {
-            T g = cc[j] * a[q];
+          for (int q = 0; q < DIM; ++q) {
+            T g = cc[j] * ((cf64p)P.ctrl64)[k * DIM + q];
             if (DRIFT) g = g + ww[j][q];
             d[q] = P.step[q] * g;
           }
+          const T I = interp_lds_f64<DIM, LXS, LY>(s_v, off[j], d);
+          mI = I < mI ? I : mI;
         }
-        const T I = interp_lds<T, DIM, LX, LY>(s_v, off[j], d);
-        if constexpr (sizeof(T) == 4) mI[j] = __builtin_fminf(mI[j], I);
-        else mI[j] = I < mI[j] ? I : mI[j];
       }
-    }
-    int ch = 0;
-#pragma unroll
-    for (int j = 0; j < NPT; ++j) {
+      bool chg = false;
       if (act[j]) {
         // min_k (beta I_k + omb) == beta (min_k I_k) + omb: the map is
         // monotone, also after rounding.
-        const T cand = Ar<T>::kruzkov(beta, mI[j], omb);
+        const T cand = Ar<T>::kruzkov(beta, mI, omb);
         const T cur = s_v[off[j]];
         if (cand < cur) {
           s_v[off[j]] = cand;
-          if (cur - cand > tolT) ch = 1;
+          chg = cur - cand > tolT;
         }
       }
+      if (__ballot(chg) != 0ull) mine |= 1u << (wave + j * NW);
     }
-    ++iters;
-    if (!__syncthreads_or(ch)) {
+    if (lane == 0 && mine) atomicOr(&s_msk[it % 3], mine);
+    __syncthreads();
+    if (s_msk[it % 3] == 0u) {
       converged = true;
       break;
     }
   }
 
-  // Write back, FP64 residual, bounding box of the changed nodes.
+  // Write back, FP64 residual, bounding box of the changed nodes.  The box
+  // is found per brick from a wave ballot of the changed lanes, then merged
+  // by one LDS atomic per wave and bound.
   double dmax = 0.0;
   int bx0 = 1 << 30, by0 = 1 << 30, bz0 = 1 << 30, bx1 = -1, by1 = -1, bz1 = -1;
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
+    bool big = false;
     if (act[j]) {
       const T nv = s_v[off[j]];
       if (nv < old[j]) {
         v[gid[j]] = nv;
         const double dd = (double)old[j] - (double)nv;
         dmax = dd > dmax ? dd : dmax;
-        if (old[j] - nv > tolT) {
-          const int i = tid + j * NT;
-          const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
-          bx0 = min(bx0, lx); bx1 = max(bx1, lx);
-          by0 = min(by0, ly); by1 = max(by1, ly);
-          bz0 = min(bz0, lz); bz1 = max(bz1, lz);
-        }
+        big = old[j] - nv > tolT;
       }
+    }
+    const unsigned long long m = __ballot(big);
+    if (m) {
+      const int b = wave + j * NW;
+      const int ox0 = (b % NBX) * BX, oy0 = ((b / NBX) % NBY) * BY, oz0 = (b / (NBX * NBY)) * BZ;
+      uint32_t xs, ys, zs;
+      if constexpr (DIM == 2) {
+        // lane = x + 8 y
+        unsigned long long c = m | (m >> 32);
+        c |= c >> 16;
+        c |= c >> 8;
+        xs = (uint32_t)(c & 0xffu);
+        ys = 0u;
+#pragma unroll
+        for (int y = 0; y < 8; ++y) ys |= ((m >> (8 * y)) & 0xffull) ? (1u << y) : 0u;
+        zs = 1u;
+      } else {
+        // lane = x + 4 y + 16 z
+        unsigned long long g = (m | (m >> 16) | (m >> 32) | (m >> 48)) & 0xffffull;
+        unsigned long long c = g | (g >> 8);
+        c |= c >> 4;
+        xs = (uint32_t)(c & 0xfu);
+        ys = 0u;
+        zs = 0u;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) ys |= ((g >> (4 * y)) & 0xfull) ? (1u << y) : 0u;
+#pragma unroll
+        for (int z = 0; z < 4; ++z) zs |= ((m >> (16 * z)) & 0xffffull) ? (1u << z) : 0u;
+      }
+      bx0 = min(bx0, ox0 + __builtin_ctz(xs)); bx1 = max(bx1, ox0 + 31 - __builtin_clz(xs));
+      by0 = min(by0, oy0 + __builtin_ctz(ys)); by1 = max(by1, oy0 + 31 - __builtin_clz(ys));
+      bz0 = min(bz0, oz0 + __builtin_ctz(zs)); bz1 = max(bz1, oz0 + 31 - __builtin_clz(zs));
     }
   }
   if (tid == 0) {
@@ -202,35 +270,45 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
     s_int[3] = -1; s_int[4] = -1; s_int[5] = -1;
   }
   wave_max(dmax);
+  // node updates executed: active nodes of the bricks swept, per sweep
+  unsigned long long cw = upd;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) cw += __shfl_xor(cw, o, 64);
   __syncthreads();
-  if ((tid & 63) == 0) s_red[tid >> 6] = dmax;
-  if (bx1 >= 0) {
-    atomicMin(&s_int[0], bx0); atomicMin(&s_int[1], by0); atomicMin(&s_int[2], bz0);
-    atomicMax(&s_int[3], bx1); atomicMax(&s_int[4], by1); atomicMax(&s_int[5], bz1);
+  if (lane == 0) {
+    s_red[wave] = dmax;
+    s_wrk[wave] = cw;
+    if (bx1 >= 0) {
+      atomicMin(&s_int[0], bx0); atomicMin(&s_int[1], by0); atomicMin(&s_int[2], bz0);
+      atomicMax(&s_int[3], bx1); atomicMax(&s_int[4], by1); atomicMax(&s_int[5], bz1);
+    }
   }
   __syncthreads();
   const int cx0 = s_int[0], cy0 = s_int[1], cz0 = s_int[2];
   const int cx1 = s_int[3], cy1 = s_int[4], cz1 = s_int[5];
+  const int slot = blockIdx.x % kSlots;
   if (tid == 0) {
     double m = 0.0;
-    for (int w = 0; w < NT / 64; ++w) m = s_red[w] > m ? s_red[w] : m;
-    if (m > 0.0) atomicMax(&P.residual[ra.round % 3], (unsigned long long)__double_as_longlong(m));
-    atomicAdd(&P.work[1], 1ull);
-  }
-  // node updates: active nodes of the item x iterations
-  {
-    int c = nact;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
-    if ((tid & 63) == 0 && c > 0) atomicAdd(&P.work[0], (unsigned long long)c * (unsigned long long)iters);
+    unsigned long long wsum = 0;
+    for (int w = 0; w < NW; ++w) {
+      m = s_red[w] > m ? s_red[w] : m;
+      wsum += s_wrk[w];
+    }
+    if (m > 0.0)
+      atomicMax(&P.residual[(ra.round % 3) * kSlots + slot],
+                (unsigned long long)__double_as_longlong(m));
+    if (wsum) atomicAdd(&P.work[slot], wsum);
+    atomicAdd(&P.work[kSlots + slot], 1ull);
   }
 
   // Queue the neighbour items (same patch) whose halo holds a changed node,
-  // and this item again if its in-LDS sweeps did not settle.
-  if (cx1 >= 0) {
+  // and this item again if its in-LDS sweeps did not settle.  The lanes of
+  // wave 0 claim their items' flags, then reserve list slots with one atomic.
+  if (cx1 >= 0 && wave == 0) {
     constexpr int NNB = (DIM == 3) ? 27 : 9;
-    if (tid < NNB) {
-      const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = (DIM == 3) ? tid / 9 - 1 : 0;
+    int it2 = -1;
+    if (lane < NNB) {
+      const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = (DIM == 3) ? lane / 9 - 1 : 0;
       bool need;
       if (dx == 0 && dy == 0 && dz == 0) {
         need = !converged;
@@ -244,10 +322,11 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
           nz < P.ntile[2]) {
         const int t2 = nx + P.ntile[0] * (ny + P.ntile[1] * nz);
         const int ntiles = P.ntile[0] * P.ntile[1] * P.ntile[2];
-        const int it2 = P.item_map[(size_t)patch * ntiles + t2];
-        if (it2 >= 0) queue_item(ra, P.item_base + it2, &P.pactive[(ra.round + 1) % 3]);
+        const int l = P.item_map[(size_t)patch * ntiles + t2];
+        if (l >= 0 && atomicCAS(&ra.flags_out[P.item_base + l], 0u, 1u) == 0u) it2 = P.item_base + l;
       }
     }
+    queue_items(ra, it2, &P.pactive[(ra.round + 1) % 3]);
   }
 }
 
@@ -257,15 +336,19 @@ k_sweep(const DevProblem *__restrict__ probs, const Item *__restrict__ items, Ro
   constexpr int LX = TX + 2 * HALO;
   constexpr int LY = TY + 2 * HALO;
   constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
-  __shared__ T s_v[LX * LY * LZ];
+  constexpr int LXS = lds_stride<T, DIM, LX>();
+  __shared__ T s_v[LXS * LY * LZ];
   __shared__ int s_int[8];
+  __shared__ uint32_t s_msk[4];
   __shared__ double s_red[NT / 64];
+  __shared__ unsigned long long s_wrk[NT / 64];
   const uint32_t r = ra.round;
   if (blockIdx.x == 0) {
     if (threadIdx.x == 0) ra.count[(r + 2) % 3] = 0u;
-    for (int p = threadIdx.x; p < ra.nprob; p += NT) {
-      probs[p].pactive[(r + 2) % 3] = 0u;
-      probs[p].residual[(r + 2) % 3] = 0ull;
+    for (int p = threadIdx.x; p < ra.nprob * kSlots; p += NT) {
+      const int q = p / kSlots, k = p % kSlots;
+      if (k == 0) probs[q].pactive[(r + 2) % 3] = 0u;
+      probs[q].residual[((r + 2) % 3) * kSlots + k] = 0ull;
     }
   }
   const uint32_t nin = ra.count[r % 3];
@@ -275,14 +358,16 @@ k_sweep(const DevProblem *__restrict__ probs, const Item *__restrict__ items, Ro
     const DevProblem &P = probs[item.prob];
     if (threadIdx.x == 0) ra.flags_in[it] = 0u;
     if (P.has_drift)
-      sweep_item<T, DIM, TX, TY, TZ, NT, true>(P, item, ra, s_v, s_int, s_red);
+      sweep_item<T, DIM, TX, TY, TZ, NT, true>(P, item, ra, s_v, s_int, s_red, s_wrk, s_msk);
     else
-      sweep_item<T, DIM, TX, TY, TZ, NT, false>(P, item, ra, s_v, s_int, s_red);
+      sweep_item<T, DIM, TX, TY, TZ, NT, false>(P, item, ra, s_v, s_int, s_red, s_wrk, s_msk);
     __syncthreads();
   }
 }
 
 #define HJB_SHAPES(X)      \
+  X(2, 16, 16, 1, 256)     \
+  X(2, 32, 8, 1, 256)      \
   X(2, 64, 16, 1, 256)     \
   X(2, 32, 32, 1, 256)     \
   X(2, 64, 8, 1, 256)      \
@@ -345,8 +430,9 @@ k_jacobi(const DevProblem *__restrict__ Pp, const T *__restrict__ vin, T *__rest
       const int pz = (int)(g / ((size_t)P.n[0] * P.n[1]));
       T c, w[DIM];
       if constexpr (sizeof(T) == 4) {
+        // offset foot point, as in the tiled sweep: y = c a + (w + 2)
         c = P.speed32[g];
-        for (int a = 0; a < DIM; ++a) w[a] = P.has_drift ? P.drift32[g * DIM + a] : 0.0f;
+        for (int a = 0; a < DIM; ++a) w[a] = (P.has_drift ? P.drift32[g * DIM + a] : 0.0f) + 2.0f;
       } else {
         c = P.speed64[g];
         for (int a = 0; a < DIM; ++a) w[a] = P.has_drift ? P.drift64[g * DIM + a] : 0.0;
@@ -357,7 +443,7 @@ k_jacobi(const DevProblem *__restrict__ Pp, const T *__restrict__ vin, T *__rest
         for (int q = 0; q < DIM; ++q) {
           if constexpr (sizeof(T) == 4) {
             const float a = ((cf32p)P.ctrl32)[k * DIM + q];
-            d[q] = P.has_drift ? __builtin_fmaf(c, a, w[q]) : c * a;
+            d[q] = __builtin_fmaf(c, a, w[q]);
           } else {
             const double a = ((cf64p)P.ctrl64)[k * DIM + q];
             double gg = c * a;
