@@ -85,8 +85,13 @@ extern "C" {
 #define HJB_F64 1
 
 /* Schedules of hjb_solve_global. */
-#define HJB_SCHED_TILED 0  /* LDS tiles, in-tile sweeps, active-tile lists */
-#define HJB_SCHED_JACOBI 1 /* one full-grid Jacobi sweep per launch */
+#define HJB_SCHED_TILED 0  /* LDS tiles, in-tile sweeps, active-tile lists:
+                              synchronous rounds, one launch per round */
+#define HJB_SCHED_JACOBI 1 /* one full-grid Jacobi sweep per launch
+                              (hjb_solve_global only) */
+#define HJB_SCHED_ASYNC 2  /* the same tiles in one persistent launch that
+                              drains a device work queue (no rounds; no
+                              sweep cap: max_sweeps must be 0) */
 
 typedef void *hjb_stream_t; /* hipStream_t */
 
@@ -141,7 +146,7 @@ typedef struct {
                               512, 32x8x4 with 256 */
   int32_t inner_sweeps;    /* max in-LDS sweeps per tile activation */
   int32_t rounds_per_poll; /* sweep rounds enqueued between host polls */
-  int32_t schedule;        /* HJB_SCHED_* (hjb_solve_global only) */
+  int32_t schedule;        /* HJB_SCHED_* (JACOBI: hjb_solve_global only) */
   int32_t time_kernels;    /* 1: HIP events around each polled block of
                               sweep launches (kernel time in hjb_stats) */
   int32_t use_graph;       /* 1: replay the polled rounds as a hipGraph */

@@ -44,7 +44,7 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
   SweepEngine eng(cfg, s);
   eng.add_problem(P, code, &items, v);
   eng.begin();
-  const int status = eng.run();
+  const int status = eng.async_ok() ? eng.run_async() : eng.run();
   if (st) {
     const EngineResult r = eng.results()[0];
     st->node_updates = (int64_t)r.work_nodes;
@@ -169,10 +169,22 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   ra.round = 2;
   HJB_HIP(launch_trace_seed(dim, a, ra, s));
   const int grid = std::min(ntiles, 4096);
-  const int rpp = 16;  // rounds between host polls (an empty round is a few us)
+  // Rounds in blocks of 16; the next block is enqueued before the host
+  // reads the queue count that the previous one left (pipelined polling).
+  const int rpp = 16;
   long long rounds = 0;
   uint32_t r = 0;
-  while (true) {
+  hipEvent_t pev[2];
+  for (auto &e : pev) HJB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() {
+      (void)hipEventDestroy(e[0]);
+      (void)hipEventDestroy(e[1]);
+    }
+  } evguard{pev};
+  uint32_t *hc = host.as<uint32_t>();
+  auto enqueue = [&](int slot) {
     for (int i = 0; i < rpp; ++i, ++r) {
       ra.list_in = lists[r & 1].as<int32_t>();
       ra.list_out = lists[(r + 1) & 1].as<int32_t>();
@@ -182,12 +194,23 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
       HJB_HIP(launch_trace(dim, grid, a, ra, s));
     }
     rounds += rpp;
-    HJB_HIP(hipMemcpyAsync(host.as<uint32_t>(), count.as<uint32_t>() + (r % 3), sizeof(uint32_t),
+    HJB_HIP(hipMemcpyAsync(hc + slot, count.as<uint32_t>() + (r % 3), sizeof(uint32_t),
                            hipMemcpyDeviceToHost, s));
-    HJB_HIP(hipStreamSynchronize(s));
-    if (host.as<uint32_t>()[0] == 0) break;
-    HJB_REQUIRE(rounds < 4000000, "colour transport did not settle");
+    HJB_HIP(hipEventRecord(pev[slot], s));
+  };
+  int cur = 0;
+  enqueue(cur);
+  while (true) {
+    enqueue(1 - cur);
+    HJB_HIP(hipEventSynchronize(pev[cur]));
+    if (hc[cur] == 0) break;
+    if (rounds >= 4000000) {
+      (void)hipStreamSynchronize(s);  // nothing in flight uses the buffers below
+      HJB_REQUIRE(false, "colour transport did not settle");
+    }
+    cur = 1 - cur;
   }
+  HJB_HIP(hipStreamSynchronize(s));
   DBuf unreached(sizeof(uint32_t) * 2);
   HJB_HIP(launch_fill_u32(unreached.as<uint32_t>(), 0u, 1, s));
   HJB_HIP(launch_labels(dim, a, H.labels.as<int16_t>(), unreached.as<uint32_t>(), s));
@@ -240,8 +263,9 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
 std::unique_ptr<CoarseHandle> coarse_solve_impl(const hjb_problem *coarse, double tol,
                                                 int32_t max_sweeps, hipStream_t s, int *status) {
   const double t0 = now_ms();
-  validate_problem(coarse, s);
-  auto P = upload_problem(*coarse, false, s);
+  std::vector<double> ctrl;
+  validate_problem(coarse, s, &ctrl);
+  auto P = upload_problem(*coarse, false, s, &ctrl);
   auto h = std::make_unique<CoarseHandle>();
   h->dim = P->dim;
   for (int d = 0; d < 3; ++d) h->n[d] = P->n[d];
@@ -307,9 +331,10 @@ int hjb_build_patches(const hjb_problem *fine, const hjb_coarse_t *coarse, hjb_s
     *out = nullptr;
     HJB_REQUIRE(coarse != nullptr, "coarse handle is NULL");
     hipStream_t s = as_stream(stream);
-    validate_problem(fine, s);
+    std::vector<double> ctrl;
+    validate_problem(fine, s, &ctrl);
     HJB_REQUIRE(fine->dim == coarse->dim, "fine and coarse dimensions differ");
-    auto F = upload_problem(*fine, false, s);
+    auto F = upload_problem(*fine, false, s, &ctrl);
     auto h = build_patches_impl(*F, *coarse, s);
     if (st) *st = h->st;
     auto* ph = new hjb_patches_s();
@@ -354,13 +379,14 @@ int hjb_solve_patches(const hjb_problem *fine, const hjb_patches_t *p, int32_t p
     HJB_REQUIRE(v_out != nullptr, "v_out is NULL");
     HJB_REQUIRE(precision == HJB_F32 || precision == HJB_F64, "precision must be HJB_F32 or HJB_F64");
     hipStream_t s = as_stream(stream);
-    validate_problem(fine, s);
+    std::vector<double> ctrl;
+    validate_problem(fine, s, &ctrl);
     HJB_REQUIRE(fine->dim == p->dim && fine->n[0] == p->n[0] && fine->n[1] == p->n[1] &&
                     fine->n[2] == p->n[2],
                 "problem grid does not match the patches handle");
     HJB_REQUIRE(fine->n_parts == p->n_parts, "n_parts does not match the patches handle");
     const bool fp64 = precision == HJB_F64;
-    auto P = upload_problem(*fine, !fp64, s);
+    auto P = upload_problem(*fine, !fp64, s, &ctrl);
     const int16_t *code = p->code.as<int16_t>();
     DBuf selcode, sel;
     if (opts && opts->patch_select) {
@@ -384,9 +410,10 @@ int hjb_solve_global(const hjb_problem *fine, int32_t precision, double tol, int
     HJB_REQUIRE(v_out != nullptr, "v_out is NULL");
     HJB_REQUIRE(precision == HJB_F32 || precision == HJB_F64, "precision must be HJB_F32 or HJB_F64");
     hipStream_t s = as_stream(stream);
-    validate_problem(fine, s);
+    std::vector<double> ctrl;
+    validate_problem(fine, s, &ctrl);
     const bool fp64 = precision == HJB_F64;
-    auto P = upload_problem(*fine, !fp64, s);
+    auto P = upload_problem(*fine, !fp64, s, &ctrl);
     DBuf code(P->N * sizeof(int16_t));
     HJB_HIP(launch_make_code(P->tp, nullptr, nullptr, P->N, code.as<int16_t>(), s));
     const int sched = opts ? opts->schedule : HJB_SCHED_TILED;

@@ -65,20 +65,23 @@ struct ProblemCopy {
 };
 
 SweepShape engine_shape(int dim, bool fp64, const hjb_solve_opts *opts) {
+  HJB_REQUIRE(!opts || opts->schedule != HJB_SCHED_ASYNC,
+              "batches and the server run in rounds (HJB_SCHED_ASYNC is for single solves)");
   return make_config(dim, fp64, opts, 0.0, 0).shape;
 }
 
 std::unique_ptr<Prepared> prepare(const hjb_problem *fine, const hjb_problem *coarse, bool fp64,
                                   const hjb_solve_opts *opts, hipStream_t s) {
   const double t0 = now_ms();
-  validate_problem(fine, s);
+  std::vector<double> ctrl;
+  validate_problem(fine, s, &ctrl);
   HJB_REQUIRE(coarse && coarse->dim == fine->dim, "coarse problem missing or of another dimension");
   int cst = HJB_OK;
   auto C = coarse_solve_impl(coarse, 0.0, 0, s, &cst);
   HJB_REQUIRE(cst == HJB_OK, "coarse solve did not converge");
   auto pr = std::make_unique<Prepared>();
   pr->dim = fine->dim;
-  pr->P = upload_problem(*fine, !fp64, s);
+  pr->P = upload_problem(*fine, !fp64, s, &ctrl);
   pr->patches = build_patches_impl(*pr->P, *C, s);
   const size_t N = pr->P->N;
   pr->v.reset(N * (fp64 ? sizeof(double) : sizeof(float)));

@@ -172,11 +172,23 @@ hipError_t launch_trace_init(int dim, const TraceArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-__device__ __forceinline__ void queue_tile(const RoundArgs &ra, int item) {
-  if (atomicCAS(&ra.flags_out[item], 0u, 1u) == 0u) {
-    const uint32_t idx = atomicAdd(&ra.count[(ra.round + 1) % 3], 1u);
-    ra.list_out[idx] = item;
+// One colour update from the corner values of the foot cell (x fastest):
+// beta times the nested linear interpolation, colours below the floor to 0.
+template <int DIM>
+__device__ __forceinline__ double colour_step(const double *c, double t0, double t1, double t2,
+                                              double beta) {
+  const double r0 = Ar<double>::lin(t0, c[0], c[1]);
+  const double r1 = Ar<double>::lin(t0, c[2], c[3]);
+  double I = Ar<double>::lin(t1, r0, r1);
+  if (DIM == 3) {
+    const double q0 = Ar<double>::lin(t0, c[4], c[5]);
+    const double q1 = Ar<double>::lin(t0, c[6], c[7]);
+    const double I1 = Ar<double>::lin(t1, q0, q1);
+    I = Ar<double>::lin(t2, I, I1);
   }
+  I = beta * I;
+  if (I < kColourFloor) I = 0.0;
+  return I;
 }
 
 template <int DIM, int TX, int TY, int TZ, int NT, int CL>
@@ -309,18 +321,19 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
           for (int f = 0; f < CL; ++f) {
             if (f >= nf) break;
             const double *sp = s_phi + f * LN;
-            double r0 = Ar<double>::lin(t0[j], sp[o], sp[o + 1]);
-            double r1 = Ar<double>::lin(t0[j], sp[o + LX], sp[o + LX + 1]);
-            double I = Ar<double>::lin(t1[j], r0, r1);
+            double c[8];
+            c[0] = sp[o];
+            c[1] = sp[o + 1];
+            c[2] = sp[o + LX];
+            c[3] = sp[o + LX + 1];
             if (DIM == 3) {
               const int oz = o + LX * LY;
-              double q0 = Ar<double>::lin(t0[j], sp[oz], sp[oz + 1]);
-              double q1 = Ar<double>::lin(t0[j], sp[oz + LX], sp[oz + LX + 1]);
-              double I1 = Ar<double>::lin(t1[j], q0, q1);
-              I = Ar<double>::lin(t2[j], I, I1);
+              c[4] = sp[oz];
+              c[5] = sp[oz + 1];
+              c[6] = sp[oz + LX];
+              c[7] = sp[oz + LX + 1];
             }
-            I = a.beta * I;
-            if (I < kColourFloor) I = 0.0;
+            const double I = colour_step<DIM>(c, t0[j], t1[j], t2[j], a.beta);
             if (I > sp[own[j]]) {
               s_phi[f * LN + own[j]] = I;
               ch = 1;
@@ -414,27 +427,38 @@ hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &
   return hipGetLastError();
 }
 
-// Queue, for round 0, every tile within reach of a target node.
-__global__ void k_trace_seed(TraceArgs a, int tx, int ty, int tz, RoundArgs ra) {
-  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= a.N) return;
-  if (a.target_part[g] < 0) return;
-  const int x = (int)(g % a.n[0]), y = (int)((g / a.n[0]) % a.n[1]);
-  const int z = (int)(g / ((size_t)a.n[0] * a.n[1]));
-  const int dz0 = a.n[2] > 1 ? -1 : 0, dz1 = a.n[2] > 1 ? 1 : 0;
-  for (int dz = dz0; dz <= dz1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int X = x + dx * HALO, Y = y + dy * HALO, Z = z + dz * HALO;
-        if (X < 0 || Y < 0 || Z < 0 || X >= a.n[0] || Y >= a.n[1] || Z >= a.n[2]) continue;
-        queue_tile(ra, X / tx + a.ntile[0] * (Y / ty + a.ntile[1] * (Z / tz)));
-      }
+// Queue, for round 0, every tile next to (or holding) a tile with a target
+// node: one thread per tile reads the part masks of its neighbourhood.
+__global__ void k_trace_seed(TraceArgs a, RoundArgs ra) {
+  const int ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int q = -1;
+  if (t < ntiles) {
+    const int tx = t % a.ntile[0], ty = (t / a.ntile[0]) % a.ntile[1];
+    const int tz = t / (a.ntile[0] * a.ntile[1]);
+    const int dz0 = a.ntile[2] > 1 ? -1 : 0, dz1 = a.ntile[2] > 1 ? 1 : 0;
+    bool near = false;
+    for (int dz = dz0; dz <= dz1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int x = tx + dx, y = ty + dy, z = tz + dz;
+          if (x < 0 || y < 0 || z < 0 || x >= a.ntile[0] || y >= a.ntile[1] || z >= a.ntile[2])
+            continue;
+          const size_t nb = (size_t)(x + a.ntile[0] * (y + a.ntile[1] * z));
+          for (int w = 0; w < a.words; ++w) near = near || a.masks[nb * a.words + w] != 0u;
+        }
+    if (near) {
+      ra.flags_out[t] = 1u;
+      q = t;
+    }
+  }
+  queue_items(ra, q, nullptr);
 }
 
 hipError_t launch_trace_seed(int dim, const TraceArgs &a, const RoundArgs &ra, hipStream_t s) {
-  const SweepShape sh = trace_shape(dim);
-  hipLaunchKernelGGL(k_trace_seed, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, sh.tx,
-                     sh.ty, sh.tz, ra);
+  (void)dim;
+  const int ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
+  hipLaunchKernelGGL(k_trace_seed, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, a, ra);
   return hipGetLastError();
 }
 

@@ -165,6 +165,140 @@ __device__ __forceinline__ void queue_items(const RoundArgs &ra, int it, uint32_
   }
 }
 
+// ---------------------------------------------------------------- async queue
+//
+// Device-scope atomics order the queue; values exchanged between workgroups
+// (which may run on different XCDs, each with its own L2) are read and
+// written with device-scope coherent loads and stores, and a workgroup
+// waits for its stores to complete before it queues anyone.  (Fences at
+// device scope would write back and invalidate a whole L2 per item.)
+
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dev(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until this wave's vector memory operations (stores included) have
+// completed: s_waitcnt vmcnt(0), other counters untouched.
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+enum : uint32_t { kQIdle = 0u, kQQueued = 1u, kQRunning = 2u, kQRerun = 3u };
+enum : uint32_t { kAbortIdle = 1u, kAbortSlot = 2u, kAbortState = 3u, kAbortPush = 4u };
+
+__device__ __forceinline__ void q_abort(const AsyncQ &q, uint32_t code) {
+  atomicCAS(&q.ctr[3], 0u, code);
+}
+
+// Ring slot of ticket t: an odd multiplier permutes the ring, so that
+// consecutive tickets (and the workgroups waiting on them) fall on
+// different cache lines.
+__device__ __forceinline__ uint32_t q_slot(const AsyncQ &q, uint32_t t) {
+  return (t * 0x9E3779B1u) & q.mask;
+}
+
+// Appends an item whose state was just set to queued.  `pending` grows
+// first, so it never reads 0 while the item is queued.
+__device__ __forceinline__ void q_enqueue(const AsyncQ &q, int it) {
+  atomicAdd(&q.ctr[2], 1u);
+  const uint32_t t = atomicAdd(&q.ctr[1], 1u);
+  int32_t *slot = &q.ring[q_slot(q, t)];
+  // the slot's previous ticket (t - ring size) was taken long ago; wait in
+  // case its holder has not emptied it yet
+  for (unsigned spins = 0; ld_dev(slot) >= 0; ++spins) {
+    if (spins > (1u << 20)) {
+      q_abort(q, kAbortSlot);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  st_dev(slot, (int32_t)it);
+}
+
+// Requests a (re)run of `it`: queued if idle, marked to run again if running.
+__device__ __forceinline__ void q_push(const AsyncQ &q, int it) {
+  for (int tries = 0; tries < 4096; ++tries) {
+    const uint32_t st = ld_dev(&q.state[it]);
+    if (st == kQQueued || st == kQRerun) return;
+    if (st == kQIdle) {
+      if (atomicCAS(&q.state[it], kQIdle, kQQueued) == kQIdle) {
+        q_enqueue(q, it);
+        return;
+      }
+    } else if (st == kQRunning) {
+      if (atomicCAS(&q.state[it], kQRunning, kQRerun) == kQRunning) return;
+    } else {
+      q_abort(q, kAbortState);
+      return;
+    }
+  }
+  q_abort(q, kAbortPush);
+}
+
+// Ends a run of `it` (thread 0, after the item's pushes): idle, or queued
+// again when a neighbour asked for it meanwhile or `again` is set.
+__device__ __forceinline__ void q_finish(const AsyncQ &q, int it, bool again) {
+  for (int tries = 0; tries < 4096; ++tries) {
+    const uint32_t st = ld_dev(&q.state[it]);
+    if (st != kQRunning && st != kQRerun) {
+      q_abort(q, kAbortState);
+      break;
+    }
+    if (st == kQRerun || again) {
+      if (atomicCAS(&q.state[it], st, kQQueued) == st) {
+        q_enqueue(q, it);
+        break;
+      }
+    } else if (atomicCAS(&q.state[it], kQRunning, kQIdle) == kQRunning) {
+      break;
+    }
+    if (tries == 4095) q_abort(q, kAbortPush);
+  }
+  atomicSub(&q.ctr[2], 1u);
+}
+
+// One attempt to take an item (thread 0).  A workgroup draws a ticket once
+// (fetch-and-add on the head) and then waits on that ticket's slot only.
+// Returns the item, -1 when the slot is still empty (after a sleep), -2
+// when the work is done (no item queued or running) or the launch aborted.
+// `idle` counts consecutive empty attempts; past the limit the launch
+// aborts instead of waiting for ever.
+__device__ __forceinline__ int q_pop(const AsyncQ &q, int64_t &ticket, unsigned &idle) {
+  constexpr unsigned kIdleLimit = 1u << 23;  // about 30 s at the longest back-off
+  if (ticket < 0) ticket = (int64_t)atomicAdd(&q.ctr[0], 1u);
+  int32_t *slot = &q.ring[q_slot(q, (uint32_t)ticket)];
+  const int32_t it = ld_dev(slot);
+  if (it >= 0) {
+    st_dev(slot, (int32_t)-1);
+    ticket = -1;
+    if (atomicCAS(&q.state[it], kQQueued, kQRunning) != kQQueued) {
+      q_abort(q, kAbortState);
+      return -2;
+    }
+    // no cache invalidation: the values the item reads from other
+    // workgroups are loaded at device scope
+    idle = 0;
+    return it;
+  }
+  ++idle;
+  // the shared counters are read on every 8th empty poll only
+  if ((idle & 7u) == 0u) {
+    if (ld_dev(&q.ctr[3]) != 0u || ld_dev(&q.ctr[2]) == 0u) return -2;
+  }
+  if (idle > kIdleLimit) {
+    q_abort(q, kAbortIdle);
+    return -2;
+  }
+  // back-off: short at first, then about 3.4 us between polls
+  if (idle < 16) __builtin_amdgcn_s_sleep(4);
+  else if (idle < 64) __builtin_amdgcn_s_sleep(32);
+  else __builtin_amdgcn_s_sleep(127);
+  return -1;
+}
+
 // Interpolate a global-memory grid at the foot point, ghost 1 outside the
 // box (every box node active).  Same nesting and the same per-precision
 // foot-point evaluation as the LDS variants: FP32 takes y = d + 2, FP64

@@ -87,6 +87,19 @@ struct RoundArgs {
   double tol;                 // a node "changes" when it decreases by more than tol
 };
 
+// Work queue of the asynchronous schedule: a ring of item ids filled by
+// the workgroups that change a neighbour's halo and drained by every
+// workgroup of one persistent launch.  An item is never queued twice nor run
+// by two workgroups at once (per-item state), and the launch ends when no
+// item is queued or running (`pending`).
+struct AsyncQ {
+  int32_t *ring;    // [mask + 1] item ids, -1 in an empty slot
+  uint32_t mask;    // ring size - 1 (a power of two above the item count)
+  uint32_t *state;  // [items] 0 idle, 1 queued, 2 running, 3 running and queued again
+  uint32_t *sides;  // [items] tile sides whose halo changed since the item started
+  uint32_t *ctr;    // [0] head, [1] tail, [2] pending, [3] abort code (0 = none)
+};
+
 // Trace (colour transport) engine arguments.
 struct TraceArgs {
   int32_t n[3];
@@ -115,6 +128,9 @@ struct SweepShape {
   int nt = 256;  // workgroup size
 };
 bool sweep_shape_supported(int dim, int tx, int ty, int tz, int nt);
+hipError_t launch_sweep_async(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
+                              const Item *items, const RoundArgs &ra, const AsyncQ &q,
+                              hipStream_t s);
 hipError_t launch_sweep(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
                         const Item *items, const RoundArgs &ra, hipStream_t s);
 hipError_t launch_jacobi(bool fp64, int dim, const DevProblem *prob_dev, size_t N, const void *vin,

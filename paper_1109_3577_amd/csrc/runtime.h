@@ -38,6 +38,11 @@ void set_last_error(const std::string &s);
     if (!(cond)) ::hjb::throw_error(HJB_EINVAL, __VA_ARGS__); \
   } while (0)
 
+#define HJB_REQUIRE_CODE(cond, code, ...)            \
+  do {                                                \
+    if (!(cond)) ::hjb::throw_error((code), __VA_ARGS__); \
+  } while (0)
+
 // Runs f() and converts exceptions into a status code + last error.
 template <typename F>
 int guarded(F &&f) {
@@ -122,15 +127,18 @@ struct ProblemDev {
   const int16_t *tp = nullptr;
   // FP32 copies (s_d folded into controls and drift)
   DBuf ctrl32, speed32, drift32;
-  std::vector<double> ctrl_host;  // controls on the host
-  std::vector<double> ctrl64_pad;  // host staging of the padded tables
-  std::vector<float> ctrl32_pad;
+  std::vector<double> ctrl_host;         // controls on the host
+  std::unique_ptr<PinnedBuf> ctrl_stage;  // pinned staging of the padded tables
 };
 
 // Checks every documented requirement of an hjb_problem; throws HJB_EINVAL.
-void validate_problem(const hjb_problem *P, hipStream_t s);
-// Uploads / borrows the inputs; builds FP32 copies when need32.
-std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hipStream_t s);
+// ctrl_out (optional) receives the controls as read for the checks.
+void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *ctrl_out = nullptr);
+// Uploads / borrows the inputs; builds FP32 copies when need32.  `ctrl` is
+// the host copy of the controls from validate_problem (read again if null).
+// Work is enqueued on s; the caller synchronises before the inputs go.
+std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hipStream_t s,
+                                           const std::vector<double> *ctrl = nullptr);
 
 // ---------------------------------------------------------------- engine
 
@@ -141,6 +149,7 @@ struct SolveConfig {
   int rounds_per_poll = 16;
   bool use_graph = false;
   bool time_kernels = false;
+  bool async = false;  // HJB_SCHED_ASYNC: one persistent launch, device work queue
   double tol = 0.0;
   long long max_rounds = 1000000;
 };
@@ -185,6 +194,10 @@ class SweepEngine {
   void begin(const std::vector<int32_t> *seeds = nullptr);
   // Runs rounds until no item is queued or the round cap (HJB_OK / HJB_ENOCONV).
   int run();
+  // One persistent launch draining a device work queue (no rounds, no cap).
+  int run_async();
+  // Whether the configuration asks for run_async (HJB_SCHED_ASYNC).
+  bool async_ok() const;
   // Enqueues `rounds` rounds, waits, returns the length of the next queue.
   int run_rounds(int rounds);
   // The next round's queue (global ids) and per-problem queued counts.
@@ -201,6 +214,8 @@ class SweepEngine {
 
  private:
   void launch_round(uint32_t r);
+  // Enqueues `rounds` rounds without waiting.
+  void launch_block(int rounds);
   SolveConfig cfg_;
   hipStream_t s_;
   std::vector<DevProblem> dps_;
@@ -209,6 +224,9 @@ class SweepEngine {
   std::vector<Item> items_h_;
   DBuf probs_d_, items_d_, lists_[2], flags_[2], count_, counters_;
   std::unique_ptr<PinnedBuf> host_;
+  hipEvent_t poll_ev_[2] = {nullptr, nullptr};
+  std::vector<int32_t> seeds_;
+  bool async_ran_ = false;
   long long rounds_ = 0;
   uint32_t r_ = 0;
   double kernel_ms_ = 0.0;

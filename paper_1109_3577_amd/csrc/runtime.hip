@@ -150,18 +150,49 @@ void DBuf::release() {
   bytes_ = cap_ = 0;
 }
 
+// Pinned host blocks are kept for reuse (allocating and freeing pinned
+// memory is slow and can synchronise the device).
+namespace {
+struct PinnedPool {
+  std::mutex m;
+  std::multimap<size_t, void *> free_blocks;
+  std::unordered_map<void *, size_t> size_of;
+};
+PinnedPool &pinned_pool() {
+  static PinnedPool *P = new PinnedPool();  // lives until the process ends
+  return *P;
+}
+}  // namespace
+
 PinnedBuf::PinnedBuf(size_t bytes) {
-  HJB_HIP(hipHostMalloc(&p_, std::max<size_t>(bytes, 64), hipHostMallocDefault));
+  size_t want = 64;
+  while (want < bytes) want *= 2;
+  PinnedPool &P = pinned_pool();
+  {
+    std::lock_guard<std::mutex> g(P.m);
+    auto it = P.free_blocks.lower_bound(want);
+    if (it != P.free_blocks.end() && it->first <= 4 * want) {
+      p_ = it->second;
+      P.free_blocks.erase(it);
+      return;
+    }
+  }
+  HJB_HIP(hipHostMalloc(&p_, want, hipHostMallocDefault));
+  std::lock_guard<std::mutex> g(P.m);
+  P.size_of[p_] = want;
 }
 PinnedBuf::~PinnedBuf() {
-  if (p_) (void)hipHostFree(p_);
+  if (!p_) return;
+  PinnedPool &P = pinned_pool();
+  std::lock_guard<std::mutex> g(P.m);
+  P.free_blocks.insert({P.size_of[p_], p_});
 }
 
 // ---------------------------------------------------------------- validation
 
 static constexpr double kReachLimit = 1.999;  // |displacement| per axis, cells
 
-void validate_problem(const hjb_problem *P, hipStream_t s) {
+void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *ctrl_out) {
   HJB_REQUIRE(P != nullptr, "problem is NULL");
   HJB_REQUIRE(P->dim == 2 || P->dim == 3, "dim must be 2 or 3 (got %d)", P->dim);
   for (int d = 0; d < P->dim; ++d)
@@ -228,13 +259,15 @@ void validate_problem(const hjb_problem *P, hipStream_t s) {
     std::memcpy(&t, &h[3], sizeof(double));
     maxpart = (int)t - 2;
   }
+  if (ctrl_out) *ctrl_out = std::move(ctrl);
   for (int d = 0; d < dim; ++d)
     HJB_REQUIRE(reach[d] <= kReachLimit,
                 "foot points reach %.4f cells on axis %d; the kernels support < 2 (halo)", reach[d], d);
   HJB_REQUIRE(maxpart < P->n_parts, "target_part holds part %d >= n_parts %d", maxpart, P->n_parts);
 }
 
-std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hipStream_t s) {
+std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hipStream_t s,
+                                           const std::vector<double> *ctrl) {
   auto D = std::make_unique<ProblemDev>();
   D->dim = P.dim;
   for (int d = 0; d < 3; ++d) {
@@ -264,8 +297,12 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
       D->drift64 = D->own_drift64.as<double>();
     }
   } else {
-    HJB_HIP(hipMemcpyAsync(D->ctrl_host.data(), P.controls, cb, hipMemcpyDeviceToHost, s));
-    HJB_HIP(hipStreamSynchronize(s));
+    if (ctrl && ctrl->size() == D->ctrl_host.size()) {
+      D->ctrl_host = *ctrl;  // the validated host copy
+    } else {
+      HJB_HIP(hipMemcpyAsync(D->ctrl_host.data(), P.controls, cb, hipMemcpyDeviceToHost, s));
+      HJB_HIP(hipStreamSynchronize(s));
+    }
     D->speed64 = P.speed;
     D->drift64 = P.drift;
     D->tp = P.target_part;
@@ -275,24 +312,27 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
   // controls four at a time and fetches the next group ahead, and a repeated
   // control leaves the minimum over the set unchanged.  FP32 rows carry
   // s_d * a_kd rounded to FP32.
+  // The tables are staged in pinned memory owned by the handle, so the
+  // copies stay asynchronous; every entry point synchronises its stream
+  // before it returns.
   const int nc = P.n_controls, dim = P.dim;
   const int rows = ((nc + 3) & ~3) + 4;
-  D->ctrl64_pad.resize((size_t)rows * dim);
-  D->ctrl32_pad.resize((size_t)rows * dim);
+  const size_t b64 = (size_t)rows * dim * sizeof(double), b32 = (size_t)rows * dim * sizeof(float);
+  D->ctrl_stage = std::make_unique<PinnedBuf>(b64 + b32);
+  double *pad64 = D->ctrl_stage->as<double>();
+  float *pad32 = reinterpret_cast<float *>(D->ctrl_stage->as<char>() + b64);
   for (int k = 0; k < rows; ++k)
     for (int d = 0; d < dim; ++d) {
       const double a = D->ctrl_host[(size_t)(k < nc ? k : nc - 1) * dim + d];
-      D->ctrl64_pad[(size_t)k * dim + d] = a;
-      D->ctrl32_pad[(size_t)k * dim + d] = (float)(P.step[d] * a);
+      pad64[(size_t)k * dim + d] = a;
+      pad32[(size_t)k * dim + d] = (float)(P.step[d] * a);
     }
-  D->own_ctrl64.reset(D->ctrl64_pad.size() * sizeof(double));
-  HJB_HIP(hipMemcpyAsync(D->own_ctrl64.get(), D->ctrl64_pad.data(),
-                         D->ctrl64_pad.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  D->own_ctrl64.reset(b64);
+  HJB_HIP(hipMemcpyAsync(D->own_ctrl64.get(), pad64, b64, hipMemcpyHostToDevice, s));
   D->ctrl64 = D->own_ctrl64.as<double>();
   if (need32) {
-    D->ctrl32.reset(D->ctrl32_pad.size() * sizeof(float));
-    HJB_HIP(hipMemcpyAsync(D->ctrl32.get(), D->ctrl32_pad.data(),
-                           D->ctrl32_pad.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    D->ctrl32.reset(b32);
+    HJB_HIP(hipMemcpyAsync(D->ctrl32.get(), pad32, b32, hipMemcpyHostToDevice, s));
     D->speed32.reset(N * sizeof(float));
     HJB_HIP(launch_f64_to_f32(D->speed64, D->speed32.as<float>(), N, s));
     if (P.drift) {
@@ -300,7 +340,6 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
       HJB_HIP(launch_scaled_f32(D->drift64, D->drift32.as<float>(), N, P.dim, P.step, s));
     }
   }
-  HJB_HIP(hipStreamSynchronize(s));
   return D;
 }
 
@@ -346,8 +385,12 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
     if (opts->rounds_per_poll > 0) c.rounds_per_poll = opts->rounds_per_poll;
     c.use_graph = opts->use_graph != 0;
     c.time_kernels = opts->time_kernels != 0;
-    HJB_REQUIRE(opts->schedule == HJB_SCHED_TILED || opts->schedule == HJB_SCHED_JACOBI,
+    HJB_REQUIRE(opts->schedule == HJB_SCHED_TILED || opts->schedule == HJB_SCHED_JACOBI ||
+                    opts->schedule == HJB_SCHED_ASYNC,
                 "unknown schedule %d", opts->schedule);
+    c.async = opts->schedule == HJB_SCHED_ASYNC;
+    HJB_REQUIRE(!c.async || max_sweeps <= 0, "HJB_SCHED_ASYNC takes no sweep cap (max_sweeps 0)");
+    HJB_REQUIRE(!c.async || !c.use_graph, "HJB_SCHED_ASYNC has no rounds to replay as a graph");
   }
   if (c.use_graph) c.rounds_per_poll = std::max(6, (c.rounds_per_poll + 5) / 6 * 6);
   return c;
@@ -412,6 +455,8 @@ SweepEngine::SweepEngine(const SolveConfig &cfg, hipStream_t s) : cfg_(cfg), s_(
 SweepEngine::~SweepEngine() {
   if (graph_) (void)hipGraphExecDestroy(graph_);
   for (auto e : events_) (void)hipEventDestroy(e);
+  for (auto e : poll_ev_)
+    if (e) (void)hipEventDestroy(e);
 }
 
 int SweepEngine::add_problem(const ProblemDev &P, const int16_t *code, const ProblemItems *items,
@@ -484,6 +529,7 @@ void SweepEngine::begin(const std::vector<int32_t> *seeds) {
     for (size_t i = 0; i < np; ++i)
       for (int32_t l : pitems_[i]->seeds) sd.push_back(bases_[i] + l);
   }
+  seeds_ = sd;
   // per-problem queued counts of the first round
   std::vector<uint32_t> pa(np, 0);
   for (int32_t g : sd) pa[items_h_[g].prob]++;
@@ -521,7 +567,7 @@ void SweepEngine::launch_round(uint32_t r) {
                        items_d_.as<Item>(), ra, s_));
 }
 
-int SweepEngine::run_rounds(int rounds) {
+void SweepEngine::launch_block(int rounds) {
   const bool timing = cfg_.time_kernels;
   // (capture is not possible on the legacy null stream: rounds are then
   // launched one by one)
@@ -573,6 +619,10 @@ int SweepEngine::run_rounds(int rounds) {
     }
   }
   rounds_ += rounds;
+}
+
+int SweepEngine::run_rounds(int rounds) {
+  launch_block(rounds);
   uint32_t *h = host_->as<uint32_t>();
   HJB_HIP(hipMemcpyAsync(h, count_.as<uint32_t>() + (r_ % 3), sizeof(uint32_t),
                          hipMemcpyDeviceToHost, s_));
@@ -581,16 +631,37 @@ int SweepEngine::run_rounds(int rounds) {
 }
 
 int SweepEngine::run() {
+  // Pipelined polling: the next block of rounds is enqueued before the host
+  // waits for the queue count that the previous block left, so the device
+  // never idles on a poll.  Once the queue is empty the block in flight
+  // runs empty rounds only (a few microseconds each).
+  for (int i = 0; i < 2; ++i)
+    if (!poll_ev_[i]) HJB_HIP(hipEventCreateWithFlags(&poll_ev_[i], hipEventDisableTiming));
+  uint32_t *h = host_->as<uint32_t>();
+  auto enqueue = [&](int slot) -> bool {
+    const long long left = cfg_.max_rounds - rounds_;
+    if (left <= 0) return false;
+    launch_block((int)std::min<long long>(cfg_.rounds_per_poll, left));
+    HJB_HIP(hipMemcpyAsync(h + slot, count_.as<uint32_t>() + (r_ % 3), sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s_));
+    HJB_HIP(hipEventRecord(poll_ev_[slot], s_));
+    return true;
+  };
   int status = HJB_OK;
-  while (true) {
-    const int n = (int)std::min<long long>(cfg_.rounds_per_poll, cfg_.max_rounds - rounds_);
-    const int q = run_rounds(std::max(n, 1));
-    if (q == 0) break;
-    if (rounds_ >= cfg_.max_rounds) {
-      status = HJB_ENOCONV;
-      break;
+  int cur = 0;
+  if (enqueue(cur)) {
+    while (true) {
+      const bool next = enqueue(1 - cur);
+      HJB_HIP(hipEventSynchronize(poll_ev_[cur]));
+      if (h[cur] == 0) break;
+      if (!next) {
+        status = HJB_ENOCONV;
+        break;
+      }
+      cur = 1 - cur;
     }
   }
+  HJB_HIP(hipStreamSynchronize(s_));
   if (cfg_.time_kernels && kernel_blocks_ > 0) {
     kernel_ms_ = 0.0;
     for (int i = 0; i < kernel_blocks_; ++i) {
@@ -612,6 +683,84 @@ std::vector<int32_t> SweepEngine::queue_now() {
                            hipMemcpyDeviceToHost, s_));
   HJB_HIP(hipStreamSynchronize(s_));
   return q;
+}
+
+bool SweepEngine::async_ok() const { return cfg_.async; }
+
+int SweepEngine::run_async() {
+  const size_t ni = items_h_.size();
+  // about four workgroups of 256 threads per CU stay resident
+  const int per_cu = std::max(1, 1024 / cfg_.shape.nt);
+  const int grid = (int)std::max<size_t>(1, std::min<size_t>(ni, (size_t)256 * per_cu));
+  // tickets in use never exceed the queued items plus one per workgroup
+  uint32_t cap = 2;
+  while (cap < 2 * (ni + (size_t)grid) + 2) cap <<= 1;
+  DBuf ring(cap * sizeof(int32_t)), state(ni * sizeof(uint32_t)), sides(ni * sizeof(uint32_t)),
+      ctr(4 * sizeof(uint32_t));
+  HJB_HIP(launch_fill_u32(sides.as<uint32_t>(), 0u, ni, s_));
+  // seeds: queued, in the first ring slots
+  const size_t ns = seeds_.size();
+  PinnedBuf stage((ni + 4) * sizeof(uint32_t));
+  uint32_t *st = stage.as<uint32_t>();
+  std::memset(st, 0, ni * sizeof(uint32_t));
+  for (int32_t g : seeds_) st[g] = 1u;  // queued
+  // seeds hold tickets 0 .. ns-1; the ring is written whole
+  PinnedBuf rstage((size_t)cap * sizeof(int32_t));
+  int32_t *rg = rstage.as<int32_t>();
+  for (uint32_t i = 0; i < cap; ++i) rg[i] = -1;
+  for (size_t i = 0; i < ns; ++i) rg[(uint32_t(i) * 0x9E3779B1u) & (cap - 1)] = seeds_[i];
+  uint32_t *c4 = st + ni;
+  c4[0] = 0u;
+  c4[1] = (uint32_t)ns;
+  c4[2] = (uint32_t)ns;
+  c4[3] = 0u;
+  HJB_HIP(hipMemcpyAsync(state.get(), st, ni * sizeof(uint32_t), hipMemcpyHostToDevice, s_));
+  HJB_HIP(hipMemcpyAsync(ring.get(), rg, (size_t)cap * sizeof(int32_t), hipMemcpyHostToDevice, s_));
+  HJB_HIP(hipMemcpyAsync(ctr.get(), c4, 4 * sizeof(uint32_t), hipMemcpyHostToDevice, s_));
+  AsyncQ q;
+  q.ring = ring.as<int32_t>();
+  q.mask = cap - 1;
+  q.state = state.as<uint32_t>();
+  q.sides = sides.as<uint32_t>();
+  q.ctr = ctr.as<uint32_t>();
+  RoundArgs ra;
+  std::memset(&ra, 0, sizeof ra);
+  ra.round = 0;
+  ra.inner_sweeps = cfg_.inner_sweeps;
+  ra.nprob = (int)dps_.size();
+  ra.tol = cfg_.tol;
+  const bool timing = cfg_.time_kernels;
+  if (timing) {
+    while (events_.size() < (size_t)(2 * (kernel_blocks_ + 1))) {
+      hipEvent_t e;
+      HJB_HIP(hipEventCreate(&e));
+      events_.push_back(e);
+    }
+    HJB_HIP(hipEventRecord(events_[2 * kernel_blocks_], s_));
+  }
+  HJB_HIP(launch_sweep_async(cfg_.fp64, cfg_.shape, grid, probs_d_.as<DevProblem>(),
+                             items_d_.as<Item>(), ra, q, s_));
+  if (timing) {
+    HJB_HIP(hipEventRecord(events_[2 * kernel_blocks_ + 1], s_));
+    ++kernel_blocks_;
+    kernel_launches_ += 1;
+  }
+  uint32_t *h = host_->as<uint32_t>();
+  HJB_HIP(hipMemcpyAsync(h, ctr.get(), 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s_));
+  HJB_HIP(hipStreamSynchronize(s_));
+  rounds_ += 1;
+  async_ran_ = true;
+  if (timing) {
+    kernel_ms_ = 0.0;
+    for (int i = 0; i < kernel_blocks_; ++i) {
+      float ms = 0.0f;
+      HJB_HIP(hipEventElapsedTime(&ms, events_[2 * i], events_[2 * i + 1]));
+      kernel_ms_ += ms;
+    }
+  }
+  HJB_REQUIRE_CODE(h[3] == 0u && h[2] == 0u, HJB_EDEVICE,
+                   "asynchronous sweep stopped with work left (code %u, %u pending)", h[3], h[2]);
+  return HJB_OK;
 }
 
 std::vector<uint32_t> SweepEngine::pactive_now() {
@@ -645,7 +794,8 @@ std::vector<EngineResult> SweepEngine::results() {
     for (int k = 0; k < kSlots; ++k) rb = std::max(rb, c[((r_ + 2) % 3) * kSlots + k]);
     double rd;
     std::memcpy(&rd, &rb, sizeof rd);
-    out[i].residual = rd;
+    // the asynchronous schedule has no rounds: it ends with no item queued
+    out[i].residual = async_ran_ ? 0.0 : rd;
     unsigned long long wn = 0, ir = 0;
     for (int k = 0; k < kSlots; ++k) {
       wn += c[3 * kSlots + 2 + k];

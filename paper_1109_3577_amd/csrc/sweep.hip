@@ -43,11 +43,31 @@ struct Brick {
   static constexpr int Z = DIM == 2 ? 1 : 4;
 };
 
-template <typename T, int DIM, int TX, int TY, int TZ, int NT, bool DRIFT>
-__device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item,
-                                           const RoundArgs &ra, T *s_v, int *s_int,
-                                           double *s_red, unsigned long long *s_wrk,
-                                           uint32_t *s_msk) {
+// Bricks on side (sx, sy, sz) of a tile of NBX x NBY x NBZ bricks: for each
+// axis, the first layer (s = -1), the last (s = +1) or all (s = 0).
+template <int NBX, int NBY, int NBZ>
+__device__ __forceinline__ uint32_t side_bricks(int sx, int sy, int sz) {
+  uint32_t m = 0u;
+#pragma unroll
+  for (int b = 0; b < NBX * NBY * NBZ; ++b) {
+    const int bx = b % NBX, by = (b / NBX) % NBY, bz = b / (NBX * NBY);
+    const bool in = (sx < 0 ? bx == 0 : sx > 0 ? bx == NBX - 1 : true) &&
+                    (sy < 0 ? by == 0 : sy > 0 ? by == NBY - 1 : true) &&
+                    (sz < 0 ? bz == 0 : sz > 0 ? bz == NBZ - 1 : true);
+    m |= in ? (1u << b) : 0u;
+  }
+  return m;
+}
+
+// One activation of a work item.  ASYNC: values are exchanged with other
+// workgroups of the same launch (device-scope loads and stores, a release
+// fence before the pushes) and neighbours go to the work queue; otherwise
+// to the next round's list.  Returns whether the tile settled.
+template <typename T, int DIM, int TX, int TY, int TZ, int NT, bool DRIFT, bool ASYNC>
+__device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item, int item_id,
+                                           uint32_t fl, const RoundArgs &ra, const AsyncQ &aq,
+                                           T *s_v, int *s_int, double *s_red,
+                                           unsigned long long *s_wrk, uint32_t *s_msk) {
   constexpr int LX = TX + 2 * HALO;
   constexpr int LY = TY + 2 * HALO;
   constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
@@ -88,7 +108,7 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
     if (inb) {
       const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0));
       const int cd = code[g];
-      const T vg = v[g];
+      const T vg = ASYNC ? ld_dev(&v[g]) : v[g];
       val = cd == CODE_TARGET ? T(0) : (cd == patch ? vg : T(1));
     }
     s_v[lx + LXS * (ly + LY * lz)] = val;
@@ -136,12 +156,27 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
       for (int q = 0; q < DIM; ++q) ww[j][q] = (DRIFT && act[j]) ? P.drift64[g * DIM + q] : 0.0;
     }
   }
+  // Bricks of the first sweep.  `fl` holds one bit per side of the tile
+  // whose halo a neighbour changed since this item last ran (bit of the
+  // centre: the item did not settle; no bit: first activation).  An item
+  // that settled is at its own fixed point except next to those sides, so
+  // only the bricks on them need the first sweep.
+  constexpr int CENTER = (DIM == 3) ? 13 : 4;
+  uint32_t first = ~0u;
+  if (fl != 0u && !(fl & (1u << CENTER))) {
+    first = 0u;
+    for (uint32_t f = fl; f; f &= f - 1u) {
+      const int d = __builtin_ctz(f);
+      const int sx = d % 3 - 1, sy = (d / 3) % 3 - 1, sz = d / 9 - 1;
+      first |= side_bricks<NBX, NBY, NBZ>(sx, sy, DIM == 3 ? sz : 0);
+    }
+  }
   // brick-change masks, three in rotation: sweep s reads the mask of sweep
   // s - 1, ORs its own into slot s % 3 and clears the slot of sweep s + 1
   if (tid == 0) {
     s_msk[0] = 0u;
     s_msk[1] = 0u;
-    s_msk[2] = ~0u;  // "changed before sweep 0": every brick is swept first
+    s_msk[2] = 0u;
   }
   __syncthreads();
 
@@ -164,7 +199,8 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
     for (int j = 0; j < NPT; ++j) {
       // Skip the brick when nothing within its reach changed in the last
       // sweep: its update would read the same values and change nothing.
-      if ((prev & nbm[j]) == 0u) continue;
+      const uint32_t bj = 1u << (wave + j * NW);
+      if (it == 0 ? (first & bj) == 0u : (prev & nbm[j]) == 0u) continue;
       upd += act[j] ? 1u : 0u;
       T mI = T(3);
       if constexpr (sizeof(T) == 4) {
@@ -226,7 +262,8 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
     if (act[j]) {
       const T nv = s_v[off[j]];
       if (nv < old[j]) {
-        v[gid[j]] = nv;
+        if (ASYNC) st_dev(&v[gid[j]], nv);
+        else v[gid[j]] = nv;
         const double dd = (double)old[j] - (double)nv;
         dmax = dd > dmax ? dd : dmax;
         big = old[j] - nv > tolT;
@@ -265,6 +302,11 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
       bz0 = min(bz0, oz0 + __builtin_ctz(zs)); bz1 = max(bz1, oz0 + 31 - __builtin_clz(zs));
     }
   }
+  // The value stores are device-scope (written through to the coherent
+  // level); each wave waits for its stores to complete, so after the
+  // barrier below every new value is visible device-wide before any
+  // neighbour is queued.
+  if (ASYNC) wait_stores();
   if (tid == 0) {
     s_int[0] = 1 << 30; s_int[1] = 1 << 30; s_int[2] = 1 << 30;
     s_int[3] = -1; s_int[4] = -1; s_int[5] = -1;
@@ -323,11 +365,24 @@ __device__ __forceinline__ void sweep_item(const DevProblem &P, const Item &item
         const int t2 = nx + P.ntile[0] * (ny + P.ntile[1] * nz);
         const int ntiles = P.ntile[0] * P.ntile[1] * P.ntile[2];
         const int l = P.item_map[(size_t)patch * ntiles + t2];
-        if (l >= 0 && atomicCAS(&ra.flags_out[P.item_base + l], 0u, 1u) == 0u) it2 = P.item_base + l;
+        // the receiver sees the change on its side (-dx, -dy, -dz); the
+        // first setter of any side queues the item
+        const uint32_t side = 1u << ((1 - dx) + 3 * (1 - dy) + 9 * (1 - dz));
+        if (ASYNC) {
+          // the item itself is queued again by its finish
+          if (l >= 0 && !(dx == 0 && dy == 0 && dz == 0)) {
+            atomicOr(&aq.sides[P.item_base + l], side);
+            q_push(aq, P.item_base + l);
+          }
+        } else if (l >= 0 && atomicOr(&ra.flags_out[P.item_base + l], side) == 0u) {
+          it2 = P.item_base + l;
+        }
       }
     }
-    queue_items(ra, it2, &P.pactive[(ra.round + 1) % 3]);
+    if (!ASYNC) queue_items(ra, it2, &P.pactive[(ra.round + 1) % 3]);
   }
+  (void)item_id;
+  return converged;
 }
 
 template <typename T, int DIM, int TX, int TY, int TZ, int NT>
@@ -356,12 +411,65 @@ k_sweep(const DevProblem *__restrict__ probs, const Item *__restrict__ items, Ro
     const int it = ra.list_in[li];
     const Item item = items[it];
     const DevProblem &P = probs[item.prob];
+    const uint32_t fl = ra.flags_in[it];
+    __syncthreads();  // every thread has read the flag before it is cleared
     if (threadIdx.x == 0) ra.flags_in[it] = 0u;
     if (P.has_drift)
-      sweep_item<T, DIM, TX, TY, TZ, NT, true>(P, item, ra, s_v, s_int, s_red, s_wrk, s_msk);
+      sweep_item<T, DIM, TX, TY, TZ, NT, true, false>(P, item, it, fl, ra, AsyncQ{}, s_v, s_int,
+                                                      s_red, s_wrk, s_msk);
     else
-      sweep_item<T, DIM, TX, TY, TZ, NT, false>(P, item, ra, s_v, s_int, s_red, s_wrk, s_msk);
+      sweep_item<T, DIM, TX, TY, TZ, NT, false, false>(P, item, it, fl, ra, AsyncQ{}, s_v, s_int,
+                                                       s_red, s_wrk, s_msk);
     __syncthreads();
+  }
+}
+
+// Asynchronous schedule: one persistent launch; every workgroup takes items
+// from the work queue until no item is queued or running.
+template <typename T, int DIM, int TX, int TY, int TZ, int NT>
+__global__ void __launch_bounds__(NT)
+k_sweep_async(const DevProblem *__restrict__ probs, const Item *__restrict__ items, RoundArgs ra,
+              AsyncQ q) {
+  constexpr int LX = TX + 2 * HALO;
+  constexpr int LY = TY + 2 * HALO;
+  constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
+  constexpr int LXS = lds_stride<T, DIM, LX>();
+  constexpr int CENTER = (DIM == 3) ? 13 : 4;
+  __shared__ T s_v[LXS * LY * LZ];
+  __shared__ int s_int[8];
+  __shared__ uint32_t s_msk[4];
+  __shared__ double s_red[NT / 64];
+  __shared__ unsigned long long s_wrk[NT / 64];
+  __shared__ int s_it;
+  __shared__ uint32_t s_fl;
+  unsigned idle = 0;
+  int64_t ticket = -1;
+  while (true) {
+    if (threadIdx.x == 0) {
+      const int it = q_pop(q, ticket, idle);
+      s_it = it;
+      s_fl = it >= 0 ? atomicExch(&q.sides[it], 0u) : 0u;
+    }
+    __syncthreads();
+    const int it = s_it;
+    const uint32_t fl = s_fl;
+    __syncthreads();
+    if (it == -2) break;
+    if (it < 0) continue;
+    const Item item = items[it];
+    const DevProblem &P = probs[item.prob];
+    bool conv;
+    if (P.has_drift)
+      conv = sweep_item<T, DIM, TX, TY, TZ, NT, true, true>(P, item, it, fl, ra, q, s_v, s_int,
+                                                             s_red, s_wrk, s_msk);
+    else
+      conv = sweep_item<T, DIM, TX, TY, TZ, NT, false, true>(P, item, it, fl, ra, q, s_v, s_int,
+                                                              s_red, s_wrk, s_msk);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (!conv) atomicOr(&q.sides[it], 1u << CENTER);
+      q_finish(q, it, !conv);
+    }
   }
 }
 
@@ -388,6 +496,24 @@ bool sweep_shape_supported(int dim, int tx, int ty, int tz, int nt) {
   HJB_SHAPES(HJB_CHECK_SHAPE)
 #undef HJB_CHECK_SHAPE
   return false;
+}
+
+hipError_t launch_sweep_async(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
+                              const Item *items, const RoundArgs &ra, const AsyncQ &q,
+                              hipStream_t s) {
+#define HJB_LAUNCH_ASYNC(D, A, B, C, NT)                                                    \
+  if (sh.dim == D && sh.tx == A && sh.ty == B && sh.tz == C && sh.nt == NT) {               \
+    if (fp64)                                                                               \
+      hipLaunchKernelGGL((k_sweep_async<double, D, A, B, C, NT>), dim3(grid), dim3(NT), 0, \
+                         s, probs, items, ra, q);                                           \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_sweep_async<float, D, A, B, C, NT>), dim3(grid), dim3(NT), 0,  \
+                         s, probs, items, ra, q);                                           \
+    return hipGetLastError();                                                               \
+  }
+  HJB_SHAPES(HJB_LAUNCH_ASYNC)
+#undef HJB_LAUNCH_ASYNC
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep(bool fp64, SweepShape sh, int grid, const DevProblem *probs,

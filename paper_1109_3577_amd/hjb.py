@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhjb.so")
 HJB_OK, HJB_EINVAL, HJB_EDEVICE, HJB_ENOMEM, HJB_ENOCONV, HJB_EAGAIN = 0, 1, 2, 3, 4, 5
 HJB_MEM_HOST, HJB_MEM_DEVICE = 0, 1
 HJB_F32, HJB_F64 = 0, 1
-HJB_SCHED_TILED, HJB_SCHED_JACOBI = 0, 1
+HJB_SCHED_TILED, HJB_SCHED_JACOBI, HJB_SCHED_ASYNC = 0, 1, 2
 
 # Every symbol include/hjb.h declares.
 EXPORTS = (

@@ -140,6 +140,26 @@ def test_solve_patches_parity(H, orc, pr, case):
     st = H.hjb_solve_patches(f, ph, H.HJB_F32, v32)
     assert np.abs(_np(v32) - out["v"]).max() <= 1e-5
     assert st["updates"] == st["node_updates"] * f.n_controls
+    # the asynchronous schedule (one persistent launch, device work queue)
+    # reaches the same fixed point bit for bit
+    a64 = _zeros(f.N, True)
+    H.hjb_solve_patches(f, ph, H.HJB_F64, a64, opts=H.make_opts(schedule=H.HJB_SCHED_ASYNC))
+    assert np.array_equal(_np(a64), out["v"])
+    a32 = _zeros(f.N, False)
+    v32e = _zeros(f.N, False)
+    H.hjb_solve_patches(f, ph, H.HJB_F32, v32e, 0.0)
+    H.hjb_solve_patches(f, ph, H.HJB_F32, a32, 0.0, opts=H.make_opts(schedule=H.HJB_SCHED_ASYNC))
+    assert np.array_equal(_np(a32), _np(v32e))
+
+
+def test_async_schedule_rejects_cap(H, pr):
+    f, c = pr.variable_speed_2d(1, 65, 17, 16, 4, 0.1, True)
+    ch = H.hjb_coarse_solve(c)
+    ph = H.hjb_build_patches(f, ch)
+    v = _zeros(f.N, False)
+    with pytest.raises(H.HjbError) as e:
+        H.hjb_solve_patches(f, ph, H.HJB_F32, v, 0.0, 10, H.make_opts(schedule=H.HJB_SCHED_ASYNC))
+    assert e.value.status == H.HJB_EINVAL
 
 
 def test_fp32_schedules_bitwise_equal(H, pr):
@@ -152,12 +172,17 @@ def test_fp32_schedules_bitwise_equal(H, pr):
     outs = []
     stream = torch.cuda.Stream()  # graphs cannot be captured on the null stream
     with torch.cuda.stream(stream):
-        for tile, K, rpp, graph in [((64, 16, 1), 48, 6, False), ((32, 32, 1), 8, 1, False),
-                                    ((64, 8, 1), 200, 12, True), ((32, 16, 1), 1, 6, True)]:
+        for tile, K, rpp, graph, sched in [
+                ((64, 16, 1), 48, 6, False, H.HJB_SCHED_TILED),
+                ((32, 32, 1), 8, 1, False, H.HJB_SCHED_TILED),
+                ((64, 8, 1), 200, 12, True, H.HJB_SCHED_TILED),
+                ((32, 16, 1), 1, 6, True, H.HJB_SCHED_TILED),
+                ((16, 16, 1), 3, 0, False, H.HJB_SCHED_ASYNC),
+                ((32, 8, 1), 64, 0, False, H.HJB_SCHED_ASYNC)]:
             v = _zeros(f.N, False)
             H.hjb_solve_patches(f, ph, H.HJB_F32, v,
                                 opts=H.make_opts(tile=tile, inner_sweeps=K, rounds_per_poll=rpp,
-                                                 use_graph=graph))
+                                                 use_graph=graph, schedule=sched))
             outs.append(_np(v))
     torch.cuda.synchronize()
     for o in outs[1:]:
@@ -169,9 +194,11 @@ def test_fp32_schedules_bitwise_equal_3d(H, pr):
     ch = H.hjb_coarse_solve(c)
     ph = H.hjb_build_patches(f, ch)
     outs = []
-    for tile, K in [((16, 8, 8), 32), ((8, 8, 8), 3), ((32, 8, 4), 100)]:
+    for tile, K, sched in [((16, 8, 8), 32, H.HJB_SCHED_TILED), ((8, 8, 8), 3, H.HJB_SCHED_TILED),
+                           ((32, 8, 4), 100, H.HJB_SCHED_TILED), ((8, 8, 8), 4, H.HJB_SCHED_ASYNC)]:
         v = _zeros(f.N, False)
-        H.hjb_solve_patches(f, ph, H.HJB_F32, v, opts=H.make_opts(tile=tile, inner_sweeps=K))
+        H.hjb_solve_patches(f, ph, H.HJB_F32, v,
+                            opts=H.make_opts(tile=tile, inner_sweeps=K, schedule=sched))
         outs.append(_np(v))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
