@@ -10,10 +10,14 @@
 // the mix.
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "runtime.h"
@@ -70,6 +74,9 @@ SweepShape engine_shape(int dim, bool fp64, const hjb_solve_opts *opts) {
   return make_config(dim, fp64, opts, 0.0, 0).shape;
 }
 
+// Host threads that prepare the problems of a batch at once.
+constexpr int kPrepareThreads = 8;
+
 std::unique_ptr<Prepared> prepare(const hjb_problem *fine, const hjb_problem *coarse, bool fp64,
                                   const hjb_solve_opts *opts, hipStream_t s) {
   const double t0 = now_ms();
@@ -93,6 +100,58 @@ std::unique_ptr<Prepared> prepare(const hjb_problem *fine, const hjb_problem *co
   pr->patches->feedback.release();
   pr->ms_prepare = now_ms() - t0;
   return pr;
+}
+
+void prepare_all(const hjb_problem *const *fine, const hjb_problem *const *coarse, int count,
+                 bool fp64, const hjb_solve_opts *opts, hipStream_t s,
+                 std::vector<std::unique_ptr<Prepared>> &out) {
+  const int workers = std::min(count, kPrepareThreads);
+  if (workers <= 1) {
+    for (int i = 0; i < count; ++i) out[i] = prepare(fine[i], coarse[i], fp64, opts, s);
+    return;
+  }
+  int dev = 0;
+  HJB_HIP(hipGetDevice(&dev));
+  HJB_HIP(hipStreamSynchronize(s));  // inputs the caller produced on s are ready
+  std::atomic<int> next{0};
+  std::mutex em;
+  int err_code = HJB_OK;
+  std::string err_msg;
+  auto work = [&]() {
+    hipStream_t ws = nullptr;
+    try {
+      HJB_HIP(hipSetDevice(dev));
+      HJB_HIP(hipStreamCreate(&ws));
+      for (int i = next++; i < count; i = next++) {
+        {
+          std::lock_guard<std::mutex> g(em);
+          if (err_code != HJB_OK) break;
+        }
+        out[i] = prepare(fine[i], coarse[i], fp64, opts, ws);
+      }
+      HJB_HIP(hipStreamSynchronize(ws));
+    } catch (const ApiError &e) {
+      std::lock_guard<std::mutex> g(em);
+      if (err_code == HJB_OK) {
+        err_code = e.code;
+        err_msg = e.msg;
+      }
+    } catch (const std::exception &e) {
+      std::lock_guard<std::mutex> g(em);
+      if (err_code == HJB_OK) {
+        err_code = HJB_EDEVICE;
+        err_msg = e.what();
+      }
+    }
+    if (ws) {
+      (void)hipStreamSynchronize(ws);
+      (void)hipStreamDestroy(ws);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 0; t < workers; ++t) pool.emplace_back(work);
+  for (auto &t : pool) t.join();
+  if (err_code != HJB_OK) throw_error(err_code, "%s", err_msg.c_str());
 }
 
 size_t footprint_bytes(const hjb_problem &f, const hjb_problem &c, bool fp64) {
@@ -137,10 +196,12 @@ int hjb_batch_create(const hjb_problem *const *fine, const hjb_problem *const *c
                 "precision must be HJB_F32 or HJB_F64");
     b->fp64 = b->opts.precision == HJB_F64;
     b->s = as_stream(stream);
-    for (int i = 0; i < count; ++i) {
-      HJB_REQUIRE(fine[i] && coarse[i], "problem %d is NULL", i);
-      b->probs.push_back(prepare(fine[i], coarse[i], b->fp64, &b->opts.solve, b->s));
-    }
+    for (int i = 0; i < count; ++i) HJB_REQUIRE(fine[i] && coarse[i], "problem %d is NULL", i);
+    // Preparation (coarse solve, feedback, colours, labels, items) is a
+    // chain of short, mostly latency-bound steps per problem: several host
+    // threads prepare problems at once, each on a stream of its own.
+    b->probs.resize(count);
+    prepare_all(fine, coarse, count, b->fp64, &b->opts.solve, b->s, b->probs);
     for (int d = 0; d < 2; ++d) {
       const int dim = d + 2;
       SolveConfig cfg = make_config(dim, b->fp64, &b->opts.solve, b->opts.tol, b->opts.max_sweeps);
@@ -382,21 +443,39 @@ int hjb_server_step(hjb_server_t *S, int32_t rounds, int32_t *live, int32_t *que
     HJB_REQUIRE(S != nullptr, "server is NULL");
     // Admission by HBM footprint, first come first served.
     std::vector<Request *> added[2];
-    while (!S->queue.empty() && S->used + S->queue.front()->footprint <= S->budget) {
-      Request *r = S->queue.front();
+    std::vector<Request *> adm;
+    size_t used = S->used;
+    while (!S->queue.empty() && used + S->queue.front()->footprint <= S->budget) {
+      adm.push_back(S->queue.front());
+      used += S->queue.front()->footprint;
       S->queue.pop_front();
+    }
+    if (!adm.empty()) {
+      // the admitted requests are prepared at once (threads and streams of
+      // their own), then join the live rounds together
+      std::vector<const hjb_problem *> fs, cs;
+      for (Request *r : adm) {
+        fs.push_back(&r->fine.p);
+        cs.push_back(&r->coarse.p);
+      }
+      std::vector<std::unique_ptr<Prepared>> preps(adm.size());
       const double t0 = now_ms();
-      r->prep = prepare(&r->fine.p, &r->coarse.p, S->fp64, &S->opts.solve, S->s);
-      r->st.ms_prolong_feedback = r->prep->patches->st.ms_prolong_feedback;
-      r->st.ms_trace = r->prep->patches->st.ms_trace;
-      r->st.unreached = r->prep->patches->st.unreached;
-      r->st.ms_wall = now_ms() - t0;
-      r->state = LIVE;
-      S->used += r->footprint;
-      added[r->prep->dim - 2].push_back(r);
-      // the request's host copies are no longer needed
-      r->fine = ProblemCopy();
-      r->coarse = ProblemCopy();
+      prepare_all(fs.data(), cs.data(), (int)adm.size(), S->fp64, &S->opts.solve, S->s, preps);
+      const double ms = now_ms() - t0;
+      for (size_t i = 0; i < adm.size(); ++i) {
+        Request *r = adm[i];
+        r->prep = std::move(preps[i]);
+        r->st.ms_prolong_feedback = r->prep->patches->st.ms_prolong_feedback;
+        r->st.ms_trace = r->prep->patches->st.ms_trace;
+        r->st.unreached = r->prep->patches->st.unreached;
+        r->st.ms_wall = ms;
+        r->state = LIVE;
+        S->used += r->footprint;
+        added[r->prep->dim - 2].push_back(r);
+        // the request's host copies are no longer needed
+        r->fine = ProblemCopy();
+        r->coarse = ProblemCopy();
+      }
     }
     for (int d = 0; d < 2; ++d)
       if (!added[d].empty()) rebuild_engine(*S, d, added[d]);

@@ -198,9 +198,15 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
   constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
   constexpr int LN = LX * LY * LZ;
   constexpr int TN = TX * TY * (DIM == 3 ? TZ : 1);
-  constexpr int NPT = TN / NT;
-  static_assert(TN % NT == 0, "tile must be a multiple of the block");
+  constexpr int NPT = TN / NT;  // bricks per wave
+  constexpr int NW = NT / 64;
+  constexpr int BX = Brick<DIM>::X, BY = Brick<DIM>::Y, BZ = Brick<DIM>::Z;
+  constexpr int NBX = TX / BX, NBY = TY / BY, NBZ = (DIM == 3) ? TZ / BZ : 1;
+  static_assert(TN % NT == 0 && NT % 64 == 0, "tile must be a multiple of the block");
+  static_assert(TX % BX == 0 && TY % BY == 0 && (DIM == 2 || TZ % BZ == 0), "brick tiling");
+  static_assert(NBX * NBY * NBZ <= 32, "brick mask is one word");
   __shared__ double s_phi[CL * LN];
+  __shared__ uint32_t s_msk[4];
   __shared__ uint32_t s_act[kMaxTraceWords];
   __shared__ int s_list[kMaxTraceWords * 32];
   __shared__ int s_nact;
@@ -208,6 +214,7 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
   __shared__ int s_nz[CL];
 
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
   const uint32_t r = ra.round;
   if (blockIdx.x == 0 && tid == 0) ra.count[(r + 2) % 3] = 0u;
   const uint32_t nin = ra.count[r % 3];
@@ -251,14 +258,20 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
     }
 
     // Per owned node: fixed foot point of its feedback control (FP64).
+    // This thread's nodes: lane `lane` of brick `wave + j NW`, j < NPT.
     int base[NPT], own[NPT];
     double t0[NPT], t1[NPT], t2[NPT];
-    bool act[NPT];
+    bool act[NPT], any[NPT];
     size_t gid[NPT];
+    uint32_t nbm[NPT];
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
-      const int i = tid + j * NT;
-      const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+      const int bb = wave + j * NW;
+      const int lx = (bb % NBX) * BX + lane % BX;
+      const int ly = ((bb / NBX) % NBY) * BY + (lane / BX) % BY;
+      const int lz = (bb / (NBX * NBY)) * BZ + lane / (BX * BY);
+      nbm[j] = brick_neighbours<NBX, NBY, NBZ>(bb);
+      any[j] = false;
       const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
       bool inb = gx < n0 && gy < n1;
       if (DIM == 3) inb = inb && gz < n2;
@@ -287,7 +300,6 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
     __syncthreads();
     const int nact = s_nact;
     bool converged_all = true;
-    int bx0 = 1 << 30, by0 = 1 << 30, bz0 = 1 << 30, bx1 = -1, by1 = -1, bz1 = -1;
 
     for (int g0 = 0; g0 < nact; g0 += CL) {
       const int nf = min(CL, nact - g0);
@@ -303,6 +315,13 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
           if (f < nf) s_phi[f * LN + i] = inb ? a.phi[(size_t)s_list[g0 + f] * a.N + g] : 0.0;
       }
       if (tid < CL) s_nz[tid] = 0;
+      // brick-change masks in rotation (as in the value sweep): sweep s
+      // reads the mask of sweep s - 1; every brick is swept first
+      if (tid == 0) {
+        s_msk[0] = 0u;
+        s_msk[1] = 0u;
+        s_msk[2] = ~0u;
+      }
       __syncthreads();
       double old[NPT][CL];
 #pragma unroll
@@ -312,10 +331,15 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
 
       bool converged = false;
       for (int it = 0; it < K; ++it) {
-        int ch = 0;
+        const uint32_t prev = s_msk[(it + 2) % 3];
+        if (tid == 0) s_msk[(it + 1) % 3] = 0u;
+        uint32_t mine = 0u;
 #pragma unroll
         for (int j = 0; j < NPT; ++j) {
-          if (!act[j]) continue;
+          // a brick none of whose neighbours changed in the last sweep
+          // would read the same colours again
+          if ((prev & nbm[j]) == 0u) continue;
+          bool ch = false;
           const int o = base[j];
 #pragma unroll
           for (int f = 0; f < CL; ++f) {
@@ -334,13 +358,16 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
               c[7] = sp[oz + LX + 1];
             }
             const double I = colour_step<DIM>(c, t0[j], t1[j], t2[j], a.beta);
-            if (I > sp[own[j]]) {
+            if (act[j] && I > sp[own[j]]) {
               s_phi[f * LN + own[j]] = I;
-              ch = 1;
+              ch = true;
             }
           }
+          if (__ballot(ch) != 0ull) mine |= 1u << (wave + j * NW);
         }
-        if (!__syncthreads_or(ch)) {
+        if (lane == 0 && mine) atomicOr(&s_msk[it % 3], mine);
+        __syncthreads();
+        if (s_msk[it % 3] == 0u) {
           converged = true;
           break;
         }
@@ -350,8 +377,6 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
 #pragma unroll
       for (int j = 0; j < NPT; ++j) {
         if (!act[j]) continue;
-        const int i = tid + j * NT;
-        const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
         bool changed = false;
 #pragma unroll
         for (int f = 0; f < CL; ++f) {
@@ -363,11 +388,7 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
             if (old[j][f] == 0.0) s_nz[f] = 1;
           }
         }
-        if (changed) {
-          bx0 = min(bx0, lx); bx1 = max(bx1, lx);
-          by0 = min(by0, ly); by1 = max(by1, ly);
-          bz0 = min(bz0, lz); bz1 = max(bz1, lz);
-        }
+        any[j] = any[j] || changed;
       }
       __syncthreads();
       if (tid < nf && s_nz[tid]) {
@@ -377,11 +398,13 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
       __syncthreads();  // LDS is refilled by the next group
     }
 
-    // changed-node box: reduced within each wave, merged by one LDS atomic
-    // per wave
-    wave_min_i(bx0); wave_min_i(by0); wave_min_i(bz0);
-    wave_max_i(bx1); wave_max_i(by1); wave_max_i(bz1);
-    if ((tid & 63) == 0 && bx1 >= 0) {
+    // changed-node box: per brick from a wave ballot, merged by one LDS
+    // atomic per wave
+    int bx0 = 1 << 30, by0 = 1 << 30, bz0 = 1 << 30, bx1 = -1, by1 = -1, bz1 = -1;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j)
+      brick_box<DIM, NBX, NBY>(__ballot(any[j]), wave + j * NW, bx0, bx1, by0, by1, bz0, bz1);
+    if (lane == 0 && bx1 >= 0) {
       atomicMin(&s_int[0], bx0); atomicMin(&s_int[1], by0); atomicMin(&s_int[2], bz0);
       atomicMax(&s_int[3], bx1); atomicMax(&s_int[4], by1); atomicMax(&s_int[5], bz1);
     }

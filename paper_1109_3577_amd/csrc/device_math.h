@@ -134,6 +134,68 @@ __device__ __forceinline__ void wave_max_i(int &x) {
   for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
 }
 
+// Work of one wave is a brick of 64 nodes: 8 x 8 in 2D, 4 x 4 x 4 in 3D;
+// lane = x + 8 y (2D), x + 4 y + 16 z (3D) within the brick.
+template <int DIM>
+struct Brick {
+  static constexpr int X = DIM == 2 ? 8 : 4;
+  static constexpr int Y = DIM == 2 ? 8 : 4;
+  static constexpr int Z = DIM == 2 ? 1 : 4;
+};
+
+// Grows the box [x0, x1] x [y0, y1] x [z0, z1] (tile-local nodes) by the
+// lanes set in `m` (a wave ballot) of brick `b` of a tile of NBX x NBY x .
+// bricks.  Uniform across the wave.
+template <int DIM, int NBX, int NBY>
+__device__ __forceinline__ void brick_box(unsigned long long m, int b, int &x0, int &x1, int &y0,
+                                          int &y1, int &z0, int &z1) {
+  if (!m) return;
+  constexpr int BX = Brick<DIM>::X, BY = Brick<DIM>::Y, BZ = Brick<DIM>::Z;
+  const int ox = (b % NBX) * BX, oy = ((b / NBX) % NBY) * BY, oz = (b / (NBX * NBY)) * BZ;
+  uint32_t xs, ys = 0u, zs;
+  if constexpr (DIM == 2) {
+    unsigned long long c = m | (m >> 32);
+    c |= c >> 16;
+    c |= c >> 8;
+    xs = (uint32_t)(c & 0xffu);
+#pragma unroll
+    for (int y = 0; y < 8; ++y) ys |= ((m >> (8 * y)) & 0xffull) ? (1u << y) : 0u;
+    zs = 1u;
+  } else {
+    const unsigned long long g = (m | (m >> 16) | (m >> 32) | (m >> 48)) & 0xffffull;
+    unsigned long long c = g | (g >> 8);
+    c |= c >> 4;
+    xs = (uint32_t)(c & 0xfu);
+    zs = 0u;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) ys |= ((g >> (4 * y)) & 0xfull) ? (1u << y) : 0u;
+#pragma unroll
+    for (int z = 0; z < 4; ++z) zs |= ((m >> (16 * z)) & 0xffffull) ? (1u << z) : 0u;
+  }
+  x0 = min(x0, ox + __builtin_ctz(xs));
+  x1 = max(x1, ox + 31 - __builtin_clz(xs));
+  y0 = min(y0, oy + __builtin_ctz(ys));
+  y1 = max(y1, oy + 31 - __builtin_clz(ys));
+  z0 = min(z0, oz + __builtin_ctz(zs));
+  z1 = max(z1, oz + 31 - __builtin_clz(zs));
+}
+
+// Bricks that a change in brick b can reach in one sweep (b and its
+// neighbours; the reach, 2 nodes, is below the brick side).
+template <int NBX, int NBY, int NBZ>
+__device__ __forceinline__ uint32_t brick_neighbours(int b) {
+  const int bx = b % NBX, by = (b / NBX) % NBY, bz = b / (NBX * NBY);
+  uint32_t m = 0u;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int x = bx + dx, y = by + dy, z = bz + dz;
+        if (x >= 0 && x < NBX && y >= 0 && y < NBY && z >= 0 && z < NBZ)
+          m |= 1u << (x + NBX * (y + NBY * z));
+      }
+  return m;
+}
+
 template <typename T>
 __device__ __forceinline__ void wave_max(T &x) {
 #pragma unroll

@@ -35,13 +35,6 @@ constexpr int lds_stride() {
   return (DIM == 2 && sizeof(T) == 4) ? LX + ((8 - LX % 32) + 32) % 32 : LX;
 }
 
-// Work of one wave is a brick of 64 nodes: 8 x 8 in 2D, 4 x 4 x 4 in 3D.
-template <int DIM>
-struct Brick {
-  static constexpr int X = DIM == 2 ? 8 : 4;
-  static constexpr int Y = DIM == 2 ? 8 : 4;
-  static constexpr int Z = DIM == 2 ? 1 : 4;
-};
 
 // Bricks on side (sx, sy, sz) of a tile of NBX x NBY x NBZ bricks: for each
 // axis, the first layer (s = -1), the last (s = +1) or all (s = 0).
@@ -128,15 +121,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
     const int lx = bx * BX + lane % BX;
     const int ly = by * BY + (lane / BX) % BY;
     const int lz = bz * BZ + lane / (BX * BY);
-    uint32_t m = 0u;
-    for (int dz = -1; dz <= 1; ++dz)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int x = bx + dx, y = by + dy, z = bz + dz;
-          if (x >= 0 && x < NBX && y >= 0 && y < NBY && z >= 0 && z < NBZ)
-            m |= 1u << (x + NBX * (y + NBY * z));
-        }
-    nbm[j] = m;
+    nbm[j] = brick_neighbours<NBX, NBY, NBZ>(b);
     const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
     bool inb = gx < n0 && gy < n1;
     if constexpr (DIM == 3) inb = inb && gz < n2;
@@ -269,38 +254,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
         big = old[j] - nv > tolT;
       }
     }
-    const unsigned long long m = __ballot(big);
-    if (m) {
-      const int b = wave + j * NW;
-      const int ox0 = (b % NBX) * BX, oy0 = ((b / NBX) % NBY) * BY, oz0 = (b / (NBX * NBY)) * BZ;
-      uint32_t xs, ys, zs;
-      if constexpr (DIM == 2) {
-        // lane = x + 8 y
-        unsigned long long c = m | (m >> 32);
-        c |= c >> 16;
-        c |= c >> 8;
-        xs = (uint32_t)(c & 0xffu);
-        ys = 0u;
-#pragma unroll
-        for (int y = 0; y < 8; ++y) ys |= ((m >> (8 * y)) & 0xffull) ? (1u << y) : 0u;
-        zs = 1u;
-      } else {
-        // lane = x + 4 y + 16 z
-        unsigned long long g = (m | (m >> 16) | (m >> 32) | (m >> 48)) & 0xffffull;
-        unsigned long long c = g | (g >> 8);
-        c |= c >> 4;
-        xs = (uint32_t)(c & 0xfu);
-        ys = 0u;
-        zs = 0u;
-#pragma unroll
-        for (int y = 0; y < 4; ++y) ys |= ((g >> (4 * y)) & 0xfull) ? (1u << y) : 0u;
-#pragma unroll
-        for (int z = 0; z < 4; ++z) zs |= ((m >> (16 * z)) & 0xffffull) ? (1u << z) : 0u;
-      }
-      bx0 = min(bx0, ox0 + __builtin_ctz(xs)); bx1 = max(bx1, ox0 + 31 - __builtin_clz(xs));
-      by0 = min(by0, oy0 + __builtin_ctz(ys)); by1 = max(by1, oy0 + 31 - __builtin_clz(ys));
-      bz0 = min(bz0, oz0 + __builtin_ctz(zs)); bz1 = max(bz1, oz0 + 31 - __builtin_clz(zs));
-    }
+    brick_box<DIM, NBX, NBY>(__ballot(big), wave + j * NW, bx0, bx1, by0, by1, bz0, bz1);
   }
   // The value stores are device-scope (written through to the coherent
   // level); each wave waits for its stores to complete, so after the
