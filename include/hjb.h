@@ -259,20 +259,28 @@ typedef struct {
   hjb_solve_opts solve;
 } hjb_server_opts;
 
-/* hbm_budget: bytes of device memory requests may hold at once. */
+/* hbm_budget: bytes of device memory requests may hold at once.  The
+ * server starts a pool of host threads (a HIP stream each, on the calling
+ * thread's current device) that prepare admitted requests; they stop in
+ * hjb_server_free.  Batches and servers run in rounds (HJB_EINVAL for
+ * HJB_SCHED_ASYNC). */
 int hjb_server_create(size_t hbm_budget, const hjb_server_opts *opts, hjb_stream_t stream,
                       hjb_server_t **out);
 /* Queues a request (arrays are copied before returning); *ticket
  * identifies it.  HJB_EINVAL if it could never fit the budget. */
 int hjb_server_submit(hjb_server_t *s, const hjb_problem *fine, const hjb_problem *coarse,
                       uint64_t *ticket);
-/* Advances the server: admits queued requests that fit, runs their build
- * steps, runs `rounds` sweep rounds over every live request and retires the
- * converged ones.  *live and *queued (may be NULL) receive the counts. */
+/* Advances the server: admits queued requests that fit (their footprint is
+ * reserved and the preparation pool runs their coarse solve and build steps
+ * meanwhile), adds the requests whose preparation finished to the live set,
+ * runs `rounds` sweep rounds over every live request and retires the
+ * converged ones.  *live and *queued (may be NULL) receive the counts
+ * (queued: waiting for admission or in preparation). */
 int hjb_server_step(hjb_server_t *s, int32_t rounds, int32_t *live, int32_t *queued);
 /* HJB_EAGAIN until the request is done; then copies its result (precision
  * of the server) to v_out (host or device per mem), fills st and releases
- * the request's memory. */
+ * the request's memory.  A request whose preparation failed returns that
+ * error here (and is released). */
 int hjb_server_poll(hjb_server_t *s, uint64_t ticket, void *v_out, int32_t mem, hjb_stats *st);
 void hjb_server_free(hjb_server_t *s);
 

@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -305,7 +307,7 @@ void hjb_batch_free(hjb_batch_t *b) { delete b; }
 
 namespace {
 
-enum ReqState { QUEUED = 0, LIVE = 1, DONE = 2 };
+enum ReqState { QUEUED = 0, PREPARING = 1, LIVE = 2, DONE = 3 };
 
 struct Request {
   uint64_t ticket = 0;
@@ -315,16 +317,23 @@ struct Request {
   std::unique_ptr<Prepared> prep;
   long long rounds_live = 0;
   int status = HJB_OK;
+  std::string error;     // message of a failed preparation
+  double ms_prepare = 0.0;
   hjb_stats st{};
 };
 
 }  // namespace
 
+// Admitted requests are prepared (coarse solve, feedback, colours, labels,
+// items) by a pool of host threads, each with a stream of its own, while
+// the live requests keep sweeping; a prepared request joins the shared
+// rounds at the next step.
 struct hjb_server_s {
   size_t budget = 0, used = 0;
   hjb_server_opts opts{};
   bool fp64 = false;
   hipStream_t s = nullptr;
+  int device = 0;
   uint64_t next_ticket = 1;
   std::deque<Request *> queue;
   std::map<uint64_t, std::unique_ptr<Request>> reqs;
@@ -332,7 +341,75 @@ struct hjb_server_s {
   std::vector<Request *> members[2];  // engine problem index -> request
   std::vector<std::unique_ptr<Request>> retired;  // collected, still listed by an engine
   SolveConfig cfg[2];
+  // preparation pool
+  std::mutex pm;
+  std::condition_variable pcv;   // work for the pool, or stop
+  std::condition_variable dcv;   // a preparation finished
+  std::deque<Request *> to_prepare;
+  std::vector<Request *> prepared;
+  int preparing = 0;             // handed to the pool, not yet joined
+  bool stopping = false;
+  std::vector<std::thread> workers;
+
+  void worker();
+  ~hjb_server_s() {
+    {
+      std::lock_guard<std::mutex> g(pm);
+      stopping = true;
+    }
+    pcv.notify_all();
+    for (auto &t : workers) t.join();
+  }
 };
+
+void hjb_server_s::worker() {
+  hipStream_t ws = nullptr;
+  bool ok = hipSetDevice(device) == hipSuccess && hipStreamCreate(&ws) == hipSuccess;
+  while (true) {
+    Request *r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(pm);
+      pcv.wait(lk, [&] { return stopping || !to_prepare.empty(); });
+      if (stopping) break;
+      r = to_prepare.front();
+      to_prepare.pop_front();
+    }
+    std::unique_ptr<Prepared> p;
+    int code = HJB_OK;
+    std::string msg;
+    const double t0 = now_ms();
+    if (!ok) {
+      code = HJB_EDEVICE;
+      msg = "preparation thread has no stream";
+    } else {
+      try {
+        p = prepare(&r->fine.p, &r->coarse.p, fp64, &opts.solve, ws);
+        HJB_HIP(hipStreamSynchronize(ws));
+      } catch (const ApiError &e) {
+        code = e.code;
+        msg = e.msg;
+        p.reset();
+      } catch (const std::exception &e) {
+        code = HJB_EDEVICE;
+        msg = e.what();
+        p.reset();
+      }
+    }
+    {
+      std::lock_guard<std::mutex> g(pm);
+      r->prep = std::move(p);
+      r->status = code;
+      r->error = msg;
+      r->ms_prepare = now_ms() - t0;
+      prepared.push_back(r);
+    }
+    dcv.notify_all();
+  }
+  if (ws) {
+    (void)hipStreamSynchronize(ws);
+    (void)hipStreamDestroy(ws);
+  }
+}
 
 namespace {
 
@@ -412,6 +489,9 @@ int hjb_server_create(size_t hbm_budget, const hjb_server_opts *opts, hjb_stream
     S->s = as_stream(stream);
     for (int d = 0; d < 2; ++d)
       S->cfg[d] = make_config(d + 2, S->fp64, &S->opts.solve, S->opts.tol, 0);
+    (void)engine_shape(2, S->fp64, &S->opts.solve);  // rejects HJB_SCHED_ASYNC
+    HJB_HIP(hipGetDevice(&S->device));
+    for (int t = 0; t < kPrepareThreads; ++t) S->workers.emplace_back([p = S.get()] { p->worker(); });
     *out = S.release();
     return HJB_OK;
   });
@@ -441,41 +521,50 @@ int hjb_server_submit(hjb_server_t *S, const hjb_problem *fine, const hjb_proble
 int hjb_server_step(hjb_server_t *S, int32_t rounds, int32_t *live, int32_t *queued) {
   return guarded([&]() -> int {
     HJB_REQUIRE(S != nullptr, "server is NULL");
-    // Admission by HBM footprint, first come first served.
-    std::vector<Request *> added[2];
-    std::vector<Request *> adm;
-    size_t used = S->used;
-    while (!S->queue.empty() && used + S->queue.front()->footprint <= S->budget) {
-      adm.push_back(S->queue.front());
-      used += S->queue.front()->footprint;
-      S->queue.pop_front();
-    }
-    if (!adm.empty()) {
-      // the admitted requests are prepared at once (threads and streams of
-      // their own), then join the live rounds together
-      std::vector<const hjb_problem *> fs, cs;
-      for (Request *r : adm) {
-        fs.push_back(&r->fine.p);
-        cs.push_back(&r->coarse.p);
-      }
-      std::vector<std::unique_ptr<Prepared>> preps(adm.size());
-      const double t0 = now_ms();
-      prepare_all(fs.data(), cs.data(), (int)adm.size(), S->fp64, &S->opts.solve, S->s, preps);
-      const double ms = now_ms() - t0;
-      for (size_t i = 0; i < adm.size(); ++i) {
-        Request *r = adm[i];
-        r->prep = std::move(preps[i]);
-        r->st.ms_prolong_feedback = r->prep->patches->st.ms_prolong_feedback;
-        r->st.ms_trace = r->prep->patches->st.ms_trace;
-        r->st.unreached = r->prep->patches->st.unreached;
-        r->st.ms_wall = ms;
-        r->state = LIVE;
+    // Admission by HBM footprint, first come first served: the footprint is
+    // reserved and the request goes to the preparation pool.
+    {
+      std::lock_guard<std::mutex> g(S->pm);
+      while (!S->queue.empty() && S->used + S->queue.front()->footprint <= S->budget) {
+        Request *r = S->queue.front();
+        S->queue.pop_front();
         S->used += r->footprint;
-        added[r->prep->dim - 2].push_back(r);
-        // the request's host copies are no longer needed
-        r->fine = ProblemCopy();
-        r->coarse = ProblemCopy();
+        r->state = PREPARING;
+        S->to_prepare.push_back(r);
+        ++S->preparing;
       }
+    }
+    S->pcv.notify_all();
+    // Prepared requests join the live rounds.  With nothing live, wait a
+    // little for one instead of returning at once.
+    bool any_live = false;
+    for (int d = 0; d < 2; ++d)
+      for (Request *r : S->members[d]) any_live |= r->state == LIVE;
+    std::vector<Request *> ready;
+    {
+      std::unique_lock<std::mutex> lk(S->pm);
+      if (!any_live && S->prepared.empty() && S->preparing > 0)
+        S->dcv.wait_for(lk, std::chrono::milliseconds(2), [&] { return !S->prepared.empty(); });
+      ready.swap(S->prepared);
+      S->preparing -= (int)ready.size();
+    }
+    std::vector<Request *> added[2];
+    for (Request *r : ready) {
+      // the request's host copies are no longer needed
+      r->fine = ProblemCopy();
+      r->coarse = ProblemCopy();
+      if (r->status != HJB_OK || !r->prep) {
+        r->state = DONE;
+        if (r->status == HJB_OK) r->status = HJB_EDEVICE;
+        r->st.status = r->status;
+        continue;
+      }
+      r->st.ms_prolong_feedback = r->prep->patches->st.ms_prolong_feedback;
+      r->st.ms_trace = r->prep->patches->st.ms_trace;
+      r->st.unreached = r->prep->patches->st.unreached;
+      r->st.ms_wall = r->ms_prepare;
+      r->state = LIVE;
+      added[r->prep->dim - 2].push_back(r);
     }
     for (int d = 0; d < 2; ++d)
       if (!added[d].empty()) rebuild_engine(*S, d, added[d]);
@@ -519,7 +608,10 @@ int hjb_server_step(hjb_server_t *S, int32_t rounds, int32_t *live, int32_t *que
     for (int d = 0; d < 2; ++d)
       for (Request *r : S->members[d]) nl += r->state == LIVE;
     if (live) *live = nl;
-    if (queued) *queued = (int32_t)S->queue.size();
+    if (queued) {
+      std::lock_guard<std::mutex> g(S->pm);
+      *queued = (int32_t)S->queue.size() + S->preparing;
+    }
     return HJB_OK;
   });
 }
@@ -531,6 +623,17 @@ int hjb_server_poll(hjb_server_t *S, uint64_t ticket, void *v_out, int32_t mem, 
     HJB_REQUIRE(it != S->reqs.end(), "unknown ticket %llu", (unsigned long long)ticket);
     Request *r = it->second.get();
     if (r->state != DONE) return HJB_EAGAIN;
+    if (!r->prep) {
+      // preparation failed: report its error and forget the request
+      const int status = r->status;
+      const std::string msg = r->error;
+      S->used -= r->footprint;
+      if (st) *st = r->st;
+      S->retired.push_back(std::move(it->second));
+      S->reqs.erase(it);
+      drop_retired(*S);
+      throw_error(status, "request preparation failed: %s", msg.c_str());
+    }
     HJB_REQUIRE(v_out != nullptr, "v_out is NULL");
     HJB_REQUIRE(mem == HJB_MEM_HOST || mem == HJB_MEM_DEVICE, "bad mem");
     HJB_HIP(hipMemcpyAsync(v_out, r->prep->v.get(), r->prep->v.bytes(),

@@ -99,7 +99,13 @@ def test_server_admission_by_budget(H, pr):
     S = H.hjb_server_create(4 << 20, H.HJB_F32)
     t1 = S.submit(f, c)
     t2 = S.submit(f, c)
-    live, queued = S.step(1)
+    # the first request is prepared in the background, then joins the live
+    # rounds; the second waits for budget the whole time
+    for _ in range(5000):
+        live, queued = S.step(1)
+        assert live + queued == 2 or live == 1
+        if live:
+            break
     assert live == 1 and queued == 1
     out = {}
     for _ in range(2000):
