@@ -79,8 +79,9 @@ def parse():
     ap.add_argument("--no-global", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=100)
     ap.add_argument("--graph", type=int, default=0)
-    ap.add_argument("--mode", choices=("solve", "batch", "serve", "copy"), default="solve",
+    ap.add_argument("--mode", choices=("solve", "solve3d", "batch", "serve", "copy"), default="solve",
                     help="solve: the 1025^2 patchy problem (default, the headline line); "
+                         "solve3d: the 257^3 patchy problem (98 controls, 64 parts); "
                          "batch: many uneven problems in shared rounds; serve: Poisson "
                          "request stream through the continuous-batching server")
     ap.add_argument("--count", type=int, default=0, help="problems (batch) / requests (serve)")
@@ -217,14 +218,23 @@ def main():
     if args.mode == "copy":
         return bench_copy(args)
     stream = torch.cuda.Stream()
-    fine_src, coarse_src = problems.config2(args.seed, args.n, args.ncoarse)
+    dim = 3 if args.mode == "solve3d" else 2
+    if dim == 2:
+        fine_src, coarse_src = problems.config2(args.seed, args.n, args.ncoarse)
+        label = (f"2D variable-speed patchy solve {args.n}^2 / {args.ncoarse}^2, 32 controls, "
+                 f"16 parts, seed {args.seed}, tol {args.tol:g}")
+        cfg = {"n": args.n, "n_coarse": args.ncoarse, "controls": 32, "parts": 16}
+    else:
+        fine_src, coarse_src = problems.config3(args.seed)
+        label = (f"3D variable-speed patchy solve 257^3 / 33^3, 98 controls, 64 parts, "
+                 f"seed {args.seed}, tol {args.tol:g}")
+        cfg = {"n": 257, "n_coarse": 33, "controls": 98, "parts": 64}
     fine = hjb.Problem(fine_src, device=True)
     coarse = hjb.Problem(coarse_src, device=True)
     N = fine.N
     v = torch.empty(N, dtype=torch.float32, device="cuda")
     opts = hjb.make_opts(time_kernels=not args.graph, use_graph=bool(args.graph))
-    print(f"[bench] workload 2D variable speed {args.n}^2 / {args.ncoarse}^2, 32 controls, "
-          f"16 parts, tol {args.tol:g}", file=sys.stderr, flush=True)
+    print(f"[bench] workload {label}", file=sys.stderr, flush=True)
 
     def step():
         ch = hjb.hjb_coarse_solve(coarse, 0.0, 0, stream)
@@ -277,10 +287,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 (values), f64 (coarse solve, feedback, colours, residual)",
         "data": "synthetic (seeded generator)",
-        "config": {"workload": f"2D variable-speed patchy solve {args.n}^2 / {args.ncoarse}^2, "
-                               f"32 controls, 16 parts, seed {args.seed}, tol {args.tol:g}",
-                   "n": args.n, "n_coarse": args.ncoarse, "controls": 32, "parts": 16,
-                   "tol": args.tol},
+        "config": {"workload": label, **cfg, "tol": args.tol},
         "step_ms": {"solve_patches": solve_ms, "build_patches": build_ms, "trace": trace_ms,
                     "coarse_and_other": ms_per_step - solve_ms - build_ms},
         "updates_per_step": {"patch_sweeps": solve_upd // args.steps,
@@ -291,10 +298,10 @@ def main():
     # Dominant kernel: the FP32 tiled sweep, HIP events around every block of
     # launches on the solve's stream.
     if launches:
-        ops = VALU_OPS_PER_UPDATE[2] * solve_upd
+        ops = VALU_OPS_PER_UPDATE[dim] * solve_upd
         achieved = ops / (kernel_ms * 1e-3)
         s0 = sts[0][0]
-        kernel = "k_sweep<float, 2, %d, %d, %d, %d>" % (*s0["tile"], s0["threads"])
+        kernel = "k_sweep<float, %d, %d, %d, %d, %d>" % (dim, *s0["tile"], s0["threads"])
         avg_s = kernel_ms * 1e-3 / launches
         traffic = recorded_traffic(kernel)
         out["roofline"] = {
@@ -305,7 +312,7 @@ def main():
             "traffic_unit": "HBM bytes per launch",
             "hbm_gbps": None if traffic is None else traffic / avg_s / 1e9,
             "avg_launch_us": avg_s * 1e6, "launches": launches,
-            "ops_per_update": VALU_OPS_PER_UPDATE[2],
+            "ops_per_update": VALU_OPS_PER_UPDATE[dim],
             "updates_per_launch": solve_upd / launches,
             "inner_sweeps": s0["inner_sweeps"],
         }
@@ -336,13 +343,16 @@ def main():
         O.build(force=False)
         threads = O.num_threads()
         t = time.perf_counter()
-        _, st = O.solve_global(fine_src, 0.0, max_sweeps=args.cpu_sweeps, allow_noconv=True)
+        # a bounded sample: 100 sweeps of the 2D grid, 5 of the 3D one
+        sweeps = args.cpu_sweeps if dim == 2 else max(1, args.cpu_sweeps // 20)
+        _, st = O.solve_global(fine_src, 0.0, max_sweeps=sweeps, allow_noconv=True)
         dt = time.perf_counter() - t
         out["cpu_baseline"] = {
             "value": st["updates"] / dt, "unit": "node-control updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{args.cpu_sweeps} Jacobi sweeps of the FP64 oracle on the full "
-                      f"{args.n}^2 fine grid (32 controls), {st['updates']:.3g} updates, {dt:.1f} s",
+            "sample": f"{sweeps} Jacobi sweeps of the FP64 oracle on the full fine grid "
+                      f"({cfg['n']}^{dim}, {cfg['controls']} controls), {st['updates']:.3g} "
+                      f"updates, {dt:.1f} s",
         }
     print(json.dumps(out))
 

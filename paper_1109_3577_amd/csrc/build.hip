@@ -135,12 +135,14 @@ hipError_t launch_feedback(int dim, const TraceArgs &a, const double *u0, uint8_
 constexpr double kColourFloor = 1e-9;
 
 // Colour-transport tiles: 2D 32 x 16 nodes, 512 threads, 8 FP64 fields per
-// LDS group, up to 32 in-tile sweeps per activation; 3D 8 x 8 x 8, 256
-// threads, 4 fields, 16 sweeps.  (The front of the colours moves about one
-// cell per sweep; the per-node work is one foot point, so sweeps are cheap
-// and a tile is swept until it settles or its budget ends.)
-constexpr int TR2_TX = 32, TR2_TY = 16, TR2_NT = 512, TR2_CL = 8, TR2_K = 32;
-constexpr int TR3_TX = 8, TR3_TY = 8, TR3_TZ = 8, TR3_NT = 256, TR3_CL = 4, TR3_K = 16;
+// LDS group, up to 24 in-tile sweeps per activation; 3D 8 x 8 x 8, 256
+// threads, 2 fields, 6 sweeps.  In 2D a tile sees about 2 parts and the
+// rounds are latency-bound; in 3D trilinear transport mixes the colours of
+// the 64 small target parts (about 15 per tile) and the work is throughput-
+// bound, where small LDS groups (more workgroups per CU) and short
+// activations pay.
+constexpr int TR2_TX = 32, TR2_TY = 16, TR2_NT = 512, TR2_CL = 8, TR2_K = 24;
+constexpr int TR3_TX = 8, TR3_TY = 8, TR3_TZ = 8, TR3_NT = 256, TR3_CL = 2, TR3_K = 6;
 constexpr int kMaxTraceWords = 32;  // up to 1024 parts
 
 int trace_chunk_capacity(int dim) { return dim == 2 ? TR2_CL : TR3_CL; }

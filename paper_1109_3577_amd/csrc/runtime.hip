@@ -356,7 +356,7 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
   SolveConfig c;
   c.fp64 = fp64;
   c.shape = default_shape(dim, fp64);
-  c.inner_sweeps = dim == 2 ? 8 : 4;
+  c.inner_sweeps = dim == 2 ? 8 : 2;
   c.tol = tol;
   c.max_rounds = max_sweeps > 0 ? max_sweeps : 1000000;
   HJB_REQUIRE(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");

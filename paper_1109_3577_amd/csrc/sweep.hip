@@ -114,6 +114,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
   size_t gid[NPT];
   bool act[NPT];
   uint32_t nbm[NPT];  // bricks whose change can reach brick j
+  bool bact[NPT];     // brick j holds a node of this patch
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int b = wave + j * NW;
@@ -129,6 +130,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
     const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0));
     gid[j] = g;
     act[j] = inb && code[g] == patch;
+    bact[j] = __ballot(act[j]) != 0ull;
     if constexpr (sizeof(T) == 4) {
       // offset foot point: y = c a + (w + 2)
       cc[j] = act[j] ? P.speed32[g] : 0.0f;
@@ -184,8 +186,10 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
     for (int j = 0; j < NPT; ++j) {
       // Skip the brick when nothing within its reach changed in the last
       // sweep: its update would read the same values and change nothing.
+      // A brick with no node of this patch (tiles that straddle patches) has
+      // nothing to update either.
       const uint32_t bj = 1u << (wave + j * NW);
-      if (it == 0 ? (first & bj) == 0u : (prev & nbm[j]) == 0u) continue;
+      if (!bact[j] || (it == 0 ? (first & bj) == 0u : (prev & nbm[j]) == 0u)) continue;
       upd += act[j] ? 1u : 0u;
       T mI = T(3);
       if constexpr (sizeof(T) == 4) {
