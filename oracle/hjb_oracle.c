@@ -69,6 +69,9 @@
  * rule of Step 3.1: colours matter only through their final projection). */
 #define ORC_COLOUR_FLOOR 1e-9
 
+/* pi to double precision (C99 has no M_PI) */
+#define ORC_PI 3.14159265358979323846
+
 #define ORC_OK 0
 #define ORC_EINVAL 1
 #define ORC_ENOCONV 4
@@ -94,6 +97,11 @@ typedef struct {
 typedef struct {
   const int16_t *labels;
   int patch;
+  /* Control restriction of add-on AO3 (Section "Patchy method's add-ons"):
+   * when allow != NULL, node q uses control k only if
+   * allow[fb[q] * n_controls + k] is 1 (fb = the Step 2 feedback). */
+  const uint8_t *fb;
+  const uint8_t *allow;
 } orc_active;
 
 static long long orc_N(const orc_problem *P) {
@@ -182,7 +190,9 @@ static double orc_interp(const orc_problem *P, const double *v, const orc_active
 static double orc_F_node(const orc_problem *P, const double *v, const orc_active *A, long long q,
                          long long px, long long py, long long pz) {
   double best = INFINITY;
+  const uint8_t *row = (A && A->allow) ? A->allow + (long long)A->fb[q] * P->n_controls : NULL;
   for (int k = 0; k < P->n_controls; ++k) {
+    if (row && !row[k]) continue;
     double disp[3];
     orc_displacement(P, q, k, disp);
     double I = orc_interp(P, v, A, px, py, pz, disp, 1.0);
@@ -503,26 +513,74 @@ int orc_labels(const orc_problem *F, const uint8_t *fb, int max_sweeps, int16_t 
   return rc;
 }
 
+/* Public: the control sets of add-on AO3 (Section "Patchy method's
+ * add-ons"): allow[ks * Nc + k] = 1 iff a_k . a_ks >= cos(pi / r), for every
+ * feedback control ks.  The dot product is summed over the axes in order,
+ * FP64, no fused multiply-add.  The feedback control itself is always kept
+ * (the cone is centred on it; this matters only for controls shorter than
+ * cos(pi/r)).  r <= 1 keeps every control.  Returns the largest set size. */
+int orc_cone_allowed(const orc_problem *P, double r, uint8_t *allow) {
+  if (orc_check(P)) return -1;
+  int nc = P->n_controls, dim = P->dim, lmax = 0;
+  double cr = r > 1.0 ? cos(ORC_PI / r) : -INFINITY;
+  for (int ks = 0; ks < nc; ++ks) {
+    int cnt = 0;
+    for (int k = 0; k < nc; ++k) {
+      double dot = 0.0;
+      for (int d = 0; d < dim; ++d) {
+        double pr = P->controls[(long long)k * dim + d] * P->controls[(long long)ks * dim + d];
+        dot = dot + pr;
+      }
+      int ok = (k == ks) || r <= 1.0 || dot >= cr;
+      allow[(long long)ks * nc + k] = (uint8_t)ok;
+      cnt += ok;
+    }
+    if (cnt > lmax) lmax = cnt;
+  }
+  return lmax;
+}
+
 /* Public: Step 3.2 + Step 4 -- independent value iteration in every patch
  * (state-constraint patch boundary), then merge.  `only_patch` >= 0 solves
- * that single patch (other nodes of v are left at 1 / 0). */
-int orc_solve_patches(const orc_problem *F, const int16_t *labels, double tol, int max_sweeps,
-                      int only_patch, double *v, int *sweeps_per_patch, long long *updates) {
+ * that single patch (other nodes of v are left at 1 / 0).  With fb != NULL
+ * and cone_r > 1, each node keeps only the controls of add-on AO3 around its
+ * feedback control fb[q] (orc_cone_allowed); `updates` then counts the
+ * controls actually evaluated. */
+int orc_solve_patches_cone(const orc_problem *F, const int16_t *labels, const uint8_t *fb,
+                           double cone_r, double tol, int max_sweeps, int only_patch, double *v,
+                           int *sweeps_per_patch, long long *updates) {
   if (orc_check(F) || F->n_parts < 1) return ORC_EINVAL;
+  uint8_t *allow = NULL;
+  long long *row_cnt = NULL;
+  if (fb && cone_r > 1.0) {
+    long long nc = F->n_controls;
+    allow = (uint8_t *)malloc((size_t)(nc * nc));
+    row_cnt = (long long *)calloc((size_t)nc, sizeof(long long));
+    if (!allow || !row_cnt) { free(allow); free(row_cnt); return ORC_ENOMEM; }
+    orc_cone_allowed(F, cone_r, allow);
+    for (long long ks = 0; ks < nc; ++ks)
+      for (long long k = 0; k < nc; ++k) row_cnt[ks] += allow[ks * nc + k];
+    long long Nf = orc_N(F);
+    for (long long q = 0; q < Nf; ++q)
+      if (F->target_part[q] < 0 && fb[q] >= nc) { free(allow); free(row_cnt); return ORC_EINVAL; }
+  }
   long long N = orc_N(F);
   long long *cnt = (long long *)calloc((size_t)F->n_parts, sizeof(long long));
   long long *start = (long long *)calloc((size_t)F->n_parts + 1, sizeof(long long));
   long long *nodes = (long long *)malloc(sizeof(long long) * (size_t)(N > 0 ? N : 1));
   double *work = (double *)malloc(sizeof(double) * (size_t)N);
   if (!cnt || !start || !nodes || !work) {
-    free(cnt); free(start); free(nodes); free(work);
+    free(cnt); free(start); free(nodes); free(work); free(allow); free(row_cnt);
     return ORC_ENOMEM;
   }
   for (long long q = 0; q < N; ++q) {
     if (F->target_part[q] >= 0) { v[q] = 0.0; continue; }
     v[q] = 1.0;
     int L = labels[q];
-    if (L >= F->n_parts) { free(cnt); free(start); free(nodes); free(work); return ORC_EINVAL; }
+    if (L >= F->n_parts) {
+      free(cnt); free(start); free(nodes); free(work); free(allow); free(row_cnt);
+      return ORC_EINVAL;
+    }
     if (L >= 0) cnt[L]++;
   }
   for (int j = 0; j < F->n_parts; ++j) start[j + 1] = start[j] + cnt[j];
@@ -539,17 +597,29 @@ int orc_solve_patches(const orc_problem *F, const int16_t *labels, double tol, i
     /* Patch-local iterate: target 0, patch nodes 1; other nodes are ghosts
      * (never read as values, see orc_corner). */
     for (long long q = 0; q < N; ++q) work[q] = (F->target_part[q] >= 0) ? 0.0 : 1.0;
-    orc_active A = {labels, j};
+    orc_active A = {labels, j, fb, allow};
     int sw = 0;
     int r = orc_jacobi(F, &A, nodes + start[j], cnt[j], tol, max_sweeps, work, &sw, NULL);
     if (r != ORC_OK) rc = r;
     if (sweeps_per_patch) sweeps_per_patch[j] = sw;
-    upd += (long long)sw * cnt[j] * F->n_controls;
+    long long per_sweep = cnt[j] * F->n_controls;
+    if (allow) {
+      per_sweep = 0;
+      for (long long i = start[j]; i < start[j] + cnt[j]; ++i) per_sweep += row_cnt[fb[nodes[i]]];
+    }
+    upd += (long long)sw * per_sweep;
     for (long long i = start[j]; i < start[j] + cnt[j]; ++i) v[nodes[i]] = work[nodes[i]];
   }
   if (updates) *updates = upd;
-  free(cnt); free(start); free(nodes); free(work);
+  free(cnt); free(start); free(nodes); free(work); free(allow); free(row_cnt);
   return rc;
+}
+
+/* Public: Steps 3.2 + 4 of the basic algorithm (every control). */
+int orc_solve_patches(const orc_problem *F, const int16_t *labels, double tol, int max_sweeps,
+                      int only_patch, double *v, int *sweeps_per_patch, long long *updates) {
+  return orc_solve_patches_cone(F, labels, NULL, 0.0, tol, max_sweeps, only_patch, v,
+                                sweeps_per_patch, updates);
 }
 
 /* Public: number of threads the parallel loops use. */

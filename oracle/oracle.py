@@ -62,6 +62,8 @@ def lib():
         L.orc_trace_part.argtypes = [vp, vp, i32, i32, vp, vp]
         L.orc_labels.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.orc_solve_patches.argtypes = [vp, vp, d, i32, i32, vp, vp, vp]
+        L.orc_solve_patches_cone.argtypes = [vp, vp, vp, d, d, i32, i32, vp, vp, vp]
+        L.orc_cone_allowed.argtypes = [vp, d, vp]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -220,6 +222,35 @@ def solve_patches(fine, labels_: np.ndarray, tol: float = 0.0, max_sweeps: int =
     upd = C.c_longlong(0)
     _check(lib().orc_solve_patches(H.ref, _p(lab), float(tol), int(max_sweeps), int(only_patch),
                                    _p(v), _p(sw), C.byref(upd)), "solve_patches")
+    return v, dict(sweeps=sw, updates=upd.value)
+
+
+def cone_allowed(fine, r: float):
+    """Add-on AO3: allowed[ks, k] = 1 iff control k lies in the cone of
+    half-angle pi/r around the feedback control ks.  Returns (allowed,
+    largest set size)."""
+    H = _Held(fine)
+    nc = int(fine.controls.shape[0])
+    allow = np.empty((nc, nc), dtype=np.uint8)
+    lmax = lib().orc_cone_allowed(H.ref, float(r), _p(allow))
+    if lmax < 0:
+        raise RuntimeError("oracle cone_allowed failed")
+    return allow, int(lmax)
+
+
+def solve_patches_cone(fine, labels_: np.ndarray, fb: np.ndarray, r: float, tol: float = 0.0,
+                       max_sweeps: int = 1_000_000, only_patch: int = -1):
+    """Steps 3.2 and 4 with add-on AO3: each node minimises over the controls
+    in the cone of half-angle pi/r around its Step 2 feedback control."""
+    H = _Held(fine)
+    lab = np.ascontiguousarray(labels_, dtype=np.int16).ravel()
+    fbc = np.ascontiguousarray(fb, dtype=np.uint8).ravel()
+    v = np.empty(fine.N, dtype=np.float64)
+    sw = np.zeros(max(1, fine.n_parts), dtype=np.int32)
+    upd = C.c_longlong(0)
+    _check(lib().orc_solve_patches_cone(H.ref, _p(lab), _p(fbc), float(r), float(tol),
+                                        int(max_sweeps), int(only_patch), _p(v), _p(sw),
+                                        C.byref(upd)), "solve_patches_cone")
     return v, dict(sweeps=sw, updates=upd.value)
 
 

@@ -5,6 +5,7 @@ of them re-types the oracle's own formula: they use closed forms of the
 continuous problem, exact discrete special cases, invariants, symmetric
 cases and the paper's own trends.
 """
+import dataclasses
 import json
 import math
 import os
@@ -508,3 +509,94 @@ def test_patchy_error_on_patch_boundaries(orc, pr):
     assert near.mean() < 0.25
     assert E[near].mean() > 5.0 * E[~near].mean()
     assert E[near].sum() > E[~near].sum()
+
+
+# ------------------------------------------------------------ add-on AO3
+
+def _ang(a, b):
+    return np.arccos(np.clip(a @ b, -1.0, 1.0))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_cone_sets_are_angular_caps(orc, pr, dim):
+    """Add-on AO3 (Section "Patchy method's add-ons"): A_r keeps the unit
+    controls within angle pi/r of the feedback control.  Checked against the
+    angles themselves, away from ties; 32 uniform directions give arcs of
+    2m+1 controls, m = floor(32 / (2 r)); r <= 1 keeps every control."""
+    P = pr.eikonal_2d(21, 32) if dim == 2 else pr.eikonal_3d(9, 98)
+    A = P.controls
+    nc = A.shape[0]
+    for r in (1.0, 1.7, 2.5, 4.5, 7.3):
+        allow, lmax = orc.cone_allowed(P, r)
+        assert allow.shape == (nc, nc) and np.all(np.diag(allow) == 1)
+        if r <= 1.0:
+            assert allow.all() and lmax == nc
+            continue
+        for ks in range(nc):
+            th = np.array([_ang(A[k], A[ks]) for k in range(nc)])
+            clear = np.abs(th - np.pi / r) > 1e-9
+            assert np.array_equal(allow[ks][clear] == 1, th[clear] < np.pi / r)
+        assert lmax == allow.sum(1).max()
+        if dim == 2:
+            m = int(np.floor(32 / (2 * r)))
+            for ks in range(nc):
+                arc = {(ks + o) % nc for o in range(-m, m + 1)}
+                assert set(np.nonzero(allow[ks])[0]) == arc
+
+
+def test_cone_constant_feedback_is_control_subset(orc, pr):
+    """With the feedback constant on a patch, AO3 is the plain scheme with
+    the control set A_r of that feedback: two patches with different
+    feedback controls, each equal bit for bit to a plain patch solve whose
+    control table is reduced to its cone (in a shuffled order)."""
+    n = 33
+    P = pr.eikonal_2d(n, 32, 0.15, 2)
+    X, Y = P.coords()
+    lab = np.where(P.target_part >= 0, P.target_part, np.where(X < 0.0, 0, 1)).astype(np.int16)
+    r = 2.5
+    ks = (0, 16 + 3)          # patch 0: angle 0; patch 1: angle 19 pi / 16
+    fb = np.where(lab == 0, ks[0], ks[1]).astype(np.uint8)
+    fb[P.target_part >= 0] = 255
+    v, _ = orc.solve_patches_cone(P, lab, fb, r)
+    allow, _ = orc.cone_allowed(P, r)
+    rng = np.random.default_rng(0)
+    for j in (0, 1):
+        S = rng.permutation(np.nonzero(allow[ks[j]])[0])
+        assert 9 <= len(S) < 32
+        Q = dataclasses.replace(P, controls=np.ascontiguousarray(P.controls[S]))
+        vj, _ = orc.solve_patches(Q, lab, only_patch=j)
+        m = (lab == j) & (P.target_part < 0)
+        assert np.array_equal(v[m], vj[m])
+    vfull, _ = orc.solve_patches(P, lab)
+    assert np.any(v != vfull)
+
+
+def test_cone_nested_sets_order_values(orc, pr):
+    """A_r shrinks as r grows (nested caps), and the min over fewer controls
+    is larger: v_full <= v_2 <= v_4 <= v_8 at every node, bit for bit (the
+    candidates are the same floating-point numbers).  The mean gap grows
+    with r; at r = 2 it is a small fraction of the r = 8 one."""
+    f, c = pr.variable_speed_2d(0, 97, 17, 32, 8, 0.1, True)
+    out = orc.patchy(f, c)
+    prev = out["v"]
+    gaps = []
+    for r in (2.0, 4.0, 8.0):
+        v, st = orc.solve_patches_cone(f, out["labels"], out["feedback"], r)
+        assert np.all(v >= prev)
+        assert st["updates"] < out["stats"]["updates"]
+        gaps.append(np.mean(v - out["v"]))
+        prev = v
+    assert gaps[0] < gaps[1] < gaps[2] and gaps[0] < 0.05 * gaps[2]
+
+
+def test_cone_line_target_exact(orc, pr):
+    """Line target: the optimal control (the axis direction to the line) is
+    the Step 2 feedback, so AO3 removes only controls that never win and
+    the result is the basic one, bit for bit."""
+    P = pr.line_target_2d(41, 32, strips=3)
+    Pc = pr.line_target_2d(21, 32, strips=3)
+    out = orc.patchy(P, Pc)
+    for r in (2.5, 4.5, 9.0):
+        v, st = orc.solve_patches_cone(P, out["labels"], out["feedback"], r)
+        assert np.array_equal(v, out["v"])
+        assert st["updates"] < out["stats"]["updates"]
