@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--no-global", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=100)
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--no-ao3", action="store_true",
+                    help="skip the add-on AO3 (control cone) side measurement")
+    ap.add_argument("--ao3-r", type=float, default=4.0, help="AO3 reduction factor r")
     ap.add_argument("--mode", choices=("solve", "solve3d", "batch", "serve", "copy"), default="solve",
                     help="solve: the 1025^2 patchy problem (default, the headline line); "
                          "solve3d: the 257^3 patchy problem (98 controls, 64 parts); "
@@ -336,6 +339,42 @@ def main():
                          "speedup_patch_solve_vs_jacobi": gj["ms_wall"] / solve_ms,
                          "patchy_error_E1": float(E.mean()), "patchy_error_Einf": float(E.max())}
         print(f"[bench] global Jacobi {gj['ms_wall']:.1f} ms, tiled {gt['ms_wall']:.1f} ms",
+              file=sys.stderr, flush=True)
+
+    # Add-on AO3 (control cones of half-angle pi/r around the Step 2
+    # feedback) beside the basic patch solve, on the same patches: kernel
+    # time of each, and the change of the result it brings.
+    if not args.no_ao3:
+        with torch.cuda.stream(stream):
+            ch = hjb.hjb_coarse_solve(coarse, 0.0, 0, stream)
+            ph = hjb.hjb_build_patches(fine, ch, stream)
+            vb = torch.empty(N, dtype=torch.float32, device="cuda")
+            va = torch.empty(N, dtype=torch.float32, device="cuda")
+            ob = hjb.make_opts(time_kernels=True)
+            oa = hjb.make_opts(time_kernels=True, control_cone=args.ao3_r)
+            rb, ra_ = [], []
+            for _ in range(3):
+                rb.append(hjb.hjb_solve_patches(fine, ph, hjb.HJB_F32, vb, args.tol, 0, ob, stream))
+                ra_.append(hjb.hjb_solve_patches(fine, ph, hjb.HJB_F32, va, args.tol, 0, oa,
+                                                 stream))
+            torch.cuda.synchronize()
+            D = va.double() - vb.double()
+            ph.free()
+            ch.free()
+        kb = min(r["ms_kernel"] for r in rb)
+        ka = min(r["ms_kernel"] for r in ra_)
+        out["ao3"] = {
+            "r": args.ao3_r,
+            "basic_kernel_ms": kb, "ao3_kernel_ms": ka, "speedup_kernel": kb / ka,
+            "basic_wall_ms": min(r["ms_wall"] for r in rb),
+            "ao3_wall_ms": min(r["ms_wall"] for r in ra_),
+            "basic_updates": rb[0]["updates"], "ao3_updates": ra_[0]["updates"],
+            "controls_per_node_update": ra_[0]["updates"] / max(1, ra_[0]["node_updates"]),
+            "ao3_updates_per_s_kernel": ra_[0]["updates"] / (ka * 1e-3),
+            "inner_sweeps": ra_[0]["inner_sweeps"],
+            "dv_mean": float(D.mean()), "dv_max": float(D.max()), "dv_min": float(D.min()),
+        }
+        print(f"[bench] AO3 r={args.ao3_r:g}: kernel {ka:.2f} ms vs basic {kb:.2f} ms",
               file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:

@@ -154,6 +154,20 @@ typedef struct {
   const uint8_t *patch_select; /* host [n_parts] 0/1, NULL = all patches
                                   (hjb_solve_patches only): nodes of
                                   unselected patches are left at 1 */
+  double control_cone;     /* add-on AO3 (Section "Patchy method's add-ons"),
+                              hjb_solve_patches only: r > 1 lets each node
+                              minimise over the controls a_k with
+                              a_k . a_ks >= cos(pi / r) only, a_ks = its
+                              Step 2 feedback control (always kept); the dot
+                              product is an FP64 sum over the axes in order,
+                              no fused multiply-add.  0 (or <= 1) = every
+                              control.  Needs HJB_SCHED_TILED and a tile
+                              shape among 2D 32x8, 32x16, 3D 8x8x8 (256
+                              threads); the tables (N_c rows of the
+                              largest cone, padded to 4 bytes, plus the
+                              controls) must fit 32 KiB of LDS.
+                              hjb_stats.updates then counts the largest
+                              cone per node update. */
 } hjb_solve_opts;
 
 typedef struct hjb_coarse_s hjb_coarse_t;

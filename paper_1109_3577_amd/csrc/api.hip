@@ -37,18 +37,21 @@ namespace hjb {
 // Value iteration on one problem with the tiled engine; fills st.
 int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *v, bool fp64,
                  const hjb_solve_opts *opts, double tol, int32_t max_sweeps, hipStream_t s,
-                 hjb_stats *st, double t0) {
+                 hjb_stats *st, double t0, const ConeArgs *cone) {
   HJB_HIP(launch_init_values(fp64, code, P.N, v, s));
   const SolveConfig cfg = make_config(P.dim, fp64, opts, tol, max_sweeps);
+  HJB_REQUIRE((cfg.cone_r > 0.0) == (cone != nullptr), "control cone tables missing");
   ProblemItems items = build_items(P, code, n_patches, cfg.shape, s);
   SweepEngine eng(cfg, s);
   eng.add_problem(P, code, &items, v);
+  if (cone) eng.set_cone(*cone);
   eng.begin();
   const int status = eng.async_ok() ? eng.run_async() : eng.run();
   if (st) {
     const EngineResult r = eng.results()[0];
     st->node_updates = (int64_t)r.work_nodes;
-    st->updates = (int64_t)r.work_nodes * P.nc;
+    // controls evaluated per node update: N_c, or the (padded) cone length
+    st->updates = (int64_t)r.work_nodes * (cone ? cone->len : P.nc);
     st->item_runs = (int64_t)r.item_runs;
     st->items = eng.total_items();
     st->rounds = (int32_t)eng.rounds();
@@ -398,6 +401,20 @@ int hjb_solve_patches(const hjb_problem *fine, const hjb_patches_t *p, int32_t p
                                selcode.as<int16_t>(), s));
       code = selcode.as<int16_t>();
     }
+    if (opts && opts->control_cone > 1.0) {
+      HJB_REQUIRE(std::isfinite(opts->control_cone), "control_cone must be finite");
+      const ConeTable t = make_cone_table(ctrl, fine->n_controls, fine->dim, opts->control_cone);
+      DBuf idx(t.idx.size());
+      HJB_HIP(hipMemcpyAsync(idx.get(), t.idx.data(), t.idx.size(), hipMemcpyHostToDevice, s));
+      ConeArgs c;
+      c.fb = p->feedback.as<uint8_t>();
+      c.idx = idx.as<uint8_t>();
+      c.len = t.len;
+      c.stride = t.stride;
+      // engine_solve synchronises the stream before it returns (t stays alive)
+      return engine_solve(*P, code, p->n_parts, v_out, fp64, opts, tol, max_sweeps, s, st, t0,
+                          &c);
+    }
     return engine_solve(*P, code, p->n_parts, v_out, fp64, opts, tol, max_sweeps, s, st, t0);
   });
 }
@@ -416,6 +433,8 @@ int hjb_solve_global(const hjb_problem *fine, int32_t precision, double tol, int
     auto P = upload_problem(*fine, !fp64, s, &ctrl);
     DBuf code(P->N * sizeof(int16_t));
     HJB_HIP(launch_make_code(P->tp, nullptr, nullptr, P->N, code.as<int16_t>(), s));
+    HJB_REQUIRE(!opts || opts->control_cone == 0.0,
+                "control_cone needs the Step 2 feedback (hjb_solve_patches only)");
     const int sched = opts ? opts->schedule : HJB_SCHED_TILED;
     if (sched == HJB_SCHED_JACOBI) {
       (void)make_config(P->dim, fp64, opts, tol, max_sweeps);  // validates opts and tol

@@ -73,6 +73,8 @@ struct ProblemCopy {
 SweepShape engine_shape(int dim, bool fp64, const hjb_solve_opts *opts) {
   HJB_REQUIRE(!opts || opts->schedule != HJB_SCHED_ASYNC,
               "batches and the server run in rounds (HJB_SCHED_ASYNC is for single solves)");
+  HJB_REQUIRE(!opts || opts->control_cone == 0.0,
+              "control_cone is an option of hjb_solve_patches only");
   return make_config(dim, fp64, opts, 0.0, 0).shape;
 }
 

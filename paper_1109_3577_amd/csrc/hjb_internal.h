@@ -58,6 +58,14 @@ struct DevProblem {
   unsigned long long *residual;  // [3][kSlots] per-round max decrease (FP64 bits)
   uint32_t *pactive;             // [3] per-round count of queued items
   unsigned long long *work;      // [2][kSlots] node updates, item runs
+  // Control cones of add-on AO3 (null / 0 without them): node p minimises
+  // over the controls cone_idx[fb[p]][0..cone_len) only.  Rows are
+  // cone_stride bytes (a multiple of 4), padded with the row's feedback
+  // control.
+  const uint8_t *fb;        // [N] Step 2 feedback control of every node
+  const uint8_t *cone_idx;  // [nc][cone_stride]
+  int32_t cone_len;
+  int32_t cone_stride;
 };
 
 struct Item {
@@ -133,6 +141,13 @@ hipError_t launch_sweep_async(bool fp64, SweepShape sh, int grid, const DevProbl
                               hipStream_t s);
 hipError_t launch_sweep(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
                         const Item *items, const RoundArgs &ra, hipStream_t s);
+// Sweep with the control cones of add-on AO3 (one problem, probs[0]); nc and
+// cone_stride size the LDS tables.
+bool sweep_cone_shape_supported(int dim, int tx, int ty, int tz, int nt);
+size_t sweep_cone_lds_bytes(bool fp64, int dim, int nc, int cone_stride);
+hipError_t launch_sweep_cone(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
+                             const Item *items, const RoundArgs &ra, int nc, int cone_stride,
+                             hipStream_t s);
 hipError_t launch_jacobi(bool fp64, int dim, const DevProblem *prob_dev, size_t N, const void *vin,
                          void *vout, unsigned long long *res_slot, hipStream_t s);
 hipError_t launch_tile_bits(int dim, const int16_t *code, const int32_t n[3], const int32_t tile[3],

@@ -150,6 +150,7 @@ struct SolveConfig {
   bool use_graph = false;
   bool time_kernels = false;
   bool async = false;  // HJB_SCHED_ASYNC: one persistent launch, device work queue
+  double cone_r = 0.0; // add-on AO3 reduction factor r (> 1: control cones on)
   double tol = 0.0;
   long long max_rounds = 1000000;
 };
@@ -169,6 +170,24 @@ struct ProblemItems {
 
 ProblemItems build_items(const ProblemDev &P, const int16_t *code, int n_patches, SweepShape sh,
                          hipStream_t s);
+
+// Control cones of add-on AO3: for every feedback control ks, the controls
+// a_k with a_k . a_ks >= cos(pi / r) (ks itself always), in index order,
+// each row padded with ks to `stride` bytes (a multiple of 4).
+struct ConeTable {
+  std::vector<uint8_t> idx;  // [nc][stride]
+  int len = 0;               // largest cone
+  int stride = 0;
+};
+ConeTable make_cone_table(const std::vector<double> &ctrl, int nc, int dim, double r);
+
+// Device side of a cone solve: the feedback of every node and the rows.
+struct ConeArgs {
+  const uint8_t *fb = nullptr;
+  const uint8_t *idx = nullptr;
+  int len = 0;
+  int stride = 0;
+};
 
 // Per-problem result of an engine run.
 struct EngineResult {
@@ -198,6 +217,9 @@ class SweepEngine {
   int run_async();
   // Whether the configuration asks for run_async (HJB_SCHED_ASYNC).
   bool async_ok() const;
+  // Switches the engine's only problem to the control cones of add-on AO3
+  // (before begin()).
+  void set_cone(const ConeArgs &c);
   // Enqueues `rounds` rounds, waits, returns the length of the next queue.
   int run_rounds(int rounds);
   // The next round's queue (global ids) and per-problem queued counts.
@@ -227,6 +249,7 @@ class SweepEngine {
   hipEvent_t poll_ev_[2] = {nullptr, nullptr};
   std::vector<int32_t> seeds_;
   bool async_ran_ = false;
+  bool cone_ = false;
   long long rounds_ = 0;
   uint32_t r_ = 0;
   double kernel_ms_ = 0.0;
@@ -262,9 +285,10 @@ std::unique_ptr<CoarseHandle> coarse_solve_impl(const hjb_problem *coarse, doubl
 std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const CoarseHandle &C,
                                                   hipStream_t s);
 // Value iteration of one problem with the tiled engine (v is initialised).
+// With `cone`, each node uses the controls of add-on AO3 only.
 int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *v, bool fp64,
                  const hjb_solve_opts *opts, double tol, int32_t max_sweeps, hipStream_t s,
-                 hjb_stats *st, double t0);
+                 hjb_stats *st, double t0, const ConeArgs *cone = nullptr);
 
 // Plain Jacobi on the whole grid (one launch per sweep).
 int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out, double tol,

@@ -389,6 +389,19 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
                     opts->schedule == HJB_SCHED_ASYNC,
                 "unknown schedule %d", opts->schedule);
     c.async = opts->schedule == HJB_SCHED_ASYNC;
+    HJB_REQUIRE(std::isfinite(opts->control_cone) && opts->control_cone >= 0.0,
+                "control_cone must be finite and >= 0");
+    c.cone_r = opts->control_cone > 1.0 ? opts->control_cone : 0.0;
+    if (c.cone_r > 0.0) {
+      // fewer controls per update: longer in-tile runs pay off in 2D
+      if (dim == 2 && opts->inner_sweeps <= 0) c.inner_sweeps = 16;
+      HJB_REQUIRE(opts->schedule == HJB_SCHED_TILED, "control_cone needs HJB_SCHED_TILED");
+      HJB_REQUIRE(sweep_cone_shape_supported(c.shape.dim, c.shape.tx, c.shape.ty, c.shape.tz,
+                                             c.shape.nt),
+                  "control_cone supports the tile shapes 2D 32x8, 32x16 and 3D 8x8x8 with 256 "
+                  "threads (got %dx%dx%d with %d)",
+                  c.shape.tx, c.shape.ty, c.shape.tz, c.shape.nt);
+    }
     HJB_REQUIRE(!c.async || max_sweeps <= 0, "HJB_SCHED_ASYNC takes no sweep cap (max_sweeps 0)");
     HJB_REQUIRE(!c.async || !c.use_graph, "HJB_SCHED_ASYNC has no rounds to replay as a graph");
   }
@@ -563,8 +576,12 @@ void SweepEngine::launch_round(uint32_t r) {
   ra.inner_sweeps = cfg_.inner_sweeps;
   ra.nprob = (int)dps_.size();
   ra.tol = cfg_.tol;
-  HJB_HIP(launch_sweep(cfg_.fp64, cfg_.shape, grid_, probs_d_.as<DevProblem>(),
-                       items_d_.as<Item>(), ra, s_));
+  if (cone_)
+    HJB_HIP(launch_sweep_cone(cfg_.fp64, cfg_.shape, grid_, probs_d_.as<DevProblem>(),
+                              items_d_.as<Item>(), ra, dps_[0].nc, dps_[0].cone_stride, s_));
+  else
+    HJB_HIP(launch_sweep(cfg_.fp64, cfg_.shape, grid_, probs_d_.as<DevProblem>(),
+                         items_d_.as<Item>(), ra, s_));
 }
 
 void SweepEngine::launch_block(int rounds) {
@@ -686,6 +703,46 @@ std::vector<int32_t> SweepEngine::queue_now() {
 }
 
 bool SweepEngine::async_ok() const { return cfg_.async; }
+
+void SweepEngine::set_cone(const ConeArgs &c) {
+  HJB_REQUIRE(dps_.size() == 1 && !cfg_.async, "control cones need one problem, rounds schedule");
+  HJB_REQUIRE(c.fb && c.idx && c.len > 0 && c.stride >= c.len && c.stride % 4 == 0,
+              "bad control cone table");
+  HJB_REQUIRE(sweep_cone_lds_bytes(cfg_.fp64, cfg_.shape.dim, dps_[0].nc, c.stride) <= 32 * 1024,
+              "control cone tables exceed 32 KiB of LDS (N_c = %d, cone stride %d)", dps_[0].nc,
+              c.stride);
+  dps_[0].fb = c.fb;
+  dps_[0].cone_idx = c.idx;
+  dps_[0].cone_len = c.len;
+  dps_[0].cone_stride = c.stride;
+  cone_ = true;
+}
+
+ConeTable make_cone_table(const std::vector<double> &ctrl, int nc, int dim, double r) {
+  // the dot products are summed over the axes in order, FP64, with
+  // separate multiplies and adds (the library is built without contraction)
+  constexpr double kPi = 3.14159265358979323846;
+  const double cr = std::cos(kPi / r);
+  std::vector<std::vector<uint8_t>> rows((size_t)nc);
+  ConeTable t;
+  for (int ks = 0; ks < nc; ++ks) {
+    for (int k = 0; k < nc; ++k) {
+      double dot = 0.0;
+      for (int d = 0; d < dim; ++d) {
+        const double pr = ctrl[(size_t)k * dim + d] * ctrl[(size_t)ks * dim + d];
+        dot = dot + pr;
+      }
+      if (k == ks || dot >= cr) rows[ks].push_back((uint8_t)k);
+    }
+    t.len = std::max(t.len, (int)rows[ks].size());
+  }
+  t.stride = (t.len + 3) / 4 * 4;
+  t.idx.assign((size_t)nc * t.stride, 0);
+  for (int ks = 0; ks < nc; ++ks)
+    for (int i = 0; i < t.stride; ++i)
+      t.idx[(size_t)ks * t.stride + i] = i < (int)rows[ks].size() ? rows[ks][i] : (uint8_t)ks;
+  return t;
+}
 
 int SweepEngine::run_async() {
   const size_t ni = items_h_.size();

@@ -20,6 +20,7 @@
 // for bit.  FP32 kernels use fused multiply-adds.
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device_math.h"
 #include "hjb_internal.h"
@@ -52,15 +53,32 @@ __device__ __forceinline__ uint32_t side_bricks(int sx, int sy, int sz) {
   return m;
 }
 
+// Tables of add-on AO3 in LDS: the controls [nc][cone_cols] (FP32: s_d a_kd,
+// FP64: a_kd; rows padded with zeros to an aligned vector), then the cone
+// index rows [nc][cone_stride] bytes.
+template <int DIM>
+constexpr int cone_cols() {
+  return DIM == 2 ? 2 : 4;
+}
+
+template <typename T, int DIM>
+__host__ __device__ constexpr size_t cone_idx_offset(int nc) {
+  return ((size_t)nc * cone_cols<DIM>() * sizeof(T) + 15) / 16 * 16;
+}
+
 // One activation of a work item.  ASYNC: values are exchanged with other
 // workgroups of the same launch (device-scope loads and stores, a release
 // fence before the pushes) and neighbours go to the work queue; otherwise
-// to the next round's list.  Returns whether the tile settled.
-template <typename T, int DIM, int TX, int TY, int TZ, int NT, bool DRIFT, bool ASYNC>
+// to the next round's list.  CONE: each node minimises over the controls of
+// its feedback's cone only (add-on AO3), read per lane from the LDS tables
+// at s_cone.  Returns whether the tile settled.
+template <typename T, int DIM, int TX, int TY, int TZ, int NT, bool DRIFT, bool ASYNC,
+          bool CONE = false>
 __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item, int item_id,
                                            uint32_t fl, const RoundArgs &ra, const AsyncQ &aq,
                                            T *s_v, int *s_int, double *s_red,
-                                           unsigned long long *s_wrk, uint32_t *s_msk) {
+                                           unsigned long long *s_wrk, uint32_t *s_msk,
+                                           const unsigned char *s_cone = nullptr) {
   constexpr int LX = TX + 2 * HALO;
   constexpr int LY = TY + 2 * HALO;
   constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
@@ -110,6 +128,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
   // This thread's nodes: lane `lane` of brick `wave + j NW`, j < NPT.
   T cc[NPT];
   T ww[NPT][DIM];
+  int krow[NPT];  // CONE: byte offset of the node's cone index row
   int off[NPT];
   size_t gid[NPT];
   bool act[NPT];
@@ -131,6 +150,10 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
     gid[j] = g;
     act[j] = inb && code[g] == patch;
     bact[j] = __ballot(act[j]) != 0ull;
+    if constexpr (CONE) {
+      const int ks = act[j] ? (int)P.fb[g] : 0;
+      krow[j] = (ks < P.nc ? ks : 0) * P.cone_stride;
+    }
     if constexpr (sizeof(T) == 4) {
       // offset foot point: y = c a + (w + 2)
       cc[j] = act[j] ? P.speed32[g] : 0.0f;
@@ -192,7 +215,69 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
       if (!bact[j] || (it == 0 ? (first & bj) == 0u : (prev & nbm[j]) == 0u)) continue;
       upd += act[j] ? 1u : 0u;
       T mI = T(3);
-      if constexpr (sizeof(T) == 4) {
+      if constexpr (CONE) {
+        // the node's cone: its index row holds four control indices per
+        // LDS word; full words first, then the uniform remainder
+        constexpr int CC = cone_cols<DIM>();
+        const T *ctl = reinterpret_cast<const T *>(s_cone);
+        const unsigned char *row = s_cone + cone_idx_offset<T, DIM>(P.nc) + krow[j];
+        const int b2 = off[j] - 2 - 2 * LXS - (DIM == 3 ? 2 * LXS * LY : 0);
+        auto group = [&](auto g_tag, uint32_t w4) {
+          constexpr int G = decltype(g_tag)::value;
+          T a[G][CC];
+#pragma unroll
+          for (int u = 0; u < G; ++u) {
+            const int k = (int)((w4 >> (8 * u)) & 255u);
+            if constexpr (sizeof(T) == 4 && DIM == 2) {
+              const float2 t2 = *reinterpret_cast<const float2 *>(ctl + k * CC);
+              a[u][0] = t2.x;
+              a[u][1] = t2.y;
+            } else if constexpr (sizeof(T) == 4) {
+              const float4 t4 = *reinterpret_cast<const float4 *>(ctl + k * CC);
+              a[u][0] = t4.x;
+              a[u][1] = t4.y;
+              a[u][2] = t4.z;
+              a[u][3] = t4.w;
+            } else {
+#pragma unroll
+              for (int q = 0; q < CC; ++q) a[u][q] = ctl[k * CC + q];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < G; ++u) {
+            if constexpr (sizeof(T) == 4) {
+              float y[DIM];
+#pragma unroll
+              for (int q = 0; q < DIM; ++q) y[q] = __builtin_fmaf(cc[j], a[u][q], ww[j][q]);
+              mI = __builtin_fminf(mI, interp_lds_f32<DIM, LXS, LY>(s_v, b2, y));
+            } else {
+              T d[DIM];
+#pragma unroll
+              for (int q = 0; q < DIM; ++q) {
+                T gq = cc[j] * a[u][q];
+                if (DRIFT) gq = gq + ww[j][q];
+                d[q] = P.step[q] * gq;
+              }
+              const T I = interp_lds_f64<DIM, LXS, LY>(s_v, off[j], d);
+              mI = I < mI ? I : mI;
+            }
+          }
+        };
+        const int cl = P.cone_len;
+        int i = 0;
+        for (; i + 4 <= cl; i += 4)
+          group(std::integral_constant<int, 4>{}, *reinterpret_cast<const uint32_t *>(row + i));
+        const int rem = cl - i;
+        if (rem > 0) {
+          const uint32_t w4 = *reinterpret_cast<const uint32_t *>(row + i);
+          if (rem == 1)
+            group(std::integral_constant<int, 1>{}, w4);
+          else if (rem == 2)
+            group(std::integral_constant<int, 2>{}, w4);
+          else
+            group(std::integral_constant<int, 3>{}, w4);
+        }
+      } else if constexpr (sizeof(T) == 4) {
         const int b2 = off[j] - 2 - 2 * LXS - (DIM == 3 ? 2 * LXS * LY : 0);
         for (int g4 = 0; g4 < ng; ++g4) {
           float a[4 * DIM];
@@ -382,6 +467,62 @@ k_sweep(const DevProblem *__restrict__ probs, const Item *__restrict__ items, Ro
   }
 }
 
+// Rounds schedule with the control cones of add-on AO3 (one problem).  The
+// controls and the cone index rows are staged in dynamic LDS once per
+// workgroup.
+template <typename T, int DIM, int TX, int TY, int TZ, int NT>
+__global__ void __launch_bounds__(NT)
+k_sweep_cone(const DevProblem *__restrict__ probs, const Item *__restrict__ items, RoundArgs ra) {
+  constexpr int LX = TX + 2 * HALO;
+  constexpr int LY = TY + 2 * HALO;
+  constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
+  constexpr int LXS = lds_stride<T, DIM, LX>();
+  constexpr int CC = cone_cols<DIM>();
+  __shared__ T s_v[LXS * LY * LZ];
+  __shared__ int s_int[8];
+  __shared__ uint32_t s_msk[4];
+  __shared__ double s_red[NT / 64];
+  __shared__ unsigned long long s_wrk[NT / 64];
+  extern __shared__ __attribute__((aligned(16))) unsigned char s_cone[];
+  const uint32_t r = ra.round;
+  const DevProblem &P = probs[0];
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) ra.count[(r + 2) % 3] = 0u;
+    for (int k = threadIdx.x; k < kSlots; k += NT) {
+      if (k == 0) P.pactive[(r + 2) % 3] = 0u;
+      P.residual[((r + 2) % 3) * kSlots + k] = 0ull;
+    }
+  }
+  const uint32_t nin = ra.count[r % 3];
+  if (blockIdx.x >= nin) return;
+  {
+    T *ctl = reinterpret_cast<T *>(s_cone);
+    for (int i = threadIdx.x; i < P.nc * CC; i += NT) {
+      const int k = i / CC, q = i % CC;
+      T a = T(0);
+      if (q < DIM) a = sizeof(T) == 4 ? (T)P.ctrl32[k * DIM + q] : (T)P.ctrl64[k * DIM + q];
+      ctl[i] = a;
+    }
+    uint32_t *idx = reinterpret_cast<uint32_t *>(s_cone + cone_idx_offset<T, DIM>(P.nc));
+    const uint32_t *gidx = reinterpret_cast<const uint32_t *>(P.cone_idx);
+    for (int i = threadIdx.x; i < P.nc * (P.cone_stride / 4); i += NT) idx[i] = gidx[i];
+  }
+  for (uint32_t li = blockIdx.x; li < nin; li += gridDim.x) {
+    const int it = ra.list_in[li];
+    const Item item = items[it];
+    const uint32_t fl = ra.flags_in[it];
+    __syncthreads();  // flag read by every thread (and, first, the tables staged)
+    if (threadIdx.x == 0) ra.flags_in[it] = 0u;
+    if (P.has_drift)
+      sweep_item<T, DIM, TX, TY, TZ, NT, true, false, true>(P, item, it, fl, ra, AsyncQ{}, s_v,
+                                                            s_int, s_red, s_wrk, s_msk, s_cone);
+    else
+      sweep_item<T, DIM, TX, TY, TZ, NT, false, false, true>(P, item, it, fl, ra, AsyncQ{}, s_v,
+                                                             s_int, s_red, s_wrk, s_msk, s_cone);
+    __syncthreads();
+  }
+}
+
 // Asynchronous schedule: one persistent launch; every workgroup takes items
 // from the work queue until no item is queued or running.
 template <typename T, int DIM, int TX, int TY, int TZ, int NT>
@@ -488,6 +629,46 @@ hipError_t launch_sweep(bool fp64, SweepShape sh, int grid, const DevProblem *pr
   }
   HJB_SHAPES(HJB_LAUNCH_SHAPE)
 #undef HJB_LAUNCH_SHAPE
+  return hipErrorInvalidValue;
+}
+
+#define HJB_CONE_SHAPES(X) \
+  X(2, 32, 8, 1, 256)        \
+  X(2, 32, 16, 1, 256)       \
+  X(3, 8, 8, 8, 256)
+
+bool sweep_cone_shape_supported(int dim, int tx, int ty, int tz, int nt) {
+#define HJB_CHECK_SHAPE(D, A, B, C, NT) \
+  if (dim == D && tx == A && ty == B && tz == C && nt == NT) return true;
+  HJB_CONE_SHAPES(HJB_CHECK_SHAPE)
+#undef HJB_CHECK_SHAPE
+  return false;
+}
+
+size_t sweep_cone_lds_bytes(bool fp64, int dim, int nc, int cone_stride) {
+  const size_t off = fp64 ? (dim == 2 ? cone_idx_offset<double, 2>(nc)
+                                      : cone_idx_offset<double, 3>(nc))
+                          : (dim == 2 ? cone_idx_offset<float, 2>(nc)
+                                      : cone_idx_offset<float, 3>(nc));
+  return off + (size_t)nc * (size_t)cone_stride;
+}
+
+hipError_t launch_sweep_cone(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
+                             const Item *items, const RoundArgs &ra, int nc, int cone_stride,
+                             hipStream_t s) {
+  const size_t lds = sweep_cone_lds_bytes(fp64, sh.dim, nc, cone_stride);
+#define HJB_LAUNCH_CONE(D, A, B, C, NT)                                                     \
+  if (sh.dim == D && sh.tx == A && sh.ty == B && sh.tz == C && sh.nt == NT) {               \
+    if (fp64)                                                                               \
+      hipLaunchKernelGGL((k_sweep_cone<double, D, A, B, C, NT>), dim3(grid), dim3(NT), lds, \
+                         s, probs, items, ra);                                              \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_sweep_cone<float, D, A, B, C, NT>), dim3(grid), dim3(NT), lds,  \
+                         s, probs, items, ra);                                              \
+    return hipGetLastError();                                                               \
+  }
+  HJB_CONE_SHAPES(HJB_LAUNCH_CONE)
+#undef HJB_LAUNCH_CONE
   return hipErrorInvalidValue;
 }
 

@@ -61,7 +61,7 @@ class hjb_solve_opts(C.Structure):
     _fields_ = [("tile", C.c_int32 * 3), ("inner_sweeps", C.c_int32),
                 ("rounds_per_poll", C.c_int32), ("schedule", C.c_int32),
                 ("time_kernels", C.c_int32), ("use_graph", C.c_int32), ("threads", C.c_int32),
-                ("patch_select", C.c_void_p)]
+                ("patch_select", C.c_void_p), ("control_cone", C.c_double)]
 
 
 class hjb_batch_opts(C.Structure):
@@ -199,7 +199,7 @@ def _as_problem(p, device=False) -> Problem:
 
 def make_opts(tile=None, inner_sweeps=0, rounds_per_poll=0, schedule=HJB_SCHED_TILED,
               time_kernels=False, use_graph=False, patch_select=None,
-              threads=0) -> hjb_solve_opts:
+              threads=0, control_cone=0.0) -> hjb_solve_opts:
     o = hjb_solve_opts()
     if tile is not None:
         for k, t in enumerate(tile):
@@ -210,6 +210,7 @@ def make_opts(tile=None, inner_sweeps=0, rounds_per_poll=0, schedule=HJB_SCHED_T
     o.time_kernels = int(bool(time_kernels))
     o.use_graph = int(bool(use_graph))
     o.threads = int(threads)
+    o.control_cone = float(control_cone)
     if patch_select is not None:
         sel = np.ascontiguousarray(patch_select, dtype=np.uint8)
         o._sel = sel
