@@ -102,6 +102,10 @@ typedef struct {
    * allow[fb[q] * n_controls + k] is 1 (fb = the Step 2 feedback). */
   const uint8_t *fb;
   const uint8_t *allow;
+  /* Dirichlet patch boundary data of eq. dbc (Section 4.4 and the add-ons
+   * section): when u0 != NULL, a box node outside the active set reads
+   * u0[q] instead of the ghost value 1. */
+  const double *u0;
 } orc_active;
 
 static long long orc_N(const orc_problem *P) {
@@ -119,14 +123,14 @@ static int orc_check(const orc_problem *P) {
 }
 
 /* Value of a corner node: stored value if inside the box and active, else
- * the ghost value. */
+ * the ghost value (or, inside the box, the Dirichlet data u0 of eq. dbc). */
 static double orc_corner(const orc_problem *P, const double *v, const orc_active *A,
                          long long x, long long y, long long z, double ghost) {
   if (x < 0 || y < 0 || z < 0 || x >= P->n[0] || y >= P->n[1] || z >= P->n[2]) return ghost;
   long long q = x + (long long)P->n[0] * (y + (long long)P->n[1] * z);
   if (A) {
     int tp = P->target_part[q];
-    if (tp < 0 && A->patch >= 0 && A->labels[q] != A->patch) return ghost;
+    if (tp < 0 && A->patch >= 0 && A->labels[q] != A->patch) return A->u0 ? A->u0[q] : ghost;
   }
   return v[q];
 }
@@ -540,15 +544,16 @@ int orc_cone_allowed(const orc_problem *P, double r, uint8_t *allow) {
   return lmax;
 }
 
-/* Public: Step 3.2 + Step 4 -- independent value iteration in every patch
- * (state-constraint patch boundary), then merge.  `only_patch` >= 0 solves
- * that single patch (other nodes of v are left at 1 / 0).  With fb != NULL
- * and cone_r > 1, each node keeps only the controls of add-on AO3 around its
- * feedback control fb[q] (orc_cone_allowed); `updates` then counts the
- * controls actually evaluated. */
-int orc_solve_patches_cone(const orc_problem *F, const int16_t *labels, const uint8_t *fb,
-                           double cone_r, double tol, int max_sweeps, int only_patch, double *v,
-                           int *sweeps_per_patch, long long *updates) {
+/* Public: Step 3.2 + Step 4 -- independent value iteration in every patch,
+ * then merge.  `only_patch` >= 0 solves that single patch (other nodes of v
+ * are left at 1 / 0).  Patch boundary: state constraint (other patches'
+ * nodes are ghosts of value 1) or, with u0 != NULL, the Dirichlet data of
+ * eq. dbc (they hold u0).  With fb != NULL and cone_r > 1, each node keeps
+ * only the controls of add-on AO3 around its feedback control fb[q]
+ * (orc_cone_allowed); `updates` then counts the controls evaluated. */
+int orc_solve_patches_ex(const orc_problem *F, const int16_t *labels, const uint8_t *fb,
+                         double cone_r, const double *u0, double tol, int max_sweeps,
+                         int only_patch, double *v, int *sweeps_per_patch, long long *updates) {
   if (orc_check(F) || F->n_parts < 1) return ORC_EINVAL;
   uint8_t *allow = NULL;
   long long *row_cnt = NULL;
@@ -597,7 +602,7 @@ int orc_solve_patches_cone(const orc_problem *F, const int16_t *labels, const ui
     /* Patch-local iterate: target 0, patch nodes 1; other nodes are ghosts
      * (never read as values, see orc_corner). */
     for (long long q = 0; q < N; ++q) work[q] = (F->target_part[q] >= 0) ? 0.0 : 1.0;
-    orc_active A = {labels, j, fb, allow};
+    orc_active A = {labels, j, fb, allow, u0};
     int sw = 0;
     int r = orc_jacobi(F, &A, nodes + start[j], cnt[j], tol, max_sweeps, work, &sw, NULL);
     if (r != ORC_OK) rc = r;
@@ -618,8 +623,8 @@ int orc_solve_patches_cone(const orc_problem *F, const int16_t *labels, const ui
 /* Public: Steps 3.2 + 4 of the basic algorithm (every control). */
 int orc_solve_patches(const orc_problem *F, const int16_t *labels, double tol, int max_sweeps,
                       int only_patch, double *v, int *sweeps_per_patch, long long *updates) {
-  return orc_solve_patches_cone(F, labels, NULL, 0.0, tol, max_sweeps, only_patch, v,
-                                sweeps_per_patch, updates);
+  return orc_solve_patches_ex(F, labels, NULL, 0.0, NULL, tol, max_sweeps, only_patch, v,
+                              sweeps_per_patch, updates);
 }
 
 /* Public: number of threads the parallel loops use. */

@@ -600,3 +600,57 @@ def test_cone_line_target_exact(orc, pr):
         v, st = orc.solve_patches_cone(P, out["labels"], out["feedback"], r)
         assert np.array_equal(v, out["v"])
         assert st["updates"] < out["stats"]["updates"]
+
+
+# ------------------------------------------------- Dirichlet patch data (dbc)
+
+def test_dbc_exact_data_gives_global(orc, pr):
+    """Eq. dbc with the exact global solution as boundary data: the global
+    solution solves every patch problem, so the patchy result is the global
+    one bit for bit (even for patches that are not invariant)."""
+    f, c = pr.variable_speed_2d(0, 97, 17, 32, 8, 0.1, True)
+    out = orc.patchy(f, c)
+    vg, _ = orc.solve_global(f)
+    v, _ = orc.solve_patches_ex(f, out["labels"], u0=vg)
+    assert np.array_equal(v, vg)
+    assert not np.array_equal(out["v"], vg)
+
+
+def test_dbc_ones_is_state_constraint(orc, pr):
+    """Boundary data equal to the ghost value 1 is the state-constraint
+    patch boundary of Step 3.2."""
+    f, c = pr.variable_speed_2d(1, 65, 17, 32, 6, 0.1, True, drift_sign=1)
+    out = orc.patchy(f, c)
+    v, _ = orc.solve_patches_ex(f, out["labels"], u0=np.ones(f.N))
+    assert np.array_equal(v, out["v"])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_dbc_smaller_error(orc, pr, seed):
+    """Section 4.4 / add-ons section: with the boundary data U^(0) the
+    patchy errors are smaller than with the state constraint, markedly so
+    in the sup norm (nodes cut off from their patch get data, not 1)."""
+    f, c = pr.variable_speed_2d(seed, 129, 17, 32, 16, 0.1, True)
+    out = orc.patchy(f, c)
+    vg, _ = orc.solve_global(f)
+    vd, _ = orc.solve_patches_ex(f, out["labels"], u0=out["u0"])
+    e_state, e_dbc = np.abs(out["v"] - vg), np.abs(vd - vg)
+    assert e_dbc.mean() < e_state.mean()
+    assert e_dbc.max() < 0.25 * e_state.max()
+
+
+def test_dbc_wrong_decomposition_matches_u0_accuracy(orc, pr):
+    """Section 3, details on boundary conditions: with a decomposition that
+    is not invariant at all (random labels), the data U^(0) keeps the result
+    as accurate as U^(0) itself, while the state constraint fails."""
+    f, c = pr.variable_speed_2d(0, 97, 17, 32, 8, 0.1, True)
+    out = orc.patchy(f, c)
+    vg, _ = orc.solve_global(f)
+    lab = out["labels"].copy()
+    m = f.target_part < 0
+    lab[m] = np.random.default_rng(0).integers(0, 8, int(m.sum()))
+    vd, _ = orc.solve_patches_ex(f, lab, u0=out["u0"])
+    vs, _ = orc.solve_patches(f, lab)
+    e_u0 = np.abs(out["u0"] - vg).mean()
+    assert np.abs(vd - vg).mean() <= 1.1 * e_u0
+    assert np.abs(vs - vg).mean() > 5.0 * e_u0
