@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=100)
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--no-ao3", action="store_true",
-                    help="skip the add-on AO3 (control cone) side measurement")
+                    help="skip the side measurement of the add-ons (dbc data, AO3 cones)")
     ap.add_argument("--ao3-r", type=float, default=4.0, help="AO3 reduction factor r")
     ap.add_argument("--mode", choices=("solve", "solve3d", "batch", "serve", "copy"), default="solve",
                     help="solve: the 1025^2 patchy problem (default, the headline line); "
@@ -341,41 +341,41 @@ def main():
         print(f"[bench] global Jacobi {gj['ms_wall']:.1f} ms, tiled {gt['ms_wall']:.1f} ms",
               file=sys.stderr, flush=True)
 
-    # Add-on AO3 (control cones of half-angle pi/r around the Step 2
-    # feedback) beside the basic patch solve, on the same patches: kernel
-    # time of each, and the change of the result it brings.
+    # The paper's add-ons beside the basic patch solve, on the same patches:
+    # the Dirichlet patch data U^(0) (eq. dbc), AO3 (control cones of
+    # half-angle pi/r around the Step 2 feedback) and both; kernel time of
+    # each and its error against the global solution (when measured).
     if not args.no_ao3:
+        variants = {"basic": {}, "dbc": {"patch_bc": hjb.HJB_BC_DIRICHLET},
+                    "ao3": {"control_cone": args.ao3_r},
+                    "dbc_ao3": {"patch_bc": hjb.HJB_BC_DIRICHLET, "control_cone": args.ao3_r}}
+        res = {}
         with torch.cuda.stream(stream):
             ch = hjb.hjb_coarse_solve(coarse, 0.0, 0, stream)
             ph = hjb.hjb_build_patches(fine, ch, stream)
-            vb = torch.empty(N, dtype=torch.float32, device="cuda")
             va = torch.empty(N, dtype=torch.float32, device="cuda")
-            ob = hjb.make_opts(time_kernels=True)
-            oa = hjb.make_opts(time_kernels=True, control_cone=args.ao3_r)
-            rb, ra_ = [], []
-            for _ in range(3):
-                rb.append(hjb.hjb_solve_patches(fine, ph, hjb.HJB_F32, vb, args.tol, 0, ob, stream))
-                ra_.append(hjb.hjb_solve_patches(fine, ph, hjb.HJB_F32, va, args.tol, 0, oa,
-                                                 stream))
-            torch.cuda.synchronize()
-            D = va.double() - vb.double()
+            for name, kw in variants.items():
+                o = hjb.make_opts(time_kernels=True, **kw)
+                runs = [hjb.hjb_solve_patches(fine, ph, hjb.HJB_F32, va, args.tol, 0, o, stream)
+                        for _ in range(3)]
+                torch.cuda.synchronize()
+                r = {"kernel_ms": min(x["ms_kernel"] for x in runs),
+                     "wall_ms": min(x["ms_wall"] for x in runs),
+                     "updates": runs[0]["updates"],
+                     "controls_per_node_update": runs[0]["updates"] / max(1, runs[0]["node_updates"]),
+                     "inner_sweeps": runs[0]["inner_sweeps"]}
+                if not args.no_global:
+                    E = (va.double() - vt.double()).abs()
+                    r["E1_vs_global"] = float(E.mean())
+                    r["Einf_vs_global"] = float(E.max())
+                res[name] = r
             ph.free()
             ch.free()
-        kb = min(r["ms_kernel"] for r in rb)
-        ka = min(r["ms_kernel"] for r in ra_)
-        out["ao3"] = {
-            "r": args.ao3_r,
-            "basic_kernel_ms": kb, "ao3_kernel_ms": ka, "speedup_kernel": kb / ka,
-            "basic_wall_ms": min(r["ms_wall"] for r in rb),
-            "ao3_wall_ms": min(r["ms_wall"] for r in ra_),
-            "basic_updates": rb[0]["updates"], "ao3_updates": ra_[0]["updates"],
-            "controls_per_node_update": ra_[0]["updates"] / max(1, ra_[0]["node_updates"]),
-            "ao3_updates_per_s_kernel": ra_[0]["updates"] / (ka * 1e-3),
-            "inner_sweeps": ra_[0]["inner_sweeps"],
-            "dv_mean": float(D.mean()), "dv_max": float(D.max()), "dv_min": float(D.min()),
-        }
-        print(f"[bench] AO3 r={args.ao3_r:g}: kernel {ka:.2f} ms vs basic {kb:.2f} ms",
-              file=sys.stderr, flush=True)
+        for name in ("dbc", "ao3", "dbc_ao3"):
+            res[name]["speedup_kernel_vs_basic"] = res["basic"]["kernel_ms"] / res[name]["kernel_ms"]
+        out["addons"] = {"r": args.ao3_r, **res}
+        print(f"[bench] add-ons (kernel ms): " + ", ".join(
+            f"{k} {v['kernel_ms']:.2f}" for k, v in res.items()), file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O

@@ -93,6 +93,13 @@ extern "C" {
                               drains a device work queue (no rounds; no
                               sweep cap: max_sweeps must be 0) */
 
+/* Boundary of the patch problems in Step 3.2 (hjb_solve_opts.patch_bc). */
+#define HJB_BC_STATE 0     /* state constraint: other patches' nodes are
+                              ghosts of value 1 */
+#define HJB_BC_DIRICHLET 1 /* eq. dbc: other patches' nodes (and unlabeled
+                              ones) hold U^(0) of Step 2; the domain
+                              boundary keeps the state constraint */
+
 typedef void *hjb_stream_t; /* hipStream_t */
 
 /* A tabulated minimum-time problem (Section 1, eq. HJB; Section 2.1). */
@@ -168,6 +175,8 @@ typedef struct {
                               controls) must fit 32 KiB of LDS.
                               hjb_stats.updates then counts the largest
                               cone per node update. */
+  int32_t patch_bc;        /* HJB_BC_* (patch solves: hjb_solve_patches,
+                              batches, the server); 0 = HJB_BC_STATE */
 } hjb_solve_opts;
 
 typedef struct hjb_coarse_s hjb_coarse_t;

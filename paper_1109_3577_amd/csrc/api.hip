@@ -37,13 +37,14 @@ namespace hjb {
 // Value iteration on one problem with the tiled engine; fills st.
 int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *v, bool fp64,
                  const hjb_solve_opts *opts, double tol, int32_t max_sweeps, hipStream_t s,
-                 hjb_stats *st, double t0, const ConeArgs *cone) {
+                 hjb_stats *st, double t0, const ConeArgs *cone, const double *dbc) {
   HJB_HIP(launch_init_values(fp64, code, P.N, v, s));
   const SolveConfig cfg = make_config(P.dim, fp64, opts, tol, max_sweeps);
   HJB_REQUIRE((cfg.cone_r > 0.0) == (cone != nullptr), "control cone tables missing");
+  HJB_REQUIRE(cfg.dbc == (dbc != nullptr), "patch boundary data missing");
   ProblemItems items = build_items(P, code, n_patches, cfg.shape, s);
   SweepEngine eng(cfg, s);
-  eng.add_problem(P, code, &items, v);
+  eng.add_problem(P, code, &items, v, dbc);
   if (cone) eng.set_cone(*cone);
   eng.begin();
   const int status = eng.async_ok() ? eng.run_async() : eng.run();
@@ -391,6 +392,8 @@ int hjb_solve_patches(const hjb_problem *fine, const hjb_patches_t *p, int32_t p
     const bool fp64 = precision == HJB_F64;
     auto P = upload_problem(*fine, !fp64, s, &ctrl);
     const int16_t *code = p->code.as<int16_t>();
+    const double *dbc =
+        opts && opts->patch_bc == HJB_BC_DIRICHLET ? p->u0.as<double>() : nullptr;
     DBuf selcode, sel;
     if (opts && opts->patch_select) {
       sel.reset((size_t)p->n_parts);
@@ -413,9 +416,10 @@ int hjb_solve_patches(const hjb_problem *fine, const hjb_patches_t *p, int32_t p
       c.stride = t.stride;
       // engine_solve synchronises the stream before it returns (t stays alive)
       return engine_solve(*P, code, p->n_parts, v_out, fp64, opts, tol, max_sweeps, s, st, t0,
-                          &c);
+                          &c, dbc);
     }
-    return engine_solve(*P, code, p->n_parts, v_out, fp64, opts, tol, max_sweeps, s, st, t0);
+    return engine_solve(*P, code, p->n_parts, v_out, fp64, opts, tol, max_sweeps, s, st, t0,
+                        nullptr, dbc);
   });
 }
 
@@ -435,6 +439,8 @@ int hjb_solve_global(const hjb_problem *fine, int32_t precision, double tol, int
     HJB_HIP(launch_make_code(P->tp, nullptr, nullptr, P->N, code.as<int16_t>(), s));
     HJB_REQUIRE(!opts || opts->control_cone == 0.0,
                 "control_cone needs the Step 2 feedback (hjb_solve_patches only)");
+    HJB_REQUIRE(!opts || opts->patch_bc == HJB_BC_STATE,
+                "patch_bc applies to patch solves (the global solve has no patches)");
     const int sched = opts ? opts->schedule : HJB_SCHED_TILED;
     if (sched == HJB_SCHED_JACOBI) {
       (void)make_config(P->dim, fp64, opts, tol, max_sweeps);  // validates opts and tol

@@ -99,8 +99,8 @@ std::unique_ptr<Prepared> prepare(const hjb_problem *fine, const hjb_problem *co
   HJB_HIP(launch_init_values(fp64, pr->patches->code.as<int16_t>(), N, pr->v.get(), s));
   pr->items = build_items(*pr->P, pr->patches->code.as<int16_t>(), pr->P->n_parts,
                           engine_shape(fine->dim, fp64, opts), s);
-  // keep only what the sweeps need
-  pr->patches->u0.release();
+  // keep only what the sweeps need (U^(0) as Dirichlet data of eq. dbc)
+  if (!opts || opts->patch_bc != HJB_BC_DIRICHLET) pr->patches->u0.release();
   pr->patches->feedback.release();
   pr->ms_prepare = now_ms() - t0;
   return pr;
@@ -213,7 +213,8 @@ int hjb_batch_create(const hjb_problem *const *fine, const hjb_problem *const *c
       for (auto &p : b->probs) {
         if (p->dim != dim) continue;
         if (!e) e = std::make_unique<SweepEngine>(cfg, b->s);
-        p->engine_index = e->add_problem(*p->P, p->patches->code.as<int16_t>(), &p->items, p->v.get());
+        p->engine_index = e->add_problem(*p->P, p->patches->code.as<int16_t>(), &p->items,
+                                         p->v.get(), p->patches->u0.as<double>());
       }
       if (e) e->begin();
       b->eng[d] = std::move(e);
@@ -450,7 +451,8 @@ void rebuild_engine(hjb_server_s &S, int d, const std::vector<Request *> &added)
   std::vector<int32_t> seeds;
   for (size_t i = 0; i < keep.size(); ++i) {
     Prepared &p = *keep[i]->prep;
-    p.engine_index = e->add_problem(*p.P, p.patches->code.as<int16_t>(), &p.items, p.v.get());
+    p.engine_index = e->add_problem(*p.P, p.patches->code.as<int16_t>(), &p.items, p.v.get(),
+                                    p.patches->u0.as<double>());
   }
   for (size_t i = 0; i < keep.size(); ++i)
     for (int32_t l : carry_local[i]) seeds.push_back(e->item_base((int)i) + l);

@@ -62,6 +62,8 @@ struct DevProblem {
   // over the controls cone_idx[fb[p]][0..cone_len) only.  Rows are
   // cone_stride bytes (a multiple of 4), padded with the row's feedback
   // control.
+  const double *u0;         // [N] Dirichlet data of other patches' nodes, or null
+                            // (state constraint: ghost 1)
   const uint8_t *fb;        // [N] Step 2 feedback control of every node
   const uint8_t *cone_idx;  // [nc][cone_stride]
   int32_t cone_len;

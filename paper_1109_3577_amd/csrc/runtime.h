@@ -151,6 +151,7 @@ struct SolveConfig {
   bool time_kernels = false;
   bool async = false;  // HJB_SCHED_ASYNC: one persistent launch, device work queue
   double cone_r = 0.0; // add-on AO3 reduction factor r (> 1: control cones on)
+  bool dbc = false;    // HJB_BC_DIRICHLET: patch boundaries hold U^(0)
   double tol = 0.0;
   long long max_rounds = 1000000;
 };
@@ -207,7 +208,9 @@ class SweepEngine {
   SweepEngine &operator=(const SweepEngine &) = delete;
   // Adds a problem; returns its index.  `v`, `code` and the inputs are on
   // the device.
-  int add_problem(const ProblemDev &P, const int16_t *code, const ProblemItems *items, void *v);
+  // `dbc` (optional, FP64 [N]): Dirichlet data of the patch boundaries.
+  int add_problem(const ProblemDev &P, const int16_t *code, const ProblemItems *items, void *v,
+                  const double *dbc = nullptr);
   // Uploads the tables and queues `seeds` (global ids) or, when null, the
   // seeds of every problem.
   void begin(const std::vector<int32_t> *seeds = nullptr);
@@ -288,7 +291,8 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
 // With `cone`, each node uses the controls of add-on AO3 only.
 int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *v, bool fp64,
                  const hjb_solve_opts *opts, double tol, int32_t max_sweeps, hipStream_t s,
-                 hjb_stats *st, double t0, const ConeArgs *cone = nullptr);
+                 hjb_stats *st, double t0, const ConeArgs *cone = nullptr,
+                 const double *dbc = nullptr);
 
 // Plain Jacobi on the whole grid (one launch per sweep).
 int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out, double tol,

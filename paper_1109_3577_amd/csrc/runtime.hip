@@ -391,6 +391,9 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
     c.async = opts->schedule == HJB_SCHED_ASYNC;
     HJB_REQUIRE(std::isfinite(opts->control_cone) && opts->control_cone >= 0.0,
                 "control_cone must be finite and >= 0");
+    HJB_REQUIRE(opts->patch_bc == HJB_BC_STATE || opts->patch_bc == HJB_BC_DIRICHLET,
+                "unknown patch_bc %d", opts->patch_bc);
+    c.dbc = opts->patch_bc == HJB_BC_DIRICHLET;
     c.cone_r = opts->control_cone > 1.0 ? opts->control_cone : 0.0;
     if (c.cone_r > 0.0) {
       // fewer controls per update: longer in-tile runs pay off in 2D
@@ -473,7 +476,7 @@ SweepEngine::~SweepEngine() {
 }
 
 int SweepEngine::add_problem(const ProblemDev &P, const int16_t *code, const ProblemItems *items,
-                             void *v) {
+                             void *v, const double *dbc) {
   HJB_REQUIRE(cfg_.shape.dim == P.dim, "tile shape dimension mismatch");
   HJB_REQUIRE(cfg_.fp64 || (P.ctrl32.get() && P.speed32.get()), "FP32 inputs missing");
   DevProblem d;
@@ -500,6 +503,7 @@ int SweepEngine::add_problem(const ProblemDev &P, const int16_t *code, const Pro
   d.drift32 = P.drift32.as<float>();
   d.code = code;
   d.v = v;
+  d.u0 = dbc;
   d.item_map = items->item_map.as<int32_t>();
   d.item_base = (int32_t)items_h_.size();
   bases_.push_back(d.item_base);

@@ -106,8 +106,9 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
   const int16_t *__restrict__ code = P.code;
 
   // Stage tile + halo: stored value where the node is active in this patch
-  // (target nodes are 0, patch nodes carry v), ghost 1 everywhere else.  The
-  // code and the value are fetched together.
+  // (target nodes are 0, patch nodes carry v); other box nodes hold the
+  // Dirichlet data U^(0) when given, else the ghost value 1, as do nodes
+  // outside the box.  The code and the value are fetched together.
   for (int i = tid; i < LN; i += NT) {
     const int lx = i % LX;
     const int ly = (i / LX) % LY;
@@ -120,7 +121,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
       const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0));
       const int cd = code[g];
       const T vg = ASYNC ? ld_dev(&v[g]) : v[g];
-      val = cd == CODE_TARGET ? T(0) : (cd == patch ? vg : T(1));
+      val = cd == CODE_TARGET ? T(0) : (cd == patch ? vg : (P.u0 ? (T)P.u0[g] : T(1)));
     }
     s_v[lx + LXS * (ly + LY * lz)] = val;
   }

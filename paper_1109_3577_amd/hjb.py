@@ -20,6 +20,7 @@ HJB_OK, HJB_EINVAL, HJB_EDEVICE, HJB_ENOMEM, HJB_ENOCONV, HJB_EAGAIN = 0, 1, 2, 
 HJB_MEM_HOST, HJB_MEM_DEVICE = 0, 1
 HJB_F32, HJB_F64 = 0, 1
 HJB_SCHED_TILED, HJB_SCHED_JACOBI, HJB_SCHED_ASYNC = 0, 1, 2
+HJB_BC_STATE, HJB_BC_DIRICHLET = 0, 1
 
 # Every symbol include/hjb.h declares.
 EXPORTS = (
@@ -61,7 +62,8 @@ class hjb_solve_opts(C.Structure):
     _fields_ = [("tile", C.c_int32 * 3), ("inner_sweeps", C.c_int32),
                 ("rounds_per_poll", C.c_int32), ("schedule", C.c_int32),
                 ("time_kernels", C.c_int32), ("use_graph", C.c_int32), ("threads", C.c_int32),
-                ("patch_select", C.c_void_p), ("control_cone", C.c_double)]
+                ("patch_select", C.c_void_p), ("control_cone", C.c_double),
+                ("patch_bc", C.c_int32)]
 
 
 class hjb_batch_opts(C.Structure):
@@ -199,7 +201,7 @@ def _as_problem(p, device=False) -> Problem:
 
 def make_opts(tile=None, inner_sweeps=0, rounds_per_poll=0, schedule=HJB_SCHED_TILED,
               time_kernels=False, use_graph=False, patch_select=None,
-              threads=0, control_cone=0.0) -> hjb_solve_opts:
+              threads=0, control_cone=0.0, patch_bc=0) -> hjb_solve_opts:
     o = hjb_solve_opts()
     if tile is not None:
         for k, t in enumerate(tile):
@@ -211,6 +213,7 @@ def make_opts(tile=None, inner_sweeps=0, rounds_per_poll=0, schedule=HJB_SCHED_T
     o.use_graph = int(bool(use_graph))
     o.threads = int(threads)
     o.control_cone = float(control_cone)
+    o.patch_bc = int(patch_bc)
     if patch_select is not None:
         sel = np.ascontiguousarray(patch_select, dtype=np.uint8)
         o._sel = sel

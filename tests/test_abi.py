@@ -123,3 +123,14 @@ def test_null_output_rejected(H):
     assert "NULL" in H.last_error()
     assert H.lib.hjb_patches_labels(None, None, 0) == H.HJB_EINVAL
     assert H.lib.hjb_server_poll(None, 1, None, 0, None) == H.HJB_EINVAL
+
+
+def test_constants_match_header(H):
+    """Every #define HJB_* integer constant of include/hjb.h that the
+    binding names has the same value there."""
+    src = open(os.path.join(ROOT, "include", "hjb.h")).read()
+    defs = dict(re.findall(r"#define\s+(HJB_[A-Z0-9_]+)\s+(-?\d+)\b", src))
+    names = [n for n in defs if hasattr(H, n)]
+    assert {"HJB_BC_STATE", "HJB_BC_DIRICHLET", "HJB_SCHED_ASYNC", "HJB_F64"} <= set(names)
+    for n in names:
+        assert getattr(H, n) == int(defs[n]), n
