@@ -346,9 +346,12 @@ def main():
     # half-angle pi/r around the Step 2 feedback) and both; kernel time of
     # each and its error against the global solution (when measured).
     if not args.no_ao3:
-        variants = {"basic": {}, "dbc": {"patch_bc": hjb.HJB_BC_DIRICHLET},
-                    "ao3": {"control_cone": args.ao3_r},
-                    "dbc_ao3": {"patch_bc": hjb.HJB_BC_DIRICHLET, "control_cone": args.ao3_r}}
+        # AO2 window (time steps per round) and in-tile sweeps that suit it
+        ao2 = {"order_window": 6.0} if dim == 2 else {"order_window": 2.5, "inner_sweeps": 4}
+        dbc = {"patch_bc": hjb.HJB_BC_DIRICHLET}
+        ao3 = {"control_cone": args.ao3_r}
+        variants = {"basic": {}, "dbc": dbc, "ao2": ao2, "ao3": ao3,
+                    "dbc_ao2_ao3": {**dbc, **ao2, **ao3}}
         res = {}
         with torch.cuda.stream(stream):
             ch = hjb.hjb_coarse_solve(coarse, 0.0, 0, stream)
@@ -359,9 +362,11 @@ def main():
                 runs = [hjb.hjb_solve_patches(fine, ph, hjb.HJB_F32, va, args.tol, 0, o, stream)
                         for _ in range(3)]
                 torch.cuda.synchronize()
-                r = {"kernel_ms": min(x["ms_kernel"] for x in runs),
+                r = {"opts": {k: float(v) for k, v in kw.items()},
+                     "kernel_ms": min(x["ms_kernel"] for x in runs),
                      "wall_ms": min(x["ms_wall"] for x in runs),
-                     "updates": runs[0]["updates"],
+                     "updates": runs[0]["updates"], "node_updates": runs[0]["node_updates"],
+                     "rounds": runs[0]["rounds"],
                      "controls_per_node_update": runs[0]["updates"] / max(1, runs[0]["node_updates"]),
                      "inner_sweeps": runs[0]["inner_sweeps"]}
                 if not args.no_global:
@@ -371,7 +376,7 @@ def main():
                 res[name] = r
             ph.free()
             ch.free()
-        for name in ("dbc", "ao3", "dbc_ao3"):
+        for name in ("dbc", "ao2", "ao3", "dbc_ao2_ao3"):
             res[name]["speedup_kernel_vs_basic"] = res["basic"]["kernel_ms"] / res[name]["kernel_ms"]
         out["addons"] = {"r": args.ao3_r, **res}
         print(f"[bench] add-ons (kernel ms): " + ", ".join(

@@ -177,6 +177,19 @@ typedef struct {
                               cone per node update. */
   int32_t patch_bc;        /* HJB_BC_* (patch solves: hjb_solve_patches,
                               batches, the server); 0 = HJB_BC_STATE */
+  double order_window;     /* add-on AO2 (Section "Patchy method's add-ons"),
+                              hjb_solve_patches only, rounds schedule: > 0
+                              runs the tiles in the order of their Step 2
+                              values.  A tile's key is the smallest minimal
+                              time -ln(1 - U^(0)) of its patch nodes; a
+                              queued tile runs in a round only if its key is
+                              at most the round's threshold, else it waits.
+                              The threshold of a round is the larger of the
+                              smallest queued key and the previous round's
+                              threshold plus order_window time steps h
+                              (h = -ln beta).  The fixed point (and so the
+                              result, bit for bit) is the same; only the
+                              order and the work change.  0 = off. */
 } hjb_solve_opts;
 
 typedef struct hjb_coarse_s hjb_coarse_t;

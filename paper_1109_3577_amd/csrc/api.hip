@@ -37,12 +37,15 @@ namespace hjb {
 // Value iteration on one problem with the tiled engine; fills st.
 int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *v, bool fp64,
                  const hjb_solve_opts *opts, double tol, int32_t max_sweeps, hipStream_t s,
-                 hjb_stats *st, double t0, const ConeArgs *cone, const double *dbc) {
+                 hjb_stats *st, double t0, const ConeArgs *cone, const double *dbc,
+                 const double *u0) {
   HJB_HIP(launch_init_values(fp64, code, P.N, v, s));
   const SolveConfig cfg = make_config(P.dim, fp64, opts, tol, max_sweeps);
   HJB_REQUIRE((cfg.cone_r > 0.0) == (cone != nullptr), "control cone tables missing");
   HJB_REQUIRE(cfg.dbc == (dbc != nullptr), "patch boundary data missing");
+  HJB_REQUIRE(cfg.win_dt == 0.0 || u0 != nullptr, "order_window needs the Step 2 values");
   ProblemItems items = build_items(P, code, n_patches, cfg.shape, s);
+  if (cfg.win_dt > 0.0) build_item_keys(P, code, u0, cfg.shape, items, s);
   SweepEngine eng(cfg, s);
   eng.add_problem(P, code, &items, v, dbc);
   if (cone) eng.set_cone(*cone);
@@ -416,10 +419,10 @@ int hjb_solve_patches(const hjb_problem *fine, const hjb_patches_t *p, int32_t p
       c.stride = t.stride;
       // engine_solve synchronises the stream before it returns (t stays alive)
       return engine_solve(*P, code, p->n_parts, v_out, fp64, opts, tol, max_sweeps, s, st, t0,
-                          &c, dbc);
+                          &c, dbc, p->u0.as<double>());
     }
     return engine_solve(*P, code, p->n_parts, v_out, fp64, opts, tol, max_sweeps, s, st, t0,
-                        nullptr, dbc);
+                        nullptr, dbc, p->u0.as<double>());
   });
 }
 
@@ -441,6 +444,8 @@ int hjb_solve_global(const hjb_problem *fine, int32_t precision, double tol, int
                 "control_cone needs the Step 2 feedback (hjb_solve_patches only)");
     HJB_REQUIRE(!opts || opts->patch_bc == HJB_BC_STATE,
                 "patch_bc applies to patch solves (the global solve has no patches)");
+    HJB_REQUIRE(!opts || opts->order_window == 0.0,
+                "order_window needs the Step 2 values (hjb_solve_patches only)");
     const int sched = opts ? opts->schedule : HJB_SCHED_TILED;
     if (sched == HJB_SCHED_JACOBI) {
       (void)make_config(P->dim, fp64, opts, tol, max_sweeps);  // validates opts and tol

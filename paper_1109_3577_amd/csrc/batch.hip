@@ -75,6 +75,8 @@ SweepShape engine_shape(int dim, bool fp64, const hjb_solve_opts *opts) {
               "batches and the server run in rounds (HJB_SCHED_ASYNC is for single solves)");
   HJB_REQUIRE(!opts || opts->control_cone == 0.0,
               "control_cone is an option of hjb_solve_patches only");
+  HJB_REQUIRE(!opts || opts->order_window == 0.0,
+              "order_window is an option of hjb_solve_patches only");
   return make_config(dim, fp64, opts, 0.0, 0).shape;
 }
 

@@ -27,7 +27,12 @@ constexpr int16_t CODE_NONE = -1;
 // workgroup index mod kSlots) so that the workgroups of a round do not all
 // update one address; the host reduces the slots.
 constexpr int kSlots = 16;
-constexpr int kCounterWords = 3 * kSlots + 2 + 2 * kSlots;  // u64 words per problem
+// Per problem: residual [3][kSlots], pactive (3 u32), work [2][kSlots],
+// ordering window (6 u32).
+constexpr int kCounterWords = 3 * kSlots + 2 + 2 * kSlots + 3;  // u64 words per problem
+// Item flag bit: the item must sweep all its bricks first (set when an item
+// that had not run yet is carried to a later round).
+constexpr uint32_t kFlagFull = 1u << 31;
 
 // Per-problem parameters as the kernels see them.  Lives in device memory
 // (an array of these for a batch).  Pointers are device pointers.
@@ -68,6 +73,16 @@ struct DevProblem {
   const uint8_t *cone_idx;  // [nc][cone_stride]
   int32_t cone_len;
   int32_t cone_stride;
+  // Value-ordered schedule (add-on AO2, null / 0 without it): a queued item
+  // runs in round r only if its key (the smallest minimal time -ln(1 - U^(0))
+  // of its nodes) is at most the round's threshold, else it is carried to
+  // the next round.  win[r % 3] is the base threshold of round r, win[3 + r %
+  // 3] the smallest key queued for it (FP32 bits); the threshold is the
+  // larger of the two, and the base of the next round exceeds it by win_dt.
+  const float *item_key;  // [n_patches][ntiles] (like item_map)
+  uint32_t *win;          // [6]
+  float win_dt;
+  int32_t pad3;
 };
 
 struct Item {
@@ -152,6 +167,11 @@ hipError_t launch_sweep_cone(bool fp64, SweepShape sh, int grid, const DevProble
                              hipStream_t s);
 hipError_t launch_jacobi(bool fp64, int dim, const DevProblem *prob_dev, size_t N, const void *vin,
                          void *vout, unsigned long long *res_slot, hipStream_t s);
+// keys[patch][tile] = min over the tile's nodes of that patch of
+// -ln(1 - u0) (FP32 bits, +inf when the tile has none); keys preset to +inf.
+hipError_t launch_item_keys(const int16_t *code, const double *u0, const int32_t n[3],
+                            const int32_t tile[3], const int32_t ntile[3], uint32_t *keys,
+                            hipStream_t s);
 hipError_t launch_tile_bits(int dim, const int16_t *code, const int32_t n[3], const int32_t tile[3],
                             const int32_t ntile[3], int words, uint32_t *bits, hipStream_t s);
 hipError_t launch_init_values(bool fp64, const int16_t *code, size_t N, void *v, hipStream_t s);

@@ -152,6 +152,7 @@ struct SolveConfig {
   bool async = false;  // HJB_SCHED_ASYNC: one persistent launch, device work queue
   double cone_r = 0.0; // add-on AO3 reduction factor r (> 1: control cones on)
   bool dbc = false;    // HJB_BC_DIRICHLET: patch boundaries hold U^(0)
+  double win_dt = 0.0; // add-on AO2 ordering window per round (> 0: on)
   double tol = 0.0;
   long long max_rounds = 1000000;
 };
@@ -164,6 +165,7 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
 struct ProblemItems {
   std::vector<Item> items;       // prob field is set by the engine
   DBuf item_map;                 // [n_patches][ntiles] local id or -1
+  DBuf item_key;                 // [n_patches][ntiles] FP32 keys of the ordered schedule
   std::vector<int32_t> seeds;    // local ids of the items that can change first
   int ntile[3] = {1, 1, 1};
   int n_patches = 1;
@@ -171,6 +173,9 @@ struct ProblemItems {
 
 ProblemItems build_items(const ProblemDev &P, const int16_t *code, int n_patches, SweepShape sh,
                          hipStream_t s);
+// Keys of the value-ordered schedule (add-on AO2) from the Step 2 values.
+void build_item_keys(const ProblemDev &P, const int16_t *code, const double *u0, SweepShape sh,
+                     ProblemItems &items, hipStream_t s);
 
 // Control cones of add-on AO3: for every feedback control ks, the controls
 // a_k with a_k . a_ks >= cos(pi / r) (ks itself always), in index order,
@@ -209,6 +214,8 @@ class SweepEngine {
   // Adds a problem; returns its index.  `v`, `code` and the inputs are on
   // the device.
   // `dbc` (optional, FP64 [N]): Dirichlet data of the patch boundaries.
+  // With items->item_key set and cfg.win_dt > 0 the problem's items run in
+  // the value-ordered schedule.
   int add_problem(const ProblemDev &P, const int16_t *code, const ProblemItems *items, void *v,
                   const double *dbc = nullptr);
   // Uploads the tables and queues `seeds` (global ids) or, when null, the
@@ -292,7 +299,7 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
 int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *v, bool fp64,
                  const hjb_solve_opts *opts, double tol, int32_t max_sweeps, hipStream_t s,
                  hjb_stats *st, double t0, const ConeArgs *cone = nullptr,
-                 const double *dbc = nullptr);
+                 const double *dbc = nullptr, const double *u0 = nullptr);
 
 // Plain Jacobi on the whole grid (one launch per sweep).
 int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out, double tol,

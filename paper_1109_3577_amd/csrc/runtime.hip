@@ -395,6 +395,10 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
                 "unknown patch_bc %d", opts->patch_bc);
     c.dbc = opts->patch_bc == HJB_BC_DIRICHLET;
     c.cone_r = opts->control_cone > 1.0 ? opts->control_cone : 0.0;
+    HJB_REQUIRE(std::isfinite(opts->order_window) && opts->order_window >= 0.0,
+                "order_window must be finite and >= 0");
+    c.win_dt = opts->order_window;
+    HJB_REQUIRE(c.win_dt == 0.0 || !c.async, "order_window needs the rounds schedule");
     if (c.cone_r > 0.0) {
       // fewer controls per update: longer in-tile runs pay off in 2D
       if (dim == 2 && opts->inner_sweeps <= 0) c.inner_sweeps = 16;
@@ -463,6 +467,17 @@ ProblemItems build_items(const ProblemDev &P, const int16_t *code, int n_patches
   return pi;
 }
 
+void build_item_keys(const ProblemDev &P, const int16_t *code, const double *u0, SweepShape sh,
+                     ProblemItems &items, hipStream_t s) {
+  const int ntiles = items.ntile[0] * items.ntile[1] * items.ntile[2];
+  const size_t cnt = (size_t)items.n_patches * ntiles;
+  items.item_key.reset(cnt * sizeof(float));
+  HJB_HIP(launch_fill_u32(items.item_key.as<uint32_t>(), 0x7f800000u, cnt, s));
+  const int32_t n3[3] = {P.n[0], P.n[1], P.n[2]};
+  const int32_t t3[3] = {sh.tx, sh.ty, P.dim == 3 ? sh.tz : 1};
+  HJB_HIP(launch_item_keys(code, u0, n3, t3, items.ntile, items.item_key.as<uint32_t>(), s));
+}
+
 SweepEngine::SweepEngine(const SolveConfig &cfg, hipStream_t s) : cfg_(cfg), s_(s) {
   count_.reset(4 * sizeof(uint32_t));
   host_ = std::make_unique<PinnedBuf>(4096);
@@ -504,6 +519,11 @@ int SweepEngine::add_problem(const ProblemDev &P, const int16_t *code, const Pro
   d.code = code;
   d.v = v;
   d.u0 = dbc;
+  if (cfg_.win_dt > 0.0 && items->item_key.get()) {
+    // the window is given in time steps h = -ln(beta) of the scheme
+    d.item_key = items->item_key.as<float>();
+    d.win_dt = (float)(cfg_.win_dt * -std::log(P.beta));
+  }
   d.item_map = items->item_map.as<int32_t>();
   d.item_base = (int32_t)items_h_.size();
   bases_.push_back(d.item_base);
@@ -521,11 +541,23 @@ void SweepEngine::begin(const std::vector<int32_t> *seeds) {
   const size_t np = dps_.size();
   counters_.reset(std::max<size_t>(np, 1) * kCounterWords * sizeof(unsigned long long));
   HJB_HIP(hipMemsetAsync(counters_.get(), 0, counters_.bytes(), s_));
+  std::vector<uint32_t> winit(6 * np);  // copied from before the final synchronisation
   for (size_t i = 0; i < np; ++i) {
     unsigned long long *c = counters_.as<unsigned long long>() + i * kCounterWords;
     dps_[i].residual = c;                                             // [3][kSlots]
     dps_[i].pactive = reinterpret_cast<uint32_t *>(c + 3 * kSlots);   // 3 x u32
     dps_[i].work = c + 3 * kSlots + 2;                                // [2][kSlots]
+    if (dps_[i].item_key) {
+      // round 0: base win_dt, smallest queued key 0 (seeds lie at the target)
+      dps_[i].win = reinterpret_cast<uint32_t *>(c + 5 * kSlots + 2);  // [6]
+      uint32_t *w0 = &winit[6 * i];
+      const float b0 = dps_[i].win_dt;
+      std::memcpy(&w0[0], &b0, sizeof b0);
+      w0[1] = w0[2] = 0u;
+      w0[3] = 0u;
+      w0[4] = w0[5] = 0x7f800000u;
+      HJB_HIP(hipMemcpyAsync(dps_[i].win, w0, 6 * sizeof(uint32_t), hipMemcpyHostToDevice, s_));
+    }
   }
   probs_d_.reset(std::max<size_t>(np, 1) * sizeof(DevProblem));
   HJB_HIP(hipMemcpyAsync(probs_d_.get(), dps_.data(), np * sizeof(DevProblem),

@@ -174,7 +174,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
   // only the bricks on them need the first sweep.
   constexpr int CENTER = (DIM == 3) ? 13 : 4;
   uint32_t first = ~0u;
-  if (fl != 0u && !(fl & (1u << CENTER))) {
+  if (fl != 0u && !(fl & ((1u << CENTER) | kFlagFull))) {
     first = 0u;
     for (uint32_t f = fl; f; f &= f - 1u) {
       const int d = __builtin_ctz(f);
@@ -420,6 +420,9 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
           }
         } else if (l >= 0 && atomicOr(&ra.flags_out[P.item_base + l], side) == 0u) {
           it2 = P.item_base + l;
+          if (P.item_key)
+            atomicMin(&P.win[3 + (ra.round + 1) % 3],
+                      __float_as_uint(P.item_key[(size_t)patch * ntiles + t2]));
         }
       }
     }
@@ -427,6 +430,31 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
   }
   (void)item_id;
   return converged;
+}
+
+// Value-ordered schedule: the threshold of round r is the larger of its
+// base and the smallest key queued for it; block 0 sets the base of round
+// r + 1 to that threshold plus win_dt and clears the minimum of round r + 2
+// (neither slot is read in round r).
+__device__ __forceinline__ float window_threshold(const DevProblem &P, uint32_t r) {
+  return fmaxf(__uint_as_float(P.win[r % 3]), __uint_as_float(P.win[3 + r % 3]));
+}
+
+__device__ __forceinline__ void window_advance(const DevProblem &P, uint32_t r) {
+  P.win[(r + 1) % 3] = __float_as_uint(window_threshold(P, r) + P.win_dt);
+  P.win[3 + (r + 2) % 3] = 0x7f800000u;
+}
+
+// Carries item `it` (not run in round r) to the next round's list with its
+// pending sides, and records its key.  One thread.
+__device__ __forceinline__ void window_defer(const DevProblem &P, const RoundArgs &ra, int it,
+                                             uint32_t fl, float key) {
+  if (atomicOr(&ra.flags_out[it], fl ? fl : kFlagFull) == 0u) {
+    const uint32_t slot = atomicAdd(&ra.count[(ra.round + 1) % 3], 1u);
+    ra.list_out[slot] = it;
+    atomicAdd(&P.pactive[(ra.round + 1) % 3], 1u);
+  }
+  atomicMin(&P.win[3 + (ra.round + 1) % 3], __float_as_uint(key));
 }
 
 template <typename T, int DIM, int TX, int TY, int TZ, int NT>
@@ -446,7 +474,10 @@ k_sweep(const DevProblem *__restrict__ probs, const Item *__restrict__ items, Ro
     if (threadIdx.x == 0) ra.count[(r + 2) % 3] = 0u;
     for (int p = threadIdx.x; p < ra.nprob * kSlots; p += NT) {
       const int q = p / kSlots, k = p % kSlots;
-      if (k == 0) probs[q].pactive[(r + 2) % 3] = 0u;
+      if (k == 0) {
+        probs[q].pactive[(r + 2) % 3] = 0u;
+        if (probs[q].item_key) window_advance(probs[q], r);
+      }
       probs[q].residual[((r + 2) % 3) * kSlots + k] = 0ull;
     }
   }
@@ -458,6 +489,14 @@ k_sweep(const DevProblem *__restrict__ probs, const Item *__restrict__ items, Ro
     const uint32_t fl = ra.flags_in[it];
     __syncthreads();  // every thread has read the flag before it is cleared
     if (threadIdx.x == 0) ra.flags_in[it] = 0u;
+    if (P.item_key) {
+      const int ntiles = P.ntile[0] * P.ntile[1] * P.ntile[2];
+      const float key = P.item_key[(size_t)item.patch * ntiles + item.tile];
+      if (key > window_threshold(P, r)) {
+        if (threadIdx.x == 0) window_defer(P, ra, it, fl, key);
+        continue;
+      }
+    }
     if (P.has_drift)
       sweep_item<T, DIM, TX, TY, TZ, NT, true, false>(P, item, it, fl, ra, AsyncQ{}, s_v, s_int,
                                                       s_red, s_wrk, s_msk);
@@ -490,7 +529,10 @@ k_sweep_cone(const DevProblem *__restrict__ probs, const Item *__restrict__ item
   if (blockIdx.x == 0) {
     if (threadIdx.x == 0) ra.count[(r + 2) % 3] = 0u;
     for (int k = threadIdx.x; k < kSlots; k += NT) {
-      if (k == 0) P.pactive[(r + 2) % 3] = 0u;
+      if (k == 0) {
+        P.pactive[(r + 2) % 3] = 0u;
+        if (P.item_key) window_advance(P, r);
+      }
       P.residual[((r + 2) % 3) * kSlots + k] = 0ull;
     }
   }
@@ -514,6 +556,14 @@ k_sweep_cone(const DevProblem *__restrict__ probs, const Item *__restrict__ item
     const uint32_t fl = ra.flags_in[it];
     __syncthreads();  // flag read by every thread (and, first, the tables staged)
     if (threadIdx.x == 0) ra.flags_in[it] = 0u;
+    if (P.item_key) {
+      const int ntiles = P.ntile[0] * P.ntile[1] * P.ntile[2];
+      const float key = P.item_key[(size_t)item.patch * ntiles + item.tile];
+      if (key > window_threshold(P, r)) {
+        if (threadIdx.x == 0) window_defer(P, ra, it, fl, key);
+        continue;
+      }
+    }
     if (P.has_drift)
       sweep_item<T, DIM, TX, TY, TZ, NT, true, false, true>(P, item, it, fl, ra, AsyncQ{}, s_v,
                                                             s_int, s_red, s_wrk, s_msk, s_cone);
@@ -780,6 +830,33 @@ k_tile_bits(const int16_t *__restrict__ code, int n0, int n1, int n2, int tx, in
   }
   __syncthreads();
   for (int w = threadIdx.x; w < words; w += blockDim.x) bits[(size_t)t * words + w] = row[w];
+}
+
+__global__ void __launch_bounds__(256)
+k_item_keys(const int16_t *__restrict__ code, const double *__restrict__ u0, int n0, int n1,
+            int n2, int tx, int ty, int tz, int nt0, int nt1, int ntiles, uint32_t *keys) {
+  const size_t N = (size_t)n0 * n1 * n2;
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < N;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const int cd = code[g];
+    if (cd < 0) continue;
+    const int x = (int)(g % n0), y = (int)((g / n0) % n1), z = (int)(g / ((size_t)n0 * n1));
+    const int t = x / tx + nt0 * (y / ty + nt1 * (z / tz));
+    const double u = u0[g];
+    const float key = u < 1.0 ? (float)(-log1p(-u)) : __int_as_float(0x7f800000);
+    atomicMin(&keys[(size_t)cd * ntiles + t], __float_as_uint(key > 0.0f ? key : 0.0f));
+  }
+}
+
+hipError_t launch_item_keys(const int16_t *code, const double *u0, const int32_t n[3],
+                            const int32_t tile[3], const int32_t ntile[3], uint32_t *keys,
+                            hipStream_t s) {
+  const size_t N = (size_t)n[0] * n[1] * n[2];
+  const int grid = (int)std::min<size_t>((N + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_item_keys, dim3(grid), dim3(256), 0, s, code, u0, n[0], n[1], n[2],
+                     tile[0], tile[1], tile[2], ntile[0], ntile[1],
+                     ntile[0] * ntile[1] * ntile[2], keys);
+  return hipGetLastError();
 }
 
 hipError_t launch_tile_bits(int dim, const int16_t *code, const int32_t n[3], const int32_t tile[3],
