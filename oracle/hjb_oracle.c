@@ -106,6 +106,9 @@ typedef struct {
    * section): when u0 != NULL, a box node outside the active set reads
    * u0[q] instead of the ghost value 1. */
   const double *u0;
+  /* Add-on AO1: the iteration is v <- F(v) from a given start (no min with
+   * the old value), for starts that are not above the fixed point. */
+  int plain;
 } orc_active;
 
 static long long orc_N(const orc_problem *P) {
@@ -271,8 +274,8 @@ static int orc_jacobi(const orc_problem *P, const orc_active *A, const long long
       long long q = nodes[i];
       long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
       double f = orc_F_node(P, v, A, q, x, y, z);
-      double nv = f < v[q] ? f : v[q];
-      double dlt = v[q] - nv;
+      double nv = (A && A->plain) ? f : (f < v[q] ? f : v[q]);
+      double dlt = fabs(v[q] - nv);
       if (dlt > res) res = dlt;
       vn[q] = nv;
     }
@@ -550,11 +553,15 @@ int orc_cone_allowed(const orc_problem *P, double r, uint8_t *allow) {
  * nodes are ghosts of value 1) or, with u0 != NULL, the Dirichlet data of
  * eq. dbc (they hold u0).  With fb != NULL and cone_r > 1, each node keeps
  * only the controls of add-on AO3 around its feedback control fb[q]
- * (orc_cone_allowed); `updates` then counts the controls evaluated. */
+ * (orc_cone_allowed); `updates` then counts the controls evaluated.  With
+ * init != NULL (add-on AO1) the patch nodes start at init and iterate
+ * v <- F(v) until no node moves by more than tol (> 0) in a sweep. */
 int orc_solve_patches_ex(const orc_problem *F, const int16_t *labels, const uint8_t *fb,
-                         double cone_r, const double *u0, double tol, int max_sweeps,
-                         int only_patch, double *v, int *sweeps_per_patch, long long *updates) {
+                         double cone_r, const double *u0, const double *init, double tol,
+                         int max_sweeps, int only_patch, double *v, int *sweeps_per_patch,
+                         long long *updates) {
   if (orc_check(F) || F->n_parts < 1) return ORC_EINVAL;
+  if (init && !(tol > 0.0)) return ORC_EINVAL;
   uint8_t *allow = NULL;
   long long *row_cnt = NULL;
   if (fb && cone_r > 1.0) {
@@ -602,7 +609,9 @@ int orc_solve_patches_ex(const orc_problem *F, const int16_t *labels, const uint
     /* Patch-local iterate: target 0, patch nodes 1; other nodes are ghosts
      * (never read as values, see orc_corner). */
     for (long long q = 0; q < N; ++q) work[q] = (F->target_part[q] >= 0) ? 0.0 : 1.0;
-    orc_active A = {labels, j, fb, allow, u0};
+    if (init)
+      for (long long i = start[j]; i < start[j] + cnt[j]; ++i) work[nodes[i]] = init[nodes[i]];
+    orc_active A = {labels, j, fb, allow, u0, init != NULL};
     int sw = 0;
     int r = orc_jacobi(F, &A, nodes + start[j], cnt[j], tol, max_sweeps, work, &sw, NULL);
     if (r != ORC_OK) rc = r;
@@ -623,7 +632,7 @@ int orc_solve_patches_ex(const orc_problem *F, const int16_t *labels, const uint
 /* Public: Steps 3.2 + 4 of the basic algorithm (every control). */
 int orc_solve_patches(const orc_problem *F, const int16_t *labels, double tol, int max_sweeps,
                       int only_patch, double *v, int *sweeps_per_patch, long long *updates) {
-  return orc_solve_patches_ex(F, labels, NULL, 0.0, NULL, tol, max_sweeps, only_patch, v,
+  return orc_solve_patches_ex(F, labels, NULL, 0.0, NULL, NULL, tol, max_sweeps, only_patch, v,
                               sweeps_per_patch, updates);
 }
 

@@ -62,7 +62,7 @@ def lib():
         L.orc_trace_part.argtypes = [vp, vp, i32, i32, vp, vp]
         L.orc_labels.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.orc_solve_patches.argtypes = [vp, vp, d, i32, i32, vp, vp, vp]
-        L.orc_solve_patches_ex.argtypes = [vp, vp, vp, d, vp, d, i32, i32, vp, vp, vp]
+        L.orc_solve_patches_ex.argtypes = [vp, vp, vp, d, vp, vp, d, i32, i32, vp, vp, vp]
         L.orc_cone_allowed.argtypes = [vp, d, vp]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
@@ -240,22 +240,25 @@ def cone_allowed(fine, r: float):
 
 def solve_patches_ex(fine, labels_: np.ndarray, fb: Optional[np.ndarray] = None, r: float = 0.0,
                      u0: Optional[np.ndarray] = None, tol: float = 0.0,
-                     max_sweeps: int = 1_000_000, only_patch: int = -1):
+                     max_sweeps: int = 1_000_000, only_patch: int = -1,
+                     init: Optional[np.ndarray] = None):
     """Steps 3.2 and 4 with the options of the paper's add-ons section:
     add-on AO3 (fb, r > 1: each node minimises over the controls in the cone
-    of half-angle pi/r around its Step 2 feedback control) and the Dirichlet
+    of half-angle pi/r around its Step 2 feedback control), the Dirichlet
     patch boundary data of eq. dbc (u0: other patches' nodes hold U^(0)
-    instead of the ghost value 1)."""
+    instead of the ghost value 1) and add-on AO1 (init: start values of the
+    patch nodes, iteration v <- F(v), tol > 0)."""
     H = _Held(fine)
     lab = np.ascontiguousarray(labels_, dtype=np.int16).ravel()
     fbc = None if fb is None else np.ascontiguousarray(fb, dtype=np.uint8).ravel()
     u0c = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64).ravel()
+    inc = None if init is None else np.ascontiguousarray(init, dtype=np.float64).ravel()
     v = np.empty(fine.N, dtype=np.float64)
     sw = np.zeros(max(1, fine.n_parts), dtype=np.int32)
     upd = C.c_longlong(0)
-    _check(lib().orc_solve_patches_ex(H.ref, _p(lab), _p(fbc), float(r), _p(u0c), float(tol),
-                                      int(max_sweeps), int(only_patch), _p(v), _p(sw),
-                                      C.byref(upd)), "solve_patches_ex")
+    _check(lib().orc_solve_patches_ex(H.ref, _p(lab), _p(fbc), float(r), _p(u0c), _p(inc),
+                                      float(tol), int(max_sweeps), int(only_patch), _p(v),
+                                      _p(sw), C.byref(upd)), "solve_patches_ex")
     return v, dict(sweeps=sw, updates=upd.value)
 
 

@@ -654,3 +654,58 @@ def test_dbc_wrong_decomposition_matches_u0_accuracy(orc, pr):
     e_u0 = np.abs(out["u0"] - vg).mean()
     assert np.abs(vd - vg).mean() <= 1.1 * e_u0
     assert np.abs(vs - vg).mean() > 5.0 * e_u0
+
+
+# ------------------------------------------------------------ add-on AO1
+
+def test_ao1_start_at_fixed_point(orc, pr):
+    """Add-on AO1 (start from given values, iterate v <- F(v)): started at
+    the fixed point, one sweep per patch changes nothing."""
+    f, c = pr.variable_speed_2d(0, 65, 17, 32, 6, 0.1, True)
+    out = orc.patchy(f, c)
+    v, st = orc.solve_patches_ex(f, out["labels"], tol=1e-12, init=out["v"])
+    assert np.array_equal(v, out["v"])
+    assert np.all(st["sweeps"][:6] == 1)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_ao1_from_u0_converges(orc, pr, seed):
+    """From U^(0) the plain iteration reaches the fixed point of the basic
+    scheme within the contraction bound tol * beta / (1 - beta)."""
+    f, c = pr.variable_speed_2d(seed, 97, 17, 32, 8, 0.1, True)
+    out = orc.patchy(f, c)
+    for tol in (1e-7, 1e-10):
+        v0, _ = orc.solve_patches_ex(f, out["labels"], tol=tol, init=out["u0"])
+        assert np.abs(v0 - out["v"]).max() <= tol * f.beta / (1.0 - f.beta)
+
+
+def test_ao1_saves_sweeps_on_average(orc, pr):
+    """Add-ons section, Table addons: AO1 saves a few iterations.  Summed
+    over six seeded problems the patch sweeps from U^(0) are fewer than from
+    1 (on a single problem they need not be)."""
+    a = b = 0
+    for seed in range(6):
+        f, c = pr.variable_speed_2d(seed, 97, 17, 32, 8, 0.1, True)
+        out = orc.patchy(f, c)
+        _, s1 = orc.solve_patches_ex(f, out["labels"], tol=1e-7)
+        _, s0 = orc.solve_patches_ex(f, out["labels"], tol=1e-7, init=out["u0"])
+        a += int(s1["sweeps"].sum())
+        b += int(s0["sweeps"].sum())
+    assert b < a
+
+
+def test_ao1_from_below_rises(orc, pr):
+    """The AO1 iteration has no min with the old value: started below the
+    fixed point (every patch node 0) it rises to it."""
+    f, c = pr.variable_speed_2d(1, 65, 17, 32, 4, 0.1, True)
+    out = orc.patchy(f, c)
+    v, _ = orc.solve_patches_ex(f, out["labels"], tol=1e-10, init=np.zeros(f.N))
+    assert np.abs(v - out["v"]).max() <= 1e-10 * f.beta / (1.0 - f.beta)
+    assert out["v"].max() > 0.5
+
+
+def test_ao1_needs_tolerance(orc, pr):
+    f, c = pr.variable_speed_2d(1, 33, 17, 8, 2, 0.2, True)
+    out = orc.patchy(f, c)
+    with pytest.raises(RuntimeError):
+        orc.solve_patches_ex(f, out["labels"], tol=0.0, init=out["u0"])
