@@ -190,6 +190,15 @@ typedef struct {
                               (h = -ln beta).  The fixed point (and so the
                               result, bit for bit) is the same; only the
                               order and the work change.  0 = off. */
+  int32_t start_u0;        /* add-on AO1 (same section), hjb_solve_patches
+                              only, rounds schedule: 1 starts every patch
+                              node at U^(0) of Step 2.  U^(0) is not above
+                              the fixed point, so the iteration becomes
+                              v <- F(v) (values may rise) and stops when no
+                              node moves by more than tol, which must be at
+                              least 1e-7 in FP32 and 1e-13 in FP64; the
+                              result then lies within about
+                              tol beta / (1 - beta) of the fixed point. */
 } hjb_solve_opts;
 
 typedef struct hjb_coarse_s hjb_coarse_t;

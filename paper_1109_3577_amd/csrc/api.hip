@@ -39,8 +39,9 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
                  const hjb_solve_opts *opts, double tol, int32_t max_sweeps, hipStream_t s,
                  hjb_stats *st, double t0, const ConeArgs *cone, const double *dbc,
                  const double *u0) {
-  HJB_HIP(launch_init_values(fp64, code, P.N, v, s));
   const SolveConfig cfg = make_config(P.dim, fp64, opts, tol, max_sweeps);
+  HJB_REQUIRE(!cfg.start_u0 || u0 != nullptr, "start_u0 needs the Step 2 values");
+  HJB_HIP(launch_init_values(fp64, code, P.N, v, s, cfg.start_u0 ? u0 : nullptr));
   HJB_REQUIRE((cfg.cone_r > 0.0) == (cone != nullptr), "control cone tables missing");
   HJB_REQUIRE(cfg.dbc == (dbc != nullptr), "patch boundary data missing");
   HJB_REQUIRE(cfg.win_dt == 0.0 || u0 != nullptr, "order_window needs the Step 2 values");
@@ -49,7 +50,14 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
   SweepEngine eng(cfg, s);
   eng.add_problem(P, code, &items, v, dbc);
   if (cone) eng.set_cone(*cone);
-  eng.begin();
+  if (cfg.start_u0) {
+    // every item starts away from its fixed point
+    std::vector<int32_t> all((size_t)eng.total_items());
+    for (size_t i = 0; i < all.size(); ++i) all[i] = (int32_t)i;
+    eng.begin(&all);
+  } else {
+    eng.begin();
+  }
   const int status = eng.async_ok() ? eng.run_async() : eng.run();
   if (st) {
     const EngineResult r = eng.results()[0];
@@ -446,6 +454,8 @@ int hjb_solve_global(const hjb_problem *fine, int32_t precision, double tol, int
                 "patch_bc applies to patch solves (the global solve has no patches)");
     HJB_REQUIRE(!opts || opts->order_window == 0.0,
                 "order_window needs the Step 2 values (hjb_solve_patches only)");
+    HJB_REQUIRE(!opts || opts->start_u0 == 0,
+                "start_u0 needs the Step 2 values (hjb_solve_patches only)");
     const int sched = opts ? opts->schedule : HJB_SCHED_TILED;
     if (sched == HJB_SCHED_JACOBI) {
       (void)make_config(P->dim, fp64, opts, tol, max_sweeps);  // validates opts and tol

@@ -77,6 +77,7 @@ SweepShape engine_shape(int dim, bool fp64, const hjb_solve_opts *opts) {
               "control_cone is an option of hjb_solve_patches only");
   HJB_REQUIRE(!opts || opts->order_window == 0.0,
               "order_window is an option of hjb_solve_patches only");
+  HJB_REQUIRE(!opts || opts->start_u0 == 0, "start_u0 is an option of hjb_solve_patches only");
   return make_config(dim, fp64, opts, 0.0, 0).shape;
 }
 

@@ -82,7 +82,7 @@ struct DevProblem {
   const float *item_key;  // [n_patches][ntiles] (like item_map)
   uint32_t *win;          // [6]
   float win_dt;
-  int32_t pad3;
+  int32_t plain;          // add-on AO1: v <- F(v) from U^(0) (updates may rise)
 };
 
 struct Item {
@@ -174,7 +174,9 @@ hipError_t launch_item_keys(const int16_t *code, const double *u0, const int32_t
                             hipStream_t s);
 hipError_t launch_tile_bits(int dim, const int16_t *code, const int32_t n[3], const int32_t tile[3],
                             const int32_t ntile[3], int words, uint32_t *bits, hipStream_t s);
-hipError_t launch_init_values(bool fp64, const int16_t *code, size_t N, void *v, hipStream_t s);
+// v = 0 on the target, `start` (when given) on patch nodes, 1 elsewhere.
+hipError_t launch_init_values(bool fp64, const int16_t *code, size_t N, void *v, hipStream_t s,
+                              const double *start = nullptr);
 hipError_t launch_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_scaled_f32(const double *src, float *dst, size_t rows, int dim,
                              const double step[3], hipStream_t s);

@@ -153,6 +153,7 @@ struct SolveConfig {
   double cone_r = 0.0; // add-on AO3 reduction factor r (> 1: control cones on)
   bool dbc = false;    // HJB_BC_DIRICHLET: patch boundaries hold U^(0)
   double win_dt = 0.0; // add-on AO2 ordering window per round (> 0: on)
+  bool start_u0 = false; // add-on AO1: start at U^(0), plain v <- F(v)
   double tol = 0.0;
   long long max_rounds = 1000000;
 };

@@ -399,6 +399,14 @@ SolveConfig make_config(int dim, bool fp64, const hjb_solve_opts *opts, double t
                 "order_window must be finite and >= 0");
     c.win_dt = opts->order_window;
     HJB_REQUIRE(c.win_dt == 0.0 || !c.async, "order_window needs the rounds schedule");
+    HJB_REQUIRE(opts->start_u0 == 0 || opts->start_u0 == 1, "start_u0 must be 0 or 1");
+    c.start_u0 = opts->start_u0 == 1;
+    if (c.start_u0) {
+      HJB_REQUIRE(!c.async, "start_u0 needs the rounds schedule");
+      HJB_REQUIRE(tol >= (fp64 ? 1e-13 : 1e-7),
+                  "start_u0 needs tol >= %g (the iteration from U^(0) is not monotone)",
+                  fp64 ? 1e-13 : 1e-7);
+    }
     if (c.cone_r > 0.0) {
       // fewer controls per update: longer in-tile runs pay off in 2D
       if (dim == 2 && opts->inner_sweeps <= 0) c.inner_sweeps = 16;
@@ -519,6 +527,7 @@ int SweepEngine::add_problem(const ProblemDev &P, const int16_t *code, const Pro
   d.code = code;
   d.v = v;
   d.u0 = dbc;
+  d.plain = cfg_.start_u0 ? 1 : 0;
   if (cfg_.win_dt > 0.0 && items->item_key.get()) {
     // the window is given in time steps h = -ln(beta) of the scheme
     d.item_key = items->item_key.as<float>();

@@ -198,6 +198,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
   const T beta = sizeof(T) == 4 ? (T)P.betaf : (T)P.beta;
   const T omb = sizeof(T) == 4 ? (T)P.ombf : (T)P.omb;
   const T tolT = (T)ra.tol;
+  const bool plain = P.plain != 0;
   const int ng = (P.nc + 3) >> 2;  // groups of 4 controls (table is padded)
   const int K = ra.inner_sweeps;
   unsigned long long upd = 0;
@@ -308,12 +309,14 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
       bool chg = false;
       if (act[j]) {
         // min_k (beta I_k + omb) == beta (min_k I_k) + omb: the map is
-        // monotone, also after rounding.
+        // monotone, also after rounding.  The iteration only decreases
+        // v, except from a start below the fixed point (add-on AO1: plain
+        // v <- F(v)).
         const T cand = Ar<T>::kruzkov(beta, mI, omb);
         const T cur = s_v[off[j]];
-        if (cand < cur) {
+        if (plain ? cand != cur : cand < cur) {
           s_v[off[j]] = cand;
-          chg = cur - cand > tolT;
+          chg = cur - cand > tolT || cand - cur > tolT;
         }
       }
       if (__ballot(chg) != 0ull) mine |= 1u << (wave + j * NW);
@@ -336,12 +339,12 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
     bool big = false;
     if (act[j]) {
       const T nv = s_v[off[j]];
-      if (nv < old[j]) {
+      if (nv != old[j]) {
         if (ASYNC) st_dev(&v[gid[j]], nv);
         else v[gid[j]] = nv;
-        const double dd = (double)old[j] - (double)nv;
+        const double dd = fabs((double)old[j] - (double)nv);
         dmax = dd > dmax ? dd : dmax;
-        big = old[j] - nv > tolT;
+        big = old[j] - nv > tolT || nv - old[j] > tolT;
       }
     }
     brick_box<DIM, NBX, NBY>(__ballot(big), wave + j * NW, bx0, bx1, by0, by1, bz0, bz1);
@@ -870,15 +873,24 @@ hipError_t launch_tile_bits(int dim, const int16_t *code, const int32_t n[3], co
 }
 
 template <typename T>
-__global__ void k_init_values(const int16_t *__restrict__ code, size_t N, T *v) {
+__global__ void k_init_values(const int16_t *__restrict__ code, size_t N, T *v,
+                              const double *__restrict__ start) {
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < N) v[g] = code[g] == CODE_TARGET ? T(0) : T(1);
+  if (g < N) {
+    const int cd = code[g];
+    v[g] = cd == CODE_TARGET ? T(0) : ((start && cd >= 0) ? (T)start[g] : T(1));
+  }
 }
 
-hipError_t launch_init_values(bool fp64, const int16_t *code, size_t N, void *v, hipStream_t s) {
+hipError_t launch_init_values(bool fp64, const int16_t *code, size_t N, void *v, hipStream_t s,
+                              const double *start) {
   const unsigned grid = (unsigned)((N + 255) / 256);
-  if (fp64) hipLaunchKernelGGL(k_init_values<double>, dim3(grid), dim3(256), 0, s, code, N, (double *)v);
-  else hipLaunchKernelGGL(k_init_values<float>, dim3(grid), dim3(256), 0, s, code, N, (float *)v);
+  if (fp64)
+    hipLaunchKernelGGL(k_init_values<double>, dim3(grid), dim3(256), 0, s, code, N, (double *)v,
+                       start);
+  else
+    hipLaunchKernelGGL(k_init_values<float>, dim3(grid), dim3(256), 0, s, code, N, (float *)v,
+                       start);
   return hipGetLastError();
 }
 

@@ -63,7 +63,8 @@ class hjb_solve_opts(C.Structure):
                 ("rounds_per_poll", C.c_int32), ("schedule", C.c_int32),
                 ("time_kernels", C.c_int32), ("use_graph", C.c_int32), ("threads", C.c_int32),
                 ("patch_select", C.c_void_p), ("control_cone", C.c_double),
-                ("patch_bc", C.c_int32), ("order_window", C.c_double)]
+                ("patch_bc", C.c_int32), ("order_window", C.c_double),
+                ("start_u0", C.c_int32)]
 
 
 class hjb_batch_opts(C.Structure):
@@ -201,7 +202,8 @@ def _as_problem(p, device=False) -> Problem:
 
 def make_opts(tile=None, inner_sweeps=0, rounds_per_poll=0, schedule=HJB_SCHED_TILED,
               time_kernels=False, use_graph=False, patch_select=None,
-              threads=0, control_cone=0.0, patch_bc=0, order_window=0.0) -> hjb_solve_opts:
+              threads=0, control_cone=0.0, patch_bc=0, order_window=0.0,
+              start_u0=False) -> hjb_solve_opts:
     o = hjb_solve_opts()
     if tile is not None:
         for k, t in enumerate(tile):
@@ -215,6 +217,7 @@ def make_opts(tile=None, inner_sweeps=0, rounds_per_poll=0, schedule=HJB_SCHED_T
     o.control_cone = float(control_cone)
     o.patch_bc = int(patch_bc)
     o.order_window = float(order_window)
+    o.start_u0 = int(bool(start_u0))
     if patch_select is not None:
         sel = np.ascontiguousarray(patch_select, dtype=np.uint8)
         o._sel = sel
