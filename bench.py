@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--no-global", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=100)
     ap.add_argument("--graph", type=int, default=0)
-    ap.add_argument("--no-ao3", action="store_true",
+    ap.add_argument("--no-addons", action="store_true",
                     help="skip the side measurement of the add-ons (dbc data, AO3 cones)")
     ap.add_argument("--ao3-r", type=float, default=4.0, help="AO3 reduction factor r")
     ap.add_argument("--mode", choices=("solve", "solve3d", "batch", "serve", "copy"), default="solve",
@@ -345,7 +345,7 @@ def main():
     # the Dirichlet patch data U^(0) (eq. dbc), AO3 (control cones of
     # half-angle pi/r around the Step 2 feedback) and both; kernel time of
     # each and its error against the global solution (when measured).
-    if not args.no_ao3:
+    if not args.no_addons:
         # AO2 window (time steps per round) and in-tile sweeps that suit it
         ao2 = {"order_window": 6.0} if dim == 2 else {"order_window": 2.5, "inner_sweeps": 4}
         dbc = {"patch_bc": hjb.HJB_BC_DIRICHLET}
