@@ -72,6 +72,11 @@
 /* pi to double precision (C99 has no M_PI) */
 #define ORC_PI 3.14159265358979323846
 
+/* target_part value of a node inside an obstacle (Section 4.5): a state
+ * constraint inside the box -- never updated, read as the ghost value (1 for
+ * v and U^(0), 0 for colours), label -2. */
+#define ORC_OBSTACLE (-2)
+
 #define ORC_OK 0
 #define ORC_EINVAL 1
 #define ORC_ENOCONV 4
@@ -131,6 +136,7 @@ static double orc_corner(const orc_problem *P, const double *v, const orc_active
                          long long x, long long y, long long z, double ghost) {
   if (x < 0 || y < 0 || z < 0 || x >= P->n[0] || y >= P->n[1] || z >= P->n[2]) return ghost;
   long long q = x + (long long)P->n[0] * (y + (long long)P->n[1] * z);
+  if (P->target_part[q] == ORC_OBSTACLE) return ghost;
   if (A) {
     int tp = P->target_part[q];
     if (tp < 0 && A->patch >= 0 && A->labels[q] != A->patch) return A->u0 ? A->u0[q] : ghost;
@@ -211,7 +217,7 @@ static double orc_F_node(const orc_problem *P, const double *v, const orc_active
 }
 
 static int orc_is_updated(const orc_problem *P, const orc_active *A, long long q) {
-  if (P->target_part[q] >= 0) return 0;
+  if (P->target_part[q] >= 0 || P->target_part[q] == ORC_OBSTACLE) return 0;
   if (A && A->patch >= 0 && A->labels[q] != A->patch) return 0;
   return 1;
 }
@@ -247,6 +253,7 @@ int orc_F_at(const orc_problem *P, const int16_t *labels, int patch, const doubl
     long long q = idx[i];
     long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
     if (P->target_part[q] >= 0) out[i] = 0.0;
+    else if (P->target_part[q] == ORC_OBSTACLE) out[i] = 1.0;
     else out[i] = orc_F_node(P, v, Ap, q, x, y, z);
   }
   return ORC_OK;
@@ -299,6 +306,7 @@ int orc_solve_global(const orc_problem *P, double tol, int max_sweeps, double *v
   if (!nodes) return ORC_ENOMEM;
   for (long long q = 0; q < N; ++q) {
     if (P->target_part[q] >= 0) v[q] = 0.0;
+    else if (P->target_part[q] == ORC_OBSTACLE) v[q] = 1.0;
     else { v[q] = 1.0; nodes[cnt++] = q; }
   }
   int sw = 0;
@@ -311,7 +319,8 @@ int orc_solve_global(const orc_problem *P, double tol, int max_sweeps, double *v
 
 /* Public: Step 2, prolongation of the coarse values onto the fine grid.
  * Fine node p_d maps to coarse index coordinate X = p_d (nc_d-1) / (nf_d-1);
- * Q = min(floor X, nc_d - 2), T = X - Q; nested linear interpolation. */
+ * Q = min(floor X, nc_d - 2), T = X - Q; nested linear interpolation.
+ * Obstacle nodes of the fine grid get 1 (T = +inf). */
 int orc_prolong(const orc_problem *C, const double *vc, const orc_problem *F, double *u0) {
   if (orc_check(C) || orc_check(F) || C->dim != F->dim) return ORC_EINVAL;
   int dim = F->dim;
@@ -346,7 +355,8 @@ int orc_prolong(const orc_problem *C, const double *vc, const orc_problem *F, do
           val = orc_lin(T[2], rz[0], rz[1]);
         }
 #undef CV
-        u0[x + nf[0] * (y + nf[1] * z)] = val;
+        long long qf = x + nf[0] * (y + nf[1] * z);
+        u0[qf] = F->target_part[qf] == ORC_OBSTACLE ? 1.0 : val;
       }
   return ORC_OK;
 }
@@ -362,7 +372,7 @@ int orc_feedback(const orc_problem *F, const double *u0, uint8_t *fb) {
     for (long long y = 0; y < ny; ++y)
       for (long long x = 0; x < nx; ++x) {
         long long q = x + nx * (y + ny * z);
-        if (F->target_part[q] >= 0) { fb[q] = 255; continue; }
+        if (F->target_part[q] >= 0 || F->target_part[q] == ORC_OBSTACLE) { fb[q] = 255; continue; }
         double best = INFINITY;
         int bk = 0;
         for (int k = 0; k < F->n_controls; ++k) {
@@ -386,7 +396,7 @@ int orc_feedback_at(const orc_problem *F, const double *u0, const long long *idx
   for (long long i = 0; i < count; ++i) {
     long long q = idx[i];
     long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
-    if (F->target_part[q] >= 0) { fb[i] = 255; continue; }
+    if (F->target_part[q] >= 0 || F->target_part[q] == ORC_OBSTACLE) { fb[i] = 255; continue; }
     double best = INFINITY;
     int bk = 0;
     for (int k = 0; k < F->n_controls; ++k) {
@@ -415,6 +425,7 @@ int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sw
   for (long long q = 0; q < N; ++q) {
     int tp = F->target_part[q];
     if (tp >= 0) phi[q] = (tp == part) ? 1.0 : 0.0;
+    else if (tp == ORC_OBSTACLE) phi[q] = 0.0;
     else { phi[q] = 0.0; nodes[cnt++] = q; }
   }
   memcpy(pn, phi, sizeof(double) * (size_t)N);
@@ -454,13 +465,13 @@ int orc_fill_labels(const orc_problem *F, int16_t *labels, long long *filled) {
   int16_t *next = (int16_t *)malloc(sizeof(int16_t) * (size_t)N);
   if (!next) return ORC_ENOMEM;
   long long before = 0;
-  for (long long q = 0; q < N; ++q) before += labels[q] < 0;
+  for (long long q = 0; q < N; ++q) before += labels[q] == -1;
   int dz0 = nz > 1 ? -1 : 0, dz1 = nz > 1 ? 1 : 0;
   for (;;) {
     int changed = 0;
     memcpy(next, labels, sizeof(int16_t) * (size_t)N);
     for (long long q = 0; q < N; ++q) {
-      if (labels[q] >= 0) continue;
+      if (labels[q] != -1) continue;  /* labelled, or an obstacle (-2) */
       long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
       int best = -1;
       for (int dz = dz0; dz <= dz1; ++dz)
@@ -511,13 +522,31 @@ int orc_labels(const orc_problem *F, const uint8_t *fb, int max_sweeps, int16_t 
       if (phi[q] > best[q]) { best[q] = phi[q]; labels[q] = (int16_t)j; }
     }
   }
-  for (long long q = 0; q < N; ++q)
+  for (long long q = 0; q < N; ++q) {
     if (F->target_part[q] >= 0) labels[q] = F->target_part[q];
+    if (F->target_part[q] == ORC_OBSTACLE) labels[q] = ORC_OBSTACLE;
+  }
   if (max_trace_sweeps) *max_trace_sweeps = mx;
   free(phi);
   free(best);
   if (rc == ORC_OK) rc = orc_fill_labels(F, labels, unreached);
   return rc;
+}
+
+/* Public: exclusion of unreachable regions (Section 4.6): after Step 1, a
+ * fine node off the target whose U^(0) is at least `theta` is excluded
+ * from the rest of the computation, i.e. becomes an obstacle node:
+ * tp_out = target_part with ORC_OBSTACLE there.  u0 is the raw
+ * prolongation.  Returns the number of excluded nodes, or -1. */
+long long orc_exclude(const orc_problem *F, const double *u0, double theta, int16_t *tp_out) {
+  if (orc_check(F) || !(theta > 0.0)) return -1;
+  long long N = orc_N(F), cnt = 0;
+  for (long long q = 0; q < N; ++q) {
+    int tp = F->target_part[q];
+    if (tp == -1 && u0[q] >= theta) { tp_out[q] = ORC_OBSTACLE; ++cnt; }
+    else tp_out[q] = (int16_t)tp;
+  }
+  return cnt;
 }
 
 /* Public: the control sets of add-on AO3 (Section "Patchy method's
@@ -574,7 +603,9 @@ int orc_solve_patches_ex(const orc_problem *F, const int16_t *labels, const uint
       for (long long k = 0; k < nc; ++k) row_cnt[ks] += allow[ks * nc + k];
     long long Nf = orc_N(F);
     for (long long q = 0; q < Nf; ++q)
-      if (F->target_part[q] < 0 && fb[q] >= nc) { free(allow); free(row_cnt); return ORC_EINVAL; }
+      if (F->target_part[q] == -1 && labels[q] >= 0 && fb[q] >= nc) {
+        free(allow); free(row_cnt); return ORC_EINVAL;
+      }
   }
   long long N = orc_N(F);
   long long *cnt = (long long *)calloc((size_t)F->n_parts, sizeof(long long));

@@ -64,6 +64,8 @@ def lib():
         L.orc_solve_patches.argtypes = [vp, vp, d, i32, i32, vp, vp, vp]
         L.orc_solve_patches_ex.argtypes = [vp, vp, vp, d, vp, vp, d, i32, i32, vp, vp, vp]
         L.orc_cone_allowed.argtypes = [vp, d, vp]
+        L.orc_exclude.argtypes = [vp, vp, d, vp]
+        L.orc_exclude.restype = C.c_longlong
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -268,11 +270,33 @@ def solve_patches_cone(fine, labels_: np.ndarray, fb: np.ndarray, r: float, tol:
     return solve_patches_ex(fine, labels_, fb, r, None, tol, max_sweeps, only_patch)
 
 
-def patchy(fine, coarse, tol: float = 0.0, max_sweeps: int = 1_000_000):
-    """The whole Patchy Algorithm of Section 3, Steps 1-4."""
+def exclude(fine, u0: np.ndarray, theta: float):
+    """Section 4.6: fine nodes off the target with U^(0) >= theta become
+    obstacle nodes (-2).  Returns (new target_part, number excluded)."""
+    H = _Held(fine)
+    u0 = np.ascontiguousarray(u0, dtype=np.float64).ravel()
+    tp = np.empty(fine.N, dtype=np.int16)
+    n = lib().orc_exclude(H.ref, _p(u0), float(theta), _p(tp))
+    if n < 0:
+        raise RuntimeError("oracle exclude failed")
+    return tp, int(n)
+
+
+def patchy(fine, coarse, tol: float = 0.0, max_sweeps: int = 1_000_000,
+           exclude_at: Optional[float] = None):
+    """The whole Patchy Algorithm of Section 3, Steps 1-4.  With exclude_at,
+    the unreachable regions (U^(0) >= exclude_at) are dropped after Step 1
+    (Section 4.6) and become obstacle nodes of the fine problem."""
+    import dataclasses
     vc, cst = solve_global(coarse, 0.0, max_sweeps)
     u0 = prolong(coarse, vc, fine)
+    excluded = 0
+    if exclude_at is not None:
+        tp, excluded = exclude(fine, u0, exclude_at)
+        fine = dataclasses.replace(fine, target_part=tp)
+        u0 = prolong(coarse, vc, fine)
     fb = feedback(fine, u0)
     lab = labels(fine, fb, max_sweeps)
     v, st = solve_patches(fine, lab, tol, max_sweeps)
-    return dict(v=v, labels=lab, feedback=fb, u0=u0, v_coarse=vc, coarse_stats=cst, stats=st)
+    return dict(v=v, labels=lab, feedback=fb, u0=u0, v_coarse=vc, coarse_stats=cst, stats=st,
+                excluded=excluded, target_part=fine.target_part)

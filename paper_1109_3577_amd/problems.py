@@ -286,6 +286,35 @@ def line_target_2d(n: int = 41, nc: int = 32, col: Optional[int] = None, strips:
                  fp32, name, meta=dict(col=col))
 
 
+def with_obstacles(P: Problem, mask: np.ndarray, name: Optional[str] = None) -> Problem:
+    """A copy of P whose nodes in `mask` (off the target) are obstacle nodes
+    (target_part -2): a state constraint inside the box."""
+    tp = P.target_part.copy()
+    tp[np.asarray(mask).ravel() & (tp < 0)] = -2
+    return dataclasses.replace(P, target_part=tp, name=name or P.name + "-obst")
+
+
+def obstacle_mask_2d(X, Y, disc=(0.45, 0.3, 0.2), rect=(-0.75, -0.45, -0.6, 0.5)):
+    """One disc (cx, cy, r) and one rectangle (x0, x1, y0, y1), the shapes of
+    the paper's obstacle example."""
+    cx, cy, r = disc
+    x0, x1, y0, y1 = rect
+    return ((X - cx) ** 2 + (Y - cy) ** 2 <= r * r) | ((X >= x0) & (X <= x1) & (Y >= y0) & (Y <= y1))
+
+
+def eikonal_obstacles_2d(n: int = 129, nc: int = 32, R: int = 8, fp32: bool = False,
+                         nc_coarse: int = 33):
+    """Eikonal dynamics around a disc and a rectangle (Section 4.5), target
+    ball r = 0.1 at the origin split into R sectors.  Returns (fine, coarse)
+    with the obstacles on both grids."""
+    out = []
+    for nn, is32 in ((n, fp32), (nc_coarse, False)):
+        P = eikonal_2d(nn, nc, 0.1, R, fp32=is32, name=f"obst2d-{nn}")
+        X, Y = P.coords()
+        out.append(with_obstacles(P, obstacle_mask_2d(X, Y).ravel()))
+    return out[0], out[1]
+
+
 def zermelo_2d(n: int = 101, nc: int = 64, c: float = 1.0, w=(0.4, 0.0), r: float = 0.2,
                fp32: bool = False, name: str = "zermelo2d") -> Problem:
     """Constant-drift Zermelo problem f = c a + w (|w| < c), target ball r at

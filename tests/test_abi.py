@@ -37,7 +37,7 @@ def test_struct_layouts_match_header(H, tmp_path):
     import subprocess
     structs = {"hjb_problem": H.hjb_problem, "hjb_stats": H.hjb_stats,
                "hjb_solve_opts": H.hjb_solve_opts, "hjb_batch_opts": H.hjb_batch_opts,
-               "hjb_server_opts": H.hjb_server_opts}
+               "hjb_server_opts": H.hjb_server_opts, "hjb_build_opts": H.hjb_build_opts}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hjb.h"', "int main(void){"]
     for sname, cls in structs.items():
         lines.append(f'printf("{sname} sizeof %zu\\n", sizeof({sname}));')

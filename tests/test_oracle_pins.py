@@ -709,3 +709,102 @@ def test_ao1_needs_tolerance(orc, pr):
     out = orc.patchy(f, c)
     with pytest.raises(RuntimeError):
         orc.solve_patches_ex(f, out["labels"], tol=0.0, init=out["u0"])
+
+
+# ------------------------------------------- obstacles and unreachable regions
+
+def test_obstacle_band_along_characteristics(orc, pr):
+    """Section 4.5: obstacle nodes are a state constraint inside the box.
+    Line target, a band of obstacle rows parallel to the characteristics:
+    every node outside the band keeps its value bit for bit (its optimal
+    path runs along its own row), the band stays at 1, and in the band the
+    feedback is 255 and the label -2."""
+    n = 41
+    P = pr.line_target_2d(n, 32)
+    Pc = pr.line_target_2d(21, 32)
+    band = np.zeros((n, n), dtype=bool)
+    band[12:17, :] = True
+    bandc = np.zeros((21, 21), dtype=bool)
+    bandc[6:9, :] = True
+    Po = pr.with_obstacles(P, band.ravel())
+    Pco = pr.with_obstacles(Pc, bandc.ravel())
+    vf, _ = orc.solve_global(P)
+    vo, _ = orc.solve_global(Po)
+    ob = Po.target_part == -2
+    assert ob.sum() == 5 * (n - 1)
+    assert np.array_equal(vo[~ob], vf[~ob]) and np.all(vo[ob] == 1.0)
+    out = orc.patchy(Po, Pco)
+    assert np.all(out["feedback"][ob] == 255) and np.all(out["labels"][ob] == -2)
+    assert np.all(out["u0"][ob] == 1.0)
+    assert np.array_equal(out["v"], vo)
+
+
+def test_obstacles_only_raise_times(orc, pr):
+    """An obstacle can only lengthen the paths: with the disc and the
+    rectangle, v >= v without them at every node (bit-level inequality),
+    strictly larger in their shadow; the patch solve keeps obstacle nodes at
+    1 and its error stays on the patch boundaries' scale."""
+    f, c = pr.eikonal_obstacles_2d(129, 32, 8)
+    ff = pr.eikonal_2d(129, 32, 0.1, 8)
+    vo, _ = orc.solve_global(f)
+    vf, _ = orc.solve_global(ff)
+    assert np.all(vo >= vf)
+    X, Y = f.coords()
+    shadow = (np.abs(Y - 0.45 * X / 0.45) < 0.05) & (X > 0.8) & (f.target_part == -1)
+    assert shadow.sum() > 10 and np.all(vo[shadow] > vf[shadow])
+    out = orc.patchy(f, c)
+    ob = f.target_part == -2
+    assert np.all(out["v"][ob] == 1.0) and np.all(out["labels"][ob] == -2)
+    assert np.all(out["labels"][~ob & (f.target_part == -1)] >= 0)
+    assert np.abs(out["v"] - vo).mean() < 0.01
+
+
+def test_obstacles_3d(orc, pr):
+    f, c = pr.variable_speed_3d(1, 25, 9, 98, 2, 2, 0.3, False)
+    X, Y, Z = f.coords()
+    box = (np.abs(X - 0.55) < 0.15) & (np.abs(Y) < 0.5) & (np.abs(Z) < 0.5)
+    Xc, Yc, Zc = c.coords()
+    boxc = (np.abs(Xc - 0.55) < 0.15) & (np.abs(Yc) < 0.5) & (np.abs(Zc) < 0.5)
+    fo, co = pr.with_obstacles(f, box.ravel()), pr.with_obstacles(c, boxc.ravel())
+    vf, _ = orc.solve_global(f)
+    vo, _ = orc.solve_global(fo)
+    assert np.all(vo >= vf) and np.all(vo[fo.target_part == -2] == 1.0)
+    out = orc.patchy(fo, co)
+    assert np.all(out["labels"][fo.target_part == -2] == -2)
+
+
+def test_exclusion_of_unreachable_region(orc, pr):
+    """Section 4.6: with a drift stronger than the control, the region
+    downstream of the target cannot reach it and the coarse solve leaves it
+    at 1.  Excluding U^(0) >= 1 after Step 1 drops exactly those nodes,
+    saves their work, and can only raise values (excluded nodes read as 1):
+    nodes the coarse grid deems unreachable stay at 1."""
+    z = pr.zermelo_2d(101, 32, c=0.6, w=(0.9, 0.0), r=0.2)
+    zc = pr.zermelo_2d(26, 32, c=0.6, w=(0.9, 0.0), r=0.2)
+    a = orc.patchy(z, zc)
+    b = orc.patchy(z, zc, exclude_at=1.0)
+    ex = b["target_part"] == -2
+    assert b["excluded"] == ex.sum() > 1000
+    assert np.all(a["u0"][ex] >= 1.0) and np.all(a["u0"][~ex & (z.target_part == -1)] < 1.0)
+    assert np.all(b["labels"][ex] == -2) and np.all(b["v"][ex] == 1.0)
+    assert np.all(b["v"] >= a["v"])
+    assert b["stats"]["updates"] < a["stats"]["updates"]
+
+
+def test_exclusion_enclosed_region_is_exact(orc, pr):
+    """A ring obstacle closes off a region: no node inside can reach the
+    target on either grid, so excluding it changes no value."""
+    f0 = pr.eikonal_2d(97, 32, 0.1, 4)
+    c0 = pr.eikonal_2d(25, 32, 0.1, 4)
+    def ring(P):
+        X, Y = P.coords()
+        r = np.hypot(X - 0.5, Y - 0.5)
+        return ((r >= 0.25) & (r <= 0.4)).ravel()
+    f, c = pr.with_obstacles(f0, ring(f0)), pr.with_obstacles(c0, ring(c0))
+    a = orc.patchy(f, c)
+    b = orc.patchy(f, c, exclude_at=1.0)
+    X, Y = f.coords()
+    inside = (np.hypot(X - 0.5, Y - 0.5) < 0.25).ravel()
+    assert np.all(a["v"][inside] == 1.0)
+    assert np.all(b["target_part"][inside] == -2)
+    assert np.array_equal(a["v"], b["v"])
