@@ -113,7 +113,8 @@ typedef struct {
   const double *controls;     /* [N_c][dim] control vectors a_k */
   const double *speed;        /* [N] c(x_p) >= 0 */
   const double *drift;        /* [N][dim] w(x_p), or NULL for w = 0 */
-  const int16_t *target_part; /* [N] -1 off the target, else part j < n_parts */
+  const int16_t *target_part; /* [N] -1 off the target, part j < n_parts on
+                                 it, HJB_OBSTACLE inside an obstacle */
   int32_t n_parts;            /* R >= 1: parts of the target (Section 3) */
   int32_t mem;                /* HJB_MEM_HOST or HJB_MEM_DEVICE */
 } hjb_problem;
@@ -141,8 +142,16 @@ typedef struct {
   int32_t tile[3];
   int32_t threads;
   int32_t inner_sweeps;
-  int32_t reserved;
+  int32_t excluded;        /* hjb_build_patches_ex: nodes excluded as
+                              unreachable after Step 1 */
 } hjb_stats;
+
+/* target_part value of a node inside an obstacle (Section 4.5): a state
+ * constraint inside the box.  Such a node is never updated, keeps the value
+ * 1 (T = +inf), reads as the ghost value in every interpolation (1 for
+ * values and U^(0), 0 for colours), gets feedback 255 and label
+ * HJB_OBSTACLE, and is never given a label by the Remark 3.1 fill. */
+#define HJB_OBSTACLE (-2)
 
 /* Tuning options; NULL or zero fields select the defaults. */
 typedef struct {
@@ -230,13 +239,33 @@ void hjb_coarse_free(hjb_coarse_t *c);
  *     of it, phi <- max(phi, I[phi](foot of the feedback)) from 0 until no
  *     node changes (ghost 0 outside the box);
  *   - labels (eq. proiezionecolore with Remark 3.1): target node -> its
- *     part; otherwise the part of largest colour, the lowest index on ties,
- *     -1 when every colour is 0 (never reached).
+ *     part; obstacle node -> HJB_OBSTACLE; otherwise the part of largest
+ *     colour, the lowest index on ties, and where every colour is 0 the
+ *     smallest label of the nearest labelled nodes (8 / 26 neighbours,
+ *     layer by layer), -1 if there is none.
  * The coarse problem only fixes the coarse grid size; the handle carries its
  * values.  *out receives a new handle with labels, feedback and U^(0) on the
  * device.  st may be NULL. */
 int hjb_build_patches(const hjb_problem *fine, const hjb_coarse_t *coarse, hjb_stream_t stream,
                       hjb_patches_t **out, hjb_stats *st);
+
+/* Options of hjb_build_patches_ex; NULL or zero fields select the defaults. */
+typedef struct {
+  double exclude_at;       /* Section 4.6: > 0 excludes, after Step 1, the
+                              unreachable regions: a fine node off the
+                              target whose U^(0) is at least exclude_at
+                              (in (0, 1]; 1 = the coarse solve never reached
+                              any of its coarse corners) takes no part in
+                              Steps 2 and 3 -- it is treated as an obstacle
+                              node: no feedback (255), label -2, value 1,
+                              a ghost of value 1 for the other nodes.
+                              hjb_stats.excluded counts these nodes. */
+} hjb_build_opts;
+
+/* hjb_build_patches with options (NULL = hjb_build_patches). */
+int hjb_build_patches_ex(const hjb_problem *fine, const hjb_coarse_t *coarse,
+                         const hjb_build_opts *opts, hjb_stream_t stream, hjb_patches_t **out,
+                         hjb_stats *st);
 
 /* Accessors of a patches handle; `out` is host or device memory per mem. */
 int hjb_patches_labels(const hjb_patches_t *p, int16_t *out, int32_t mem);     /* [N] */

@@ -86,7 +86,7 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
 
 // Steps 2 and 3.1: prolongation, feedback, chunked colour transport, labels.
 std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const CoarseHandle &C,
-                                                  hipStream_t s) {
+                                                  hipStream_t s, double exclude_at) {
   auto hp = std::make_unique<PatchesHandle>();
   PatchesHandle &H = *hp;
   H.dim = F.dim;
@@ -127,6 +127,12 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   const int32_t nc3[3] = {C.n[0], C.n[1], C.n[2]};
   HJB_HIP(launch_prolong(dim, nf3, nc3, C.v.as<double>(), dQ.as<int32_t>(), dT.as<double>(),
                          H.u0.as<double>(), s));
+  // Obstacle nodes, and the unreachable nodes excluded after Step 1, hold
+  // U^(0) = 1 and take no part in Steps 2 and 3.
+  DBuf tp_eff(N * sizeof(int16_t)), nex(sizeof(unsigned long long));
+  HJB_HIP(launch_fill_u32(nex.as<uint32_t>(), 0u, 2, s));
+  HJB_HIP(launch_obstacles(F.tp, H.u0.as<double>(), N, exclude_at, tp_eff.as<int16_t>(),
+                           nex.as<unsigned long long>(), s));
 
   TraceArgs a;
   std::memset(&a, 0, sizeof a);
@@ -143,7 +149,7 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   a.ctrl64 = F.ctrl64;
   a.speed64 = F.speed64;
   a.drift64 = F.drift64;
-  a.target_part = F.tp;
+  a.target_part = tp_eff.as<int16_t>();
   a.feedback = H.feedback.as<uint8_t>();
   a.N = N;
   HJB_HIP(launch_feedback(dim, a, H.u0.as<double>(), H.feedback.as<uint8_t>(), s));
@@ -258,7 +264,10 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
     if (cur != H.labels.as<int16_t>())
       HJB_HIP(hipMemcpyAsync(H.labels.get(), cur, N * sizeof(int16_t), hipMemcpyDeviceToDevice, s));
   }
-  HJB_HIP(launch_make_code(F.tp, H.labels.as<int16_t>(), nullptr, N, H.code.as<int16_t>(), s));
+  HJB_HIP(launch_make_code(tp_eff.as<int16_t>(), H.labels.as<int16_t>(), nullptr, N,
+                           H.code.as<int16_t>(), s));
+  unsigned long long excluded = 0;
+  HJB_HIP(hipMemcpyAsync(&excluded, nex.get(), sizeof excluded, hipMemcpyDeviceToHost, s));
   HJB_HIP(hipStreamSynchronize(s));
   const double t2 = now_ms();
   std::memset(&H.st, 0, sizeof H.st);
@@ -268,6 +277,7 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   // per-node colour updates of one in-tile sweep)
   H.st.trace_node_updates = (int64_t)w[0] * TT[0] * TT[1] * TT[2];
   H.st.unreached = (int32_t)un;
+  H.st.excluded = (int32_t)excluded;
   H.st.rounds = (int32_t)rounds;
   H.st.item_runs = (int64_t)w[1];
   H.st.updates = (int64_t)F.N * F.nc;  // feedback evaluations
@@ -341,16 +351,25 @@ void hjb_coarse_free(hjb_coarse_t *c) { delete c; }
 
 int hjb_build_patches(const hjb_problem *fine, const hjb_coarse_t *coarse, hjb_stream_t stream,
                       hjb_patches_t **out, hjb_stats *st) {
+  return hjb_build_patches_ex(fine, coarse, nullptr, stream, out, st);
+}
+
+int hjb_build_patches_ex(const hjb_problem *fine, const hjb_coarse_t *coarse,
+                         const hjb_build_opts *opts, hjb_stream_t stream, hjb_patches_t **out,
+                         hjb_stats *st) {
   return guarded([&]() -> int {
     HJB_REQUIRE(out != nullptr, "out is NULL");
     *out = nullptr;
     HJB_REQUIRE(coarse != nullptr, "coarse handle is NULL");
+    const double theta = opts ? opts->exclude_at : 0.0;
+    HJB_REQUIRE(theta == 0.0 || (theta > 0.0 && theta <= 1.0),
+                "exclude_at must be 0 (off) or in (0, 1]");
     hipStream_t s = as_stream(stream);
     std::vector<double> ctrl;
     validate_problem(fine, s, &ctrl);
     HJB_REQUIRE(fine->dim == coarse->dim, "fine and coarse dimensions differ");
     auto F = upload_problem(*fine, false, s, &ctrl);
-    auto h = build_patches_impl(*F, *coarse, s);
+    auto h = build_patches_impl(*F, *coarse, s, theta);
     if (st) *st = h->st;
     auto* ph = new hjb_patches_s();
     static_cast<PatchesHandle &>(*ph) = std::move(*h);

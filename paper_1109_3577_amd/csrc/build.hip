@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256)
 k_feedback(TraceArgs a, const double *__restrict__ u0, uint8_t *__restrict__ fb) {
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= a.N) return;
-  if (a.target_part[g] >= 0) {
+  if (a.target_part[g] != -1) {  // target or obstacle: no feedback
     fb[g] = 255;
     return;
   }
@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
       if (DIM == 3) inb = inb && gz < n2;
       const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0));
       gid[j] = g;
-      act[j] = inb && a.target_part[g] < 0;
+      act[j] = inb && a.target_part[g] == -1;
       own[j] = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
       base[j] = own[j];
       t0[j] = t1[j] = t2[j] = 0.0;
@@ -498,7 +498,7 @@ __global__ void k_labels(TraceArgs a, int tx, int ty, int tz, int16_t *labels, u
   int u = 0;
   if (g < a.N) {
     const int tp = a.target_part[g];
-    if (tp >= 0) {
+    if (tp >= 0 || tp == TP_OBSTACLE) {
       labels[g] = (int16_t)tp;
     } else {
       const int x = (int)(g % a.n[0]), y = (int)((g / a.n[0]) % a.n[1]);
@@ -544,7 +544,7 @@ __global__ void k_label_fill(int n0, int n1, int n2, const int16_t *__restrict__
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
   int L = in[g];
-  if (L < 0) {
+  if (L == -1) {  // not an obstacle (-2), not labelled
     const int x = (int)(g % n0), y = (int)((g / n0) % n1), z = (int)(g / ((size_t)n0 * n1));
     const int dz0 = n2 > 1 ? -1 : 0, dz1 = n2 > 1 ? 1 : 0;
     int best = -1;

@@ -23,6 +23,9 @@ namespace hjb {
 constexpr int HALO = 2;  // foot points lie within 2 cells (checked on input)
 constexpr int16_t CODE_TARGET = -2;
 constexpr int16_t CODE_NONE = -1;
+constexpr int16_t CODE_OBST = -3;  // obstacle or excluded node: ghost 1, never updated
+// target_part / label value of an obstacle node (or an excluded one)
+constexpr int16_t TP_OBSTACLE = -2;
 // Statistics and residual counters are spread over kSlots addresses (slot =
 // workgroup index mod kSlots) so that the workgroups of a round do not all
 // update one address; the host reduces the slots.
@@ -180,6 +183,12 @@ hipError_t launch_init_values(bool fp64, const int16_t *code, size_t N, void *v,
 hipError_t launch_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_scaled_f32(const double *src, float *dst, size_t rows, int dim,
                              const double step[3], hipStream_t s);
+// Obstacles and exclusion (Sections 4.5, 4.6): tp_out = tp with
+// TP_OBSTACLE where tp is -1 and theta > 0 and u0 >= theta; u0 = 1 at every
+// obstacle node of tp_out.  *count (zeroed by the caller) receives the
+// number of excluded nodes.
+hipError_t launch_obstacles(const int16_t *tp, double *u0, size_t N, double theta,
+                            int16_t *tp_out, unsigned long long *count, hipStream_t s);
 hipError_t launch_make_code(const int16_t *target_part, const int16_t *labels,
                             const uint8_t *select, size_t N, int16_t *code, hipStream_t s);
 hipError_t launch_scan_problem(const hjb_problem &P, size_t N, const double amax[3],

@@ -293,8 +293,10 @@ struct PatchesHandle {
 std::unique_ptr<CoarseHandle> coarse_solve_impl(const hjb_problem *coarse, double tol,
                                                 int32_t max_sweeps, hipStream_t s, int *status);
 // Steps 2 and 3.1 on an uploaded fine problem.
+// exclude_at > 0: nodes off the target with U^(0) >= exclude_at are
+// excluded (Section 4.6) and treated as obstacle nodes.
 std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const CoarseHandle &C,
-                                                  hipStream_t s);
+                                                  hipStream_t s, double exclude_at = 0.0);
 // Value iteration of one problem with the tiled engine (v is initialised).
 // With `cone`, each node uses the controls of add-on AO3 only.
 int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *v, bool fp64,

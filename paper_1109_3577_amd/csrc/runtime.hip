@@ -239,7 +239,7 @@ void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *
         reach[d] = std::max(reach[d], P->step[d] * (c * amax[d] + std::fabs(w)));
       }
       const int tp = P->target_part[g];
-      HJB_REQUIRE(tp >= -1, "target_part[%zu] = %d < -1", g, tp);
+      HJB_REQUIRE(tp >= -2, "target_part[%zu] = %d < -2", g, tp);
       maxpart = std::max(maxpart, tp);
     }
   } else {
@@ -253,7 +253,7 @@ void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *
     HJB_HIP(hipStreamSynchronize(s));
     int badv = 0;
     std::memcpy(&badv, &h[4], sizeof(int));
-    HJB_REQUIRE(!badv, "speed must be finite and >= 0, drift finite, target_part >= -1");
+    HJB_REQUIRE(!badv, "speed must be finite and >= 0, drift finite, target_part >= -2");
     for (int d = 0; d < 3; ++d) std::memcpy(&reach[d], &h[d], sizeof(double));
     double t;
     std::memcpy(&t, &h[3], sizeof(double));

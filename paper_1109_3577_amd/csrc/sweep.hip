@@ -121,7 +121,10 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
       const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * (DIM == 3 ? gz : 0));
       const int cd = code[g];
       const T vg = ASYNC ? ld_dev(&v[g]) : v[g];
-      val = cd == CODE_TARGET ? T(0) : (cd == patch ? vg : (P.u0 ? (T)P.u0[g] : T(1)));
+      val = cd == CODE_TARGET ? T(0)
+            : cd == patch     ? vg
+            : (P.u0 && cd != CODE_OBST) ? (T)P.u0[g]
+                                          : T(1);
     }
     s_v[lx + LXS * (ly + LY * lz)] = val;
   }
@@ -922,19 +925,45 @@ hipError_t launch_scaled_f32(const double *src, float *dst, size_t rows, int dim
   return hipGetLastError();
 }
 
-// code = target ? TARGET : (labels ? (selected(label) ? label : NONE) : 0)
+// code = target ? TARGET : obstacle (in tp or as label) ? OBST :
+//        (labels ? (selected(label) ? label : NONE) : 0)
 __global__ void k_make_code(const int16_t *__restrict__ tp, const int16_t *__restrict__ lab,
                             const uint8_t *__restrict__ sel, size_t N, int16_t *code) {
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
   int16_t c;
   if (tp[g] >= 0) c = CODE_TARGET;
+  else if (tp[g] == TP_OBSTACLE) c = CODE_OBST;
   else if (!lab) c = 0;
   else {
     const int L = lab[g];
-    c = (L >= 0 && (!sel || sel[L])) ? (int16_t)L : CODE_NONE;
+    c = L == TP_OBSTACLE ? CODE_OBST : (L >= 0 && (!sel || sel[L])) ? (int16_t)L : CODE_NONE;
   }
   code[g] = c;
+}
+
+__global__ void k_obstacles(const int16_t *__restrict__ tp, double *u0, size_t N, double theta,
+                            int16_t *tp_out, unsigned long long *count) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool ex = false;
+  if (g < N) {
+    int16_t t = tp[g];
+    if (t == -1 && theta > 0.0 && u0[g] >= theta) {
+      t = TP_OBSTACLE;
+      ex = true;
+    }
+    if (t == TP_OBSTACLE) u0[g] = 1.0;
+    tp_out[g] = t;
+  }
+  const unsigned long long m = __ballot(ex);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, (unsigned long long)__popcll(m));
+}
+
+hipError_t launch_obstacles(const int16_t *tp, double *u0, size_t N, double theta,
+                            int16_t *tp_out, unsigned long long *count, hipStream_t s) {
+  hipLaunchKernelGGL(k_obstacles, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, tp, u0, N,
+                     theta, tp_out, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_make_code(const int16_t *target_part, const int16_t *labels,
@@ -947,7 +976,8 @@ hipError_t launch_make_code(const int16_t *target_part, const int16_t *labels,
 // Input scan of a device-resident problem: out[0..2] = max displacement
 // bound per axis, out[3] = max target part + 2 (FP64 bits, non-negative);
 // *bad = 1 on a non-finite or negative speed, non-finite drift or a target
-// part below -1.  Block reduction, one atomic per block and quantity.
+// part below -2 (-2 marks an obstacle node).  Block reduction, one atomic
+// per block and quantity.
 __global__ void __launch_bounds__(256)
 k_scan(const double *__restrict__ speed, const double *__restrict__ drift,
        const int16_t *__restrict__ tp, size_t N, int dim, double ax, double ay, double az,
@@ -971,7 +1001,7 @@ k_scan(const double *__restrict__ speed, const double *__restrict__ drift,
     }
     const double t = (double)tp[g] + 2.0;
     r[3] = t > r[3] ? t : r[3];
-    if (tp[g] < -1) b = 1;
+    if (tp[g] < -2) b = 1;
   }
   __syncthreads();
   if (b) sbad = 1;

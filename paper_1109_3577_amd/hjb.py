@@ -21,10 +21,12 @@ HJB_MEM_HOST, HJB_MEM_DEVICE = 0, 1
 HJB_F32, HJB_F64 = 0, 1
 HJB_SCHED_TILED, HJB_SCHED_JACOBI, HJB_SCHED_ASYNC = 0, 1, 2
 HJB_BC_STATE, HJB_BC_DIRICHLET = 0, 1
+HJB_OBSTACLE = -2
 
 # Every symbol include/hjb.h declares.
 EXPORTS = (
     "hjb_coarse_solve", "hjb_coarse_values", "hjb_coarse_free", "hjb_build_patches",
+    "hjb_build_patches_ex",
     "hjb_patches_labels", "hjb_patches_feedback", "hjb_patches_u0", "hjb_patches_free",
     "hjb_solve_patches", "hjb_solve_global", "hjb_batch_create", "hjb_batch_run",
     "hjb_batch_result", "hjb_batch_free", "hjb_server_create", "hjb_server_submit",
@@ -48,7 +50,7 @@ class hjb_stats(C.Structure):
                 ("ms_prolong_feedback", C.c_double), ("ms_trace", C.c_double),
                 ("trace_node_updates", C.c_int64), ("unreached", C.c_int32),
                 ("sweeps", C.c_int32), ("tile", C.c_int32 * 3), ("threads", C.c_int32),
-                ("inner_sweeps", C.c_int32), ("reserved", C.c_int32)]
+                ("inner_sweeps", C.c_int32), ("excluded", C.c_int32)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -65,6 +67,10 @@ class hjb_solve_opts(C.Structure):
                 ("patch_select", C.c_void_p), ("control_cone", C.c_double),
                 ("patch_bc", C.c_int32), ("order_window", C.c_double),
                 ("start_u0", C.c_int32)]
+
+
+class hjb_build_opts(C.Structure):
+    _fields_ = [("exclude_at", C.c_double)]
 
 
 class hjb_batch_opts(C.Structure):
@@ -95,6 +101,8 @@ def _load():
     L.hjb_coarse_free.argtypes = [vp]
     L.hjb_coarse_free.restype = None
     L.hjb_build_patches.argtypes = [P(hjb_problem), vp, vp, P(vp), P(hjb_stats)]
+    L.hjb_build_patches_ex.argtypes = [P(hjb_problem), vp, P(hjb_build_opts), vp, P(vp),
+                                       P(hjb_stats)]
     for f in ("hjb_patches_labels", "hjb_patches_feedback", "hjb_patches_u0"):
         getattr(L, f).argtypes = [vp, vp, i32]
     L.hjb_patches_free.argtypes = [vp]
@@ -286,12 +294,20 @@ def hjb_coarse_solve(coarse, tol: float = 0.0, max_sweeps: int = 0, stream=None,
     return Coarse(h.value, P.N)
 
 
-def hjb_build_patches(fine, coarse: Coarse, stream=None, device: bool = False) -> Patches:
+def hjb_build_patches(fine, coarse: Coarse, stream=None, device: bool = False,
+                      exclude_at: Optional[float] = None) -> Patches:
+    """Steps 2 and 3.1; with exclude_at, hjb_build_patches_ex (Section 4.6)."""
     P = _as_problem(fine, device)
     h = C.c_void_p()
     st = hjb_stats()
-    _check(lib.hjb_build_patches(P.ref, coarse.h, _stream(stream), C.byref(h), C.byref(st)),
-           "hjb_build_patches")
+    if exclude_at is None:
+        rc = lib.hjb_build_patches(P.ref, coarse.h, _stream(stream), C.byref(h), C.byref(st))
+    else:
+        o = hjb_build_opts()
+        o.exclude_at = float(exclude_at)
+        rc = lib.hjb_build_patches_ex(P.ref, coarse.h, C.byref(o), _stream(stream), C.byref(h),
+                                      C.byref(st))
+    _check(rc, "hjb_build_patches")
     return Patches(h.value, P.N, st.as_dict())
 
 
