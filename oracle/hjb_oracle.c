@@ -94,6 +94,10 @@ typedef struct {
   const double *drift;         /* [N][dim] or NULL */
   const int16_t *target_part;  /* [N], -1 = not target */
   int32_t n_parts;
+  /* Variable step of Section 2.1 (h_i such that the foot point lies one
+   * cell away): per-node beta_i = exp(-h_i), 1 - beta_i formed in FP64; or
+   * NULL for the scalar beta. */
+  const double *beta_node;
 } orc_problem;
 
 /* Active-set description: patch < 0 means "every box node is active"
@@ -209,8 +213,10 @@ static double orc_F_node(const orc_problem *P, const double *v, const orc_active
     double disp[3];
     orc_displacement(P, q, k, disp);
     double I = orc_interp(P, v, A, px, py, pz, disp, 1.0);
-    double bI = P->beta * I;
-    double cand = bI + P->omb;
+    double b = P->beta_node ? P->beta_node[q] : P->beta;
+    double omb = P->beta_node ? 1.0 - b : P->omb;
+    double bI = b * I;
+    double cand = bI + omb;
     if (cand < best) best = cand;
   }
   return best;
@@ -439,7 +445,7 @@ int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sw
       double disp[3];
       orc_displacement(F, q, fb[q], disp);
       double I = orc_interp(F, phi, NULL, x, y, z, disp, 0.0);
-      double bI = F->beta * I;
+      double bI = (F->beta_node ? F->beta_node[q] : F->beta) * I;
       if (bI < ORC_COLOUR_FLOOR) bI = 0.0;
       double nv = bI > phi[q] ? bI : phi[q];
       if (nv != phi[q]) changed = 1;

@@ -40,7 +40,8 @@ class _Prob(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("step", C.c_double * 3),
                 ("beta", C.c_double), ("omb", C.c_double), ("n_controls", C.c_int32),
                 ("controls", C.c_void_p), ("speed", C.c_void_p), ("drift", C.c_void_p),
-                ("target_part", C.c_void_p), ("n_parts", C.c_int32)]
+                ("target_part", C.c_void_p), ("n_parts", C.c_int32),
+                ("beta_node", C.c_void_p)]
 
 
 _lib = None
@@ -90,6 +91,8 @@ class _Held:
         s.drift = None if P.drift is None else self._ptr(P.drift, np.float64)
         s.target_part = self._ptr(P.target_part, np.int16)
         s.n_parts = int(P.n_parts)
+        bn = getattr(P, "beta_node", None)
+        s.beta_node = None if bn is None else self._ptr(bn, np.float64)
         self.s = s
 
     def _ptr(self, a, dt):

@@ -56,6 +56,9 @@ class Problem:
     n_parts: int
     name: str = ""
     meta: dict = dataclasses.field(default_factory=dict)
+    # variable step of Section 2.1 (h_i with |h_i f| = k): per-node
+    # beta_i = exp(-h_i), or None for the scalar beta
+    beta_node: Optional[np.ndarray] = None
 
     @property
     def N(self) -> int:
@@ -91,6 +94,9 @@ class Problem:
         if self.drift is not None:
             assert self.drift.dtype == np.float64 and self.drift.shape == (self.N, self.dim)
         assert 0.5 <= self.beta < 1.0 and self.omb == 1.0 - self.beta
+        if self.beta_node is not None:
+            assert self.beta_node.dtype == np.float64 and self.beta_node.shape == (self.N,)
+            assert np.all((self.beta_node >= 0.0) & (self.beta_node < 1.0))
 
 
 def grid_coords(dim: int, n: Sequence[int], lo: Sequence[float], hi: Sequence[float]):
@@ -313,6 +319,85 @@ def eikonal_obstacles_2d(n: int = 129, nc: int = 32, R: int = 8, fp32: bool = Fa
         X, Y = P.coords()
         out.append(with_obstacles(P, obstacle_mask_2d(X, Y).ravel()))
     return out[0], out[1]
+
+
+def unit_reach(P: Problem, fp32: Optional[bool] = None) -> Problem:
+    """The paper's variable step (Section 2.1): h_i = k / |f(x_i, a)| so that
+    every foot point lies one cell away.  For drift-free dynamics
+    f = c(x) a with unit controls on a grid of equal spacing k, the foot
+    point is p + a_k (in cells) and beta_i = exp(-k / c_i) (0 where c_i = 0:
+    the node cannot move).  Returns the problem with speed 1, step 1 and the
+    per-node beta; the scalar beta becomes exp(-k)."""
+    assert P.drift is None, "the variable step is built for drift-free dynamics"
+    k = P.k[:P.dim]
+    assert max(k) - min(k) <= 1e-12 * max(k), "equal grid spacing required"
+    assert np.allclose(np.linalg.norm(P.controls, axis=1), 1.0, rtol=0, atol=1e-12)
+    kk = float(k[0])
+    fp32 = (P.meta.get("fp32", False) if fp32 is None else fp32)
+    c = P.speed
+    with np.errstate(divide="ignore"):
+        bn = np.where(c > 0.0, np.exp(-kk / np.where(c > 0.0, c, 1.0)), 0.0)
+    if fp32:
+        bn = bn.astype(np.float32).astype(np.float64)
+    b = _beta(kk, fp32)
+    return dataclasses.replace(
+        P, h=kk, step=(1.0, 1.0, 1.0 if P.dim == 3 else 0.0), beta=b, omb=1.0 - b,
+        speed=np.ones(P.N), beta_node=np.ascontiguousarray(bn),
+        name=P.name + "-unit", meta={**P.meta, "unit_reach": True, "c": c})
+
+
+def _line_parts(n_other, R):
+    """R strips of equal node count along the other axis (line targets)."""
+    return np.minimum(R - 1, np.arange(n_other) * R // n_other).astype(np.int16)
+
+
+def fan_2d(n: int = 101, nc: int = 32, R: int = 16, fp32: bool = False) -> Problem:
+    """Fan dynamics of Table test2d: f = |x1 + x2 + 0.1| a on [-2,2]^2, unit
+    controls, target the line {x1 = 0} split into R strips; with the paper's
+    variable step (unit_reach).  n must be odd (a node column at x1 = 0)."""
+    assert n % 2 == 1
+    lo, hi = (-2.0, -2.0), (2.0, 2.0)
+    k = 4.0 / (n - 1)
+    X, Y = grid_coords(2, (n, n), lo, hi)
+    tp = np.full((n, n), -1, dtype=np.int16)
+    tp[:, (n - 1) // 2] = _line_parts(n, R)
+    c = np.abs(X + Y + 0.1)
+    P = _make(2, (n, n), k, unit_controls_2d(nc), c.ravel(), None, tp.ravel(), R, fp32,
+              f"fan2d-{n}", lo=lo, hi=hi, meta=dict(fp32=fp32))
+    return unit_reach(P, fp32)
+
+
+def fan_3d(n: int = 33, nc: int = 189, R: int = 8, fp32: bool = False) -> Problem:
+    """Fan 3D of Table test3d: f = |x1 + x2 + x3 + 0.1| a on [-2,2]^3,
+    quasi-uniform unit controls, target the plane {x1 = 0} split into R
+    blocks; with the paper's variable step.  n must be odd."""
+    assert n % 2 == 1
+    lo, hi = (-2.0, -2.0, -2.0), (2.0, 2.0, 2.0)
+    k = 4.0 / (n - 1)
+    X, Y, Z = grid_coords(3, (n, n, n), lo, hi)
+    tp = np.full((n, n, n), -1, dtype=np.int16)
+    ry = max(1, int(round(math.sqrt(R))))
+    while R % ry:
+        ry -= 1
+    rz = R // ry
+    py = _line_parts(n, ry).astype(np.int32)
+    pz = _line_parts(n, rz).astype(np.int32)
+    tp[:, :, (n - 1) // 2] = (pz[:, None] * ry + py[None, :]).astype(np.int16)
+    c = np.abs(X + Y + Z + 0.1)
+    P = _make(3, (n, n, n), k, fibonacci_controls_3d(nc), c.ravel(), None, tp.ravel(), R, fp32,
+              f"fan3d-{n}", lo=lo, hi=hi, meta=dict(fp32=fp32))
+    return unit_reach(P, fp32)
+
+
+def eikonal_paper_2d(n: int = 101, nc: int = 32, R: int = 16, fp32: bool = False) -> Problem:
+    """Eikonal of Table test2d: f = a on [-2,2]^2, target B(0, 0.5) split
+    into R equal-angle sectors (the variable step is the constant h = k)."""
+    lo, hi = (-2.0, -2.0), (2.0, 2.0)
+    k = 4.0 / (n - 1)
+    X, Y = grid_coords(2, (n, n), lo, hi)
+    tp = _ball_sectors_2d(X, Y, (0.0, 0.0), 0.5, R)
+    return _make(2, (n, n), k, unit_controls_2d(nc), np.ones(n * n), None, tp, R, fp32,
+                 f"eikonal-paper-{n}", lo=lo, hi=hi, meta=dict(r=0.5, c=1.0))
 
 
 def zermelo_2d(n: int = 101, nc: int = 64, c: float = 1.0, w=(0.4, 0.0), r: float = 0.2,

@@ -808,3 +808,72 @@ def test_exclusion_enclosed_region_is_exact(orc, pr):
     assert np.all(a["v"][inside] == 1.0)
     assert np.all(b["target_part"][inside] == -2)
     assert np.array_equal(a["v"], b["v"])
+
+
+# ------------------------------------------------ variable step h_i (Section 2.1)
+
+def test_node_beta_constant_is_scalar(orc, pr):
+    """A per-node beta equal everywhere to the scalar beta is the scalar
+    scheme, bit for bit (1 - beta is exact for beta in [0.5, 1))."""
+    P = pr.variable_speed_2d(0, 65, 17, 32, 4, 0.1, False)[0]
+    v1, _ = orc.solve_global(P)
+    v2, _ = orc.solve_global(dataclasses.replace(P, beta_node=np.full(P.N, P.beta)))
+    assert np.array_equal(v1, v2)
+
+
+def test_unit_reach_line_target_recurrence(orc, pr):
+    """Section 2.1, h_i = k / |f(x_i, a)|: with f = c(x1) a and the target a
+    vertical line, the optimal control is the axis one, whose foot point is
+    the next node towards the line exactly; so 1 - v follows the product of
+    the per-node beta_i = exp(-k / c_i) along each row (an exact recurrence,
+    bit for bit), i.e. T is the Riemann sum of the integral of 1 / c, which
+    it matches to O(k)."""
+    n = 41
+    L = pr.line_target_2d(n, 32)
+    X, _ = L.coords()
+    c = 1.0 + 0.5 * np.sin(np.pi * X)
+    U = pr.unit_reach(dataclasses.replace(L, speed=c))
+    v, _ = orc.solve_global(U)
+    col = L.meta["col"]
+    V = v.reshape(n, n)
+    B = U.beta_node.reshape(n, n)
+    for row in range(n):
+        vv = 0.0
+        for j in range(col + 1, n):
+            vv = B[row, j] * vv + (1.0 - B[row, j])
+            assert V[row, j] == vv
+    k = 2.0 / (n - 1)
+    xs = -1.0 + k * np.arange(n)
+    T = -np.log1p(-V[n // 2, col:])
+    exact = np.array([np.sum(k / (1.0 + 0.5 * np.sin(np.pi * xs[col + 1:j + 1])))
+                      for j in range(col, n)])
+    assert np.abs(T - exact).max() < 1e-12 * n
+    fine = np.linspace(0.0, 1.0, 20001)
+    integral = np.trapezoid(1.0 / (1.0 + 0.5 * np.sin(np.pi * fine)), fine)
+    assert abs(T[-1] - integral) < 2 * k
+
+
+def test_unit_reach_frozen_where_speed_vanishes(orc, pr):
+    """Fan dynamics: where c = |x1 + x2 + 0.1| vanishes, h_i is infinite,
+    beta_i = 0 and the node keeps v = 1 (it cannot move)."""
+    f = pr.fan_2d(41, 16, 4)
+    assert np.any(f.beta_node == 0.0)
+    v, _ = orc.solve_global(f)
+    assert np.all(v[(f.beta_node == 0.0) & (f.target_part < 0)] == 1.0)
+
+
+def test_fan_patchy_error_decreases_with_N(orc, pr):
+    """Section 4.2, Table patchy_error_fan: at a fixed coarse grid the
+    patchy error E1 of the Fan problem (paper's domain and variable step,
+    R = 16) decreases as the fine grid is refined."""
+    with open(os.path.join(GOLDEN, "paper_patchy_error_trend.json")) as fh:
+        row = json.load(fh)["fan"]["coarse_50"]["E1"]
+    assert all(a > b for a, b in zip(row, row[1:]))
+    c = pr.fan_2d(33, 32, 16)
+    e1 = []
+    for n in (65, 129, 257):
+        f = pr.fan_2d(n, 32, 16)
+        out = orc.patchy(f, c)
+        vg, _ = orc.solve_global(f)
+        e1.append(np.abs(out["v"] - vg).mean())
+    assert e1[0] > e1[1] > e1[2]
