@@ -117,6 +117,15 @@ typedef struct {
                                  it, HJB_OBSTACLE inside an obstacle */
   int32_t n_parts;            /* R >= 1: parts of the target (Section 3) */
   int32_t mem;                /* HJB_MEM_HOST or HJB_MEM_DEVICE */
+  const double *beta_node;    /* [N] or NULL.  Variable step (Section 2.1,
+                                 h_i with the foot point one cell away):
+                                 beta_i = exp(-h_i) in [0, 1) per node, used
+                                 instead of beta in the scheme and in the
+                                 colour transport, with 1 - beta_i formed in
+                                 FP64.  beta_i = 0 freezes the node at 1.
+                                 For f = c(x) a with unit controls the caller
+                                 passes speed 1, step 1 and
+                                 beta_i = exp(-k / c_i). */
 } hjb_problem;
 
 /* Per-call statistics. */

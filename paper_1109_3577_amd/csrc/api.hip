@@ -150,6 +150,7 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   a.speed64 = F.speed64;
   a.drift64 = F.drift64;
   a.target_part = tp_eff.as<int16_t>();
+  a.beta_node = F.beta64;
   a.feedback = H.feedback.as<uint8_t>();
   a.N = N;
   HJB_HIP(launch_feedback(dim, a, H.u0.as<double>(), H.feedback.as<uint8_t>(), s));

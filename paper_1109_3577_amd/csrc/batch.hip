@@ -46,7 +46,7 @@ struct Prepared {
 // Host copy of an hjb_problem's arrays (for requests queued by the server).
 struct ProblemCopy {
   hjb_problem p{};
-  std::vector<double> ctrl, speed, drift;
+  std::vector<double> ctrl, speed, drift, bnode;
   std::vector<int16_t> tp;
   void take(const hjb_problem &src, hipStream_t s) {
     p = src;
@@ -61,11 +61,16 @@ struct ProblemCopy {
     HJB_HIP(hipMemcpyAsync(tp.data(), src.target_part, N * sizeof(int16_t), k, s));
     if (src.drift)
       HJB_HIP(hipMemcpyAsync(drift.data(), src.drift, drift.size() * sizeof(double), k, s));
+    if (src.beta_node) {
+      bnode.resize(N);
+      HJB_HIP(hipMemcpyAsync(bnode.data(), src.beta_node, N * sizeof(double), k, s));
+    }
     HJB_HIP(hipStreamSynchronize(s));
     p.controls = ctrl.data();
     p.speed = speed.data();
     p.drift = src.drift ? drift.data() : nullptr;
     p.target_part = tp.data();
+    p.beta_node = src.beta_node ? bnode.data() : nullptr;
     p.mem = HJB_MEM_HOST;
   }
 };

@@ -263,6 +263,7 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
     // This thread's nodes: lane `lane` of brick `wave + j NW`, j < NPT.
     int base[NPT], own[NPT];
     double t0[NPT], t1[NPT], t2[NPT];
+    double bt[NPT];  // the node's per-step factor (per-node beta of the variable step)
     bool act[NPT], any[NPT];
     size_t gid[NPT];
     uint32_t nbm[NPT];
@@ -283,6 +284,7 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
       own[j] = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
       base[j] = own[j];
       t0[j] = t1[j] = t2[j] = 0.0;
+      bt[j] = (a.beta_node && act[j]) ? a.beta_node[g] : a.beta;
       if (act[j]) {
         double d[DIM];
         displacement64<DIM>(a, g, a.feedback[g], d);
@@ -359,7 +361,7 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
               c[6] = sp[oz + LX];
               c[7] = sp[oz + LX + 1];
             }
-            const double I = colour_step<DIM>(c, t0[j], t1[j], t2[j], a.beta);
+            const double I = colour_step<DIM>(c, t0[j], t1[j], t2[j], bt[j]);
             if (act[j] && I > sp[own[j]]) {
               s_phi[f * LN + own[j]] = I;
               ch = true;

@@ -56,6 +56,9 @@ struct DevProblem {
   const float *ctrl32;  // [rows][dim] s_d * a_kd rounded to FP32
   const double *speed64;
   const float *speed32;
+  const double *beta64;   // [N] per-node beta of the variable step, or null
+  const float *beta32;    // [N] beta_i and 1 - beta_i rounded to FP32, or null
+  const float *omb32;
   const double *drift64;  // [N][dim] or null
   const float *drift32;   // [N][dim] s_d * w_d rounded to FP32, or null
   const int16_t *code;    // [N]
@@ -142,6 +145,7 @@ struct TraceArgs {
   const double *speed64;
   const double *drift64;
   const int16_t *target_part;
+  const double *beta_node;  // [N] per-node beta (variable step) or null
   const uint8_t *feedback;
   double *phi;       // [R][N], zero-initialised
   uint32_t *masks;   // [ntiles][words]: parts nonzero somewhere in the tile
@@ -181,6 +185,12 @@ hipError_t launch_tile_bits(int dim, const int16_t *code, const int32_t n[3], co
 hipError_t launch_init_values(bool fp64, const int16_t *code, size_t N, void *v, hipStream_t s,
                               const double *start = nullptr);
 hipError_t launch_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t s);
+// beta32 = (float)beta, omb32 = (float)(1 - beta) (the difference in FP64).
+hipError_t launch_beta_f32(const double *beta, float *beta32, float *omb32, size_t n,
+                           hipStream_t s);
+// *bad = 1 when some x[i] is not in [lo, hi) (NaN included).
+hipError_t launch_check_range(const double *x, size_t n, double lo, double hi, int *bad,
+                              hipStream_t s);
 hipError_t launch_scaled_f32(const double *src, float *dst, size_t rows, int dim,
                              const double step[3], hipStream_t s);
 // Obstacles and exclusion (Sections 4.5, 4.6): tp_out = tp with

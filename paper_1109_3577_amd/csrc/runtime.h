@@ -120,13 +120,15 @@ struct ProblemDev {
   double step[3] = {0, 0, 0};
   double beta = 0, omb = 0;
   // FP64 inputs on the device (owned copies when the caller passed host data)
-  DBuf own_ctrl64, own_speed64, own_drift64, own_tp;
+  DBuf own_ctrl64, own_speed64, own_drift64, own_tp, own_beta64;
   const double *ctrl64 = nullptr;
   const double *speed64 = nullptr;
   const double *drift64 = nullptr;
   const int16_t *tp = nullptr;
+  const double *beta64 = nullptr;  // per-node beta (variable step) or null
   // FP32 copies (s_d folded into controls and drift)
   DBuf ctrl32, speed32, drift32;
+  DBuf beta32, omb32;              // per-node beta and 1 - beta (FP64) rounded to FP32
   std::vector<double> ctrl_host;         // controls on the host
   std::unique_ptr<PinnedBuf> ctrl_stage;  // pinned staging of the padded tables
 };

@@ -259,6 +259,22 @@ void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *
     std::memcpy(&t, &h[3], sizeof(double));
     maxpart = (int)t - 2;
   }
+  if (P->beta_node) {
+    // per-node beta of the variable step: finite, in [0, 1)
+    bool ok = true;
+    if (P->mem == HJB_MEM_HOST) {
+      for (size_t g = 0; g < N && ok; ++g) ok = P->beta_node[g] >= 0.0 && P->beta_node[g] < 1.0;
+    } else {
+      DBuf bad(sizeof(int));
+      HJB_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), s));
+      HJB_HIP(launch_check_range(P->beta_node, N, 0.0, 1.0, bad.as<int>(), s));
+      int hb = 0;
+      HJB_HIP(hipMemcpyAsync(&hb, bad.get(), sizeof hb, hipMemcpyDeviceToHost, s));
+      HJB_HIP(hipStreamSynchronize(s));
+      ok = hb == 0;
+    }
+    HJB_REQUIRE(ok, "beta_node must lie in [0, 1) at every node");
+  }
   if (ctrl_out) *ctrl_out = std::move(ctrl);
   for (int d = 0; d < dim; ++d)
     HJB_REQUIRE(reach[d] <= kReachLimit,
@@ -290,6 +306,12 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
     HJB_HIP(hipMemcpyAsync(D->own_tp.get(), P.target_part, N * sizeof(int16_t), hipMemcpyHostToDevice, s));
     D->speed64 = D->own_speed64.as<double>();
     D->tp = D->own_tp.as<int16_t>();
+    if (P.beta_node) {
+      D->own_beta64.reset(N * sizeof(double));
+      HJB_HIP(hipMemcpyAsync(D->own_beta64.get(), P.beta_node, N * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      D->beta64 = D->own_beta64.as<double>();
+    }
     if (P.drift) {
       D->own_drift64.reset(N * P.dim * sizeof(double));
       HJB_HIP(hipMemcpyAsync(D->own_drift64.get(), P.drift, N * P.dim * sizeof(double),
@@ -306,6 +328,7 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
     D->speed64 = P.speed;
     D->drift64 = P.drift;
     D->tp = P.target_part;
+    D->beta64 = P.beta_node;
   }
   // Control tables padded to a whole number of groups of 4 plus one more
   // group, the extra rows repeating the last control: the sweep reads the
@@ -335,6 +358,11 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
     HJB_HIP(hipMemcpyAsync(D->ctrl32.get(), pad32, b32, hipMemcpyHostToDevice, s));
     D->speed32.reset(N * sizeof(float));
     HJB_HIP(launch_f64_to_f32(D->speed64, D->speed32.as<float>(), N, s));
+    if (D->beta64) {
+      D->beta32.reset(N * sizeof(float));
+      D->omb32.reset(N * sizeof(float));
+      HJB_HIP(launch_beta_f32(D->beta64, D->beta32.as<float>(), D->omb32.as<float>(), N, s));
+    }
     if (P.drift) {
       D->drift32.reset(N * P.dim * sizeof(float));
       HJB_HIP(launch_scaled_f32(D->drift64, D->drift32.as<float>(), N, P.dim, P.step, s));
@@ -520,6 +548,9 @@ int SweepEngine::add_problem(const ProblemDev &P, const int16_t *code, const Pro
   d.ombf = (float)P.omb;
   d.ctrl64 = P.ctrl64;
   d.ctrl32 = P.ctrl32.as<float>();
+  d.beta64 = P.beta64;
+  d.beta32 = P.beta32.as<float>();
+  d.omb32 = P.omb32.as<float>();
   d.speed64 = P.speed64;
   d.speed32 = P.speed32.as<float>();
   d.drift64 = P.drift64;
@@ -931,6 +962,9 @@ int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out,
   d.ombf = (float)P.omb;
   d.ctrl64 = P.ctrl64;
   d.ctrl32 = P.ctrl32.as<float>();
+  d.beta64 = P.beta64;
+  d.beta32 = P.beta32.as<float>();
+  d.omb32 = P.omb32.as<float>();
   d.speed64 = P.speed64;
   d.speed32 = P.speed32.as<float>();
   d.drift64 = P.drift64;

@@ -132,6 +132,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
   // This thread's nodes: lane `lane` of brick `wave + j NW`, j < NPT.
   T cc[NPT];
   T ww[NPT][DIM];
+  T bb[NPT], oo[NPT];  // beta and 1 - beta of the node (variable step) or the scalars
   int krow[NPT];  // CONE: byte offset of the node's cone index row
   int off[NPT];
   size_t gid[NPT];
@@ -157,6 +158,13 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
     if constexpr (CONE) {
       const int ks = act[j] ? (int)P.fb[g] : 0;
       krow[j] = (ks < P.nc ? ks : 0) * P.cone_stride;
+    }
+    if constexpr (sizeof(T) == 4) {
+      bb[j] = (P.beta32 && act[j]) ? P.beta32[g] : P.betaf;
+      oo[j] = (P.beta32 && act[j]) ? P.omb32[g] : P.ombf;
+    } else {
+      bb[j] = (P.beta64 && act[j]) ? P.beta64[g] : P.beta;
+      oo[j] = (P.beta64 && act[j]) ? 1.0 - bb[j] : P.omb;
     }
     if constexpr (sizeof(T) == 4) {
       // offset foot point: y = c a + (w + 2)
@@ -198,8 +206,6 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
 #pragma unroll
   for (int j = 0; j < NPT; ++j) old[j] = s_v[off[j]];
 
-  const T beta = sizeof(T) == 4 ? (T)P.betaf : (T)P.beta;
-  const T omb = sizeof(T) == 4 ? (T)P.ombf : (T)P.omb;
   const T tolT = (T)ra.tol;
   const bool plain = P.plain != 0;
   const int ng = (P.nc + 3) >> 2;  // groups of 4 controls (table is padded)
@@ -315,7 +321,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
         // monotone, also after rounding.  The iteration only decreases
         // v, except from a start below the fixed point (add-on AO1: plain
         // v <- F(v)).
-        const T cand = Ar<T>::kruzkov(beta, mI, omb);
+        const T cand = Ar<T>::kruzkov(bb[j], mI, oo[j]);
         const T cur = s_v[off[j]];
         if (plain ? cand != cur : cand < cur) {
           s_v[off[j]] = cand;
@@ -776,8 +782,14 @@ k_jacobi(const DevProblem *__restrict__ Pp, const T *__restrict__ vin, T *__rest
         const T I = interp_global<T, DIM>(vin, P.n, px, py, pz, d);
         mI = I < mI ? I : mI;
       }
-      const T beta = sizeof(T) == 4 ? (T)P.betaf : (T)P.beta;
-      const T omb = sizeof(T) == 4 ? (T)P.ombf : (T)P.omb;
+      T beta, omb;
+      if constexpr (sizeof(T) == 4) {
+        beta = P.beta32 ? P.beta32[g] : P.betaf;
+        omb = P.beta32 ? P.omb32[g] : P.ombf;
+      } else {
+        beta = P.beta64 ? P.beta64[g] : P.beta;
+        omb = P.beta64 ? 1.0 - beta : P.omb;
+      }
       const T cand = Ar<T>::kruzkov(beta, mI, omb);
       nv = cand < old ? cand : old;
       dd = (double)old - (double)nv;
@@ -894,6 +906,39 @@ hipError_t launch_init_values(bool fp64, const int16_t *code, size_t N, void *v,
   else
     hipLaunchKernelGGL(k_init_values<float>, dim3(grid), dim3(256), 0, s, code, N, (float *)v,
                        start);
+  return hipGetLastError();
+}
+
+__global__ void k_beta_f32(const double *__restrict__ beta, float *beta32, float *omb32,
+                           size_t n) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) {
+    const double b = beta[g];
+    beta32[g] = (float)b;
+    omb32[g] = (float)(1.0 - b);
+  }
+}
+
+hipError_t launch_beta_f32(const double *beta, float *beta32, float *omb32, size_t n,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_beta_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, beta, beta32,
+                     omb32, n);
+  return hipGetLastError();
+}
+
+__global__ void k_check_range(const double *__restrict__ x, size_t n, double lo, double hi,
+                              int *bad) {
+  int b = 0;
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (size_t)gridDim.x * blockDim.x)
+    if (!(x[g] >= lo && x[g] < hi)) b = 1;
+  if (__ballot(b) != 0ull && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+}
+
+hipError_t launch_check_range(const double *x, size_t n, double lo, double hi, int *bad,
+                              hipStream_t s) {
+  const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_check_range, dim3(grid), dim3(256), 0, s, x, n, lo, hi, bad);
   return hipGetLastError();
 }
 
