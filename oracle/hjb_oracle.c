@@ -98,6 +98,12 @@ typedef struct {
    * cell away): per-node beta_i = exp(-h_i), 1 - beta_i formed in FP64; or
    * NULL for the scalar beta. */
   const double *beta_node;
+  /* Tabulated dynamics (any f, with the step rule of Section 2.1 per node
+   * and control): foot[(q Nc + k) dim + d] is the foot-point displacement in
+   * cells, beta_pk[q Nc + k] the factor exp(-h_{q,k}); either may be NULL
+   * (displacement s (c a + w); beta per node or scalar). */
+  const double *foot;
+  const double *beta_pk;
 } orc_problem;
 
 /* Active-set description: patch < 0 means "every box node is active"
@@ -160,6 +166,11 @@ static double orc_lin(double t, double lo, double hi) {
 static void orc_displacement(const orc_problem *P, long long q, int k, double disp[3]) {
   double c = P->speed[q];
   for (int d = 0; d < 3; ++d) disp[d] = 0.0;
+  if (P->foot) {
+    for (int d = 0; d < P->dim; ++d)
+      disp[d] = P->foot[((long long)q * P->n_controls + k) * P->dim + d];
+    return;
+  }
   for (int d = 0; d < P->dim; ++d) {
     double g = c * P->controls[(long long)k * P->dim + d];
     if (P->drift) g = g + P->drift[q * P->dim + d];
@@ -213,8 +224,10 @@ static double orc_F_node(const orc_problem *P, const double *v, const orc_active
     double disp[3];
     orc_displacement(P, q, k, disp);
     double I = orc_interp(P, v, A, px, py, pz, disp, 1.0);
-    double b = P->beta_node ? P->beta_node[q] : P->beta;
-    double omb = P->beta_node ? 1.0 - b : P->omb;
+    double b = P->beta_pk     ? P->beta_pk[(long long)q * P->n_controls + k]
+               : P->beta_node ? P->beta_node[q]
+                              : P->beta;
+    double omb = (P->beta_pk || P->beta_node) ? 1.0 - b : P->omb;
     double bI = b * I;
     double cand = bI + omb;
     if (cand < best) best = cand;
@@ -445,7 +458,10 @@ int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sw
       double disp[3];
       orc_displacement(F, q, fb[q], disp);
       double I = orc_interp(F, phi, NULL, x, y, z, disp, 0.0);
-      double bI = (F->beta_node ? F->beta_node[q] : F->beta) * I;
+      double b = F->beta_pk     ? F->beta_pk[(long long)q * F->n_controls + fb[q]]
+                 : F->beta_node ? F->beta_node[q]
+                                : F->beta;
+      double bI = b * I;
       if (bI < ORC_COLOUR_FLOOR) bI = 0.0;
       double nv = bI > phi[q] ? bI : phi[q];
       if (nv != phi[q]) changed = 1;

@@ -41,7 +41,7 @@ class _Prob(C.Structure):
                 ("beta", C.c_double), ("omb", C.c_double), ("n_controls", C.c_int32),
                 ("controls", C.c_void_p), ("speed", C.c_void_p), ("drift", C.c_void_p),
                 ("target_part", C.c_void_p), ("n_parts", C.c_int32),
-                ("beta_node", C.c_void_p)]
+                ("beta_node", C.c_void_p), ("foot", C.c_void_p), ("beta_pk", C.c_void_p)]
 
 
 _lib = None
@@ -93,6 +93,9 @@ class _Held:
         s.n_parts = int(P.n_parts)
         bn = getattr(P, "beta_node", None)
         s.beta_node = None if bn is None else self._ptr(bn, np.float64)
+        ft, bp = getattr(P, "foot", None), getattr(P, "beta_pk", None)
+        s.foot = None if ft is None else self._ptr(ft, np.float64)
+        s.beta_pk = None if bp is None else self._ptr(bp, np.float64)
         self.s = s
 
     def _ptr(self, a, dt):

@@ -59,6 +59,10 @@ class Problem:
     # variable step of Section 2.1 (h_i with |h_i f| = k): per-node
     # beta_i = exp(-h_i), or None for the scalar beta
     beta_node: Optional[np.ndarray] = None
+    # tabulated dynamics: foot-point displacement in cells [N, Nc, dim] and
+    # beta per node and control [N, Nc] (either may be None)
+    foot: Optional[np.ndarray] = None
+    beta_pk: Optional[np.ndarray] = None
 
     @property
     def N(self) -> int:
@@ -398,6 +402,77 @@ def eikonal_paper_2d(n: int = 101, nc: int = 32, R: int = 16, fp32: bool = False
     tp = _ball_sectors_2d(X, Y, (0.0, 0.0), 0.5, R)
     return _make(2, (n, n), k, unit_controls_2d(nc), np.ones(n * n), None, tp, R, fp32,
                  f"eikonal-paper-{n}", lo=lo, hi=hi, meta=dict(r=0.5, c=1.0))
+
+
+def tabulate(P: Problem, f, fp32: bool = False) -> Problem:
+    """Tabulated dynamics with the step rule of Section 2.1: for every node p
+    and control k, h = k / |f(x_p, a_k)| puts the foot point one cell away,
+    so the table holds the displacement f / |f| (in cells; equal grid
+    spacing k) and beta = exp(-k / |f|); where f vanishes, displacement 0 and
+    beta 0 (no move).  f(X, a) takes the node coordinates [N, dim] and one
+    control [dim] and returns [N, dim]."""
+    k = P.k[:P.dim]
+    assert max(k) - min(k) <= 1e-12 * max(k), "equal grid spacing required"
+    kk = float(k[0])
+    X = np.stack(P.coords(), axis=1)
+    foot = np.zeros((P.N, P.n_controls, P.dim))
+    bpk = np.zeros((P.N, P.n_controls))
+    for i, a in enumerate(P.controls):
+        F = np.broadcast_to(np.asarray(f(X, a), dtype=np.float64), (P.N, P.dim))
+        nf = np.linalg.norm(F, axis=1)
+        ok = nf > 0.0
+        foot[ok, i, :] = F[ok] / nf[ok, None]
+        bpk[ok, i] = np.exp(-kk / nf[ok])
+    if fp32:
+        bpk = bpk.astype(np.float32).astype(np.float64)
+    b = _beta(kk, fp32)
+    return dataclasses.replace(
+        P, h=kk, step=(1.0, 1.0, 1.0 if P.dim == 3 else 0.0), beta=b, omb=1.0 - b,
+        speed=np.ones(P.N), drift=None, beta_node=None, foot=np.ascontiguousarray(foot),
+        beta_pk=np.ascontiguousarray(bpk), name=P.name + "-tab", meta={**P.meta, "tabulated": True})
+
+
+def zermelo_paper_2d(n: int = 101, nc: int = 32, R: int = 16, fp32: bool = False) -> Problem:
+    """Zermelo of Table test2d: f = 2.1 a + (2, 0) on [-2,2]^2, unit
+    controls, target B(0, 0.5) in R sectors, with the paper's step rule
+    (per node and control, tabulated)."""
+    P = eikonal_paper_2d(n, nc, R, fp32)
+    P = dataclasses.replace(P, name=f"zermelo-paper-{n}", meta={**P.meta, "c": 2.1, "w": (2.0, 0.0)})
+    return tabulate(P, lambda X, a: 2.1 * a[None, :] + np.array([2.0, 0.0])[None, :], fp32)
+
+
+def brockett_3d(n: int = 33, R: int = 8, fp32: bool = False) -> Problem:
+    """Brockett's integrator of Table test3d: f = (a1, a2, x1 a2 - x2 a1) on
+    [-2,2]^3, A = {-5, 0, 5}^2 (9 controls, stored as (a1, a2, 0)), target
+    B(0, 0.25) in R parts (2 bands x R/2 sectors), with the paper's step rule
+    (tabulated)."""
+    lo, hi = (-2.0, -2.0, -2.0), (2.0, 2.0, 2.0)
+    k = 4.0 / (n - 1)
+    assert k <= 0.25, "the target ball must hold nodes"
+    X, Y, Z = grid_coords(3, (n, n, n), lo, hi)
+    tp = _sphere_parts(X, Y, Z, (0.0, 0.0, 0.0), 0.25, 2, max(1, R // 2))
+    ctrl = np.array([[a1, a2, 0.0] for a2 in (-5.0, 0.0, 5.0) for a1 in (-5.0, 0.0, 5.0)])
+    P = _make(3, (n, n, n), k, ctrl, np.ones(n ** 3), None, tp, 2 * max(1, R // 2), fp32,
+              f"brockett3d-{n}", lo=lo, hi=hi, meta=dict(r=0.25))
+
+    def f(Xn, a):
+        return np.stack([np.full(len(Xn), a[0]), np.full(len(Xn), a[1]),
+                         Xn[:, 0] * a[1] - Xn[:, 1] * a[0]], axis=1)
+    return tabulate(P, f, fp32)
+
+
+def lunar_landing_2d(n: int = 101, eps: float = 0.12, R: int = 4, fp32: bool = False) -> Problem:
+    """Lunar landing (Section 4.6): f = (x2, a), A = {-1, 1} (stored as
+    (0, -1), (0, 1)), target B(0, eps) in R sectors, on [-1,1]^2, with the
+    paper's step rule (tabulated)."""
+    lo, hi = (-1.0, -1.0), (1.0, 1.0)
+    k = 2.0 / (n - 1)
+    X, Y = grid_coords(2, (n, n), lo, hi)
+    tp = _ball_sectors_2d(X, Y, (0.0, 0.0), eps, R)
+    ctrl = np.array([[0.0, -1.0], [0.0, 1.0]])
+    P = _make(2, (n, n), k, ctrl, np.ones(n * n), None, tp, R, fp32, f"lunar-{n}",
+              lo=lo, hi=hi, meta=dict(eps=eps))
+    return tabulate(P, lambda Xn, a: np.stack([Xn[:, 1], np.full(len(Xn), a[1])], axis=1), fp32)
 
 
 def zermelo_2d(n: int = 101, nc: int = 64, c: float = 1.0, w=(0.4, 0.0), r: float = 0.2,

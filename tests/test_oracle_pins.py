@@ -877,3 +877,87 @@ def test_fan_patchy_error_decreases_with_N(orc, pr):
         vg, _ = orc.solve_global(f)
         e1.append(np.abs(out["v"] - vg).mean())
     assert e1[0] > e1[1] > e1[2]
+
+
+# ------------------------------------------ tabulated dynamics (Section 2.1)
+
+def test_table_reproduces_model(orc, pr):
+    """A displacement table holding s (c a_k + w) at every node (formed in
+    the same order) is the model c(x) a + w(x), bit for bit."""
+    f, _ = pr.variable_speed_2d(3, 65, 17, 20, 4, 0.1, False, drift_sign=1)
+    foot = np.zeros((f.N, f.n_controls, 2))
+    for k in range(f.n_controls):
+        for d in range(2):
+            g = f.speed * f.controls[k, d]
+            g = g + f.drift[:, d]
+            foot[:, k, d] = f.step[d] * g
+    v1, _ = orc.solve_global(f)
+    v2, _ = orc.solve_global(dataclasses.replace(f, foot=foot))
+    assert np.array_equal(v1, v2)
+
+
+def test_zermelo_axis_recurrence(orc, pr):
+    """Zermelo of Table test2d with the step rule of Section 2.1: on the
+    axis of the current the optimal control is the axis control, whose foot
+    point is the next node, with beta = exp(-k / |2.1 a + w|): upstream of
+    the target |f| = 4.1, downstream 0.1.  1 - v follows the per-node
+    product exactly, and T = distance / 4.1 or / 0.1 to rounding."""
+    n = 41
+    Z = pr.zermelo_paper_2d(n, 32, 1)
+    v, _ = orc.solve_global(Z)
+    V = v.reshape(n, n)
+    Bk = Z.beta_pk.reshape(n, n, 32)
+    mid = n // 2
+    X = -2.0 + 4.0 / (n - 1) * np.arange(n)
+    tgt = Z.target_part.reshape(n, n)[mid] >= 0
+    hi = int(np.nonzero(tgt)[0].max())
+    lo = int(np.nonzero(tgt)[0].min())
+    vv = 0.0
+    for j in range(hi + 1, n):          # downstream, control a = (-1, 0), index 16
+        vv = Bk[mid, j, 16] * vv + (1.0 - Bk[mid, j, 16])
+        assert V[mid, j] == vv
+        T = -np.log1p(-vv)
+        assert abs(T - (X[j] - X[hi]) / 0.1) < 1e-9 * (1 + T)
+    vv = 0.0
+    for j in range(lo - 1, -1, -1):     # upstream, control a = (1, 0), index 0
+        vv = Bk[mid, j, 0] * vv + (1.0 - Bk[mid, j, 0])
+        assert V[mid, j] == vv
+        assert abs(-np.log1p(-vv) - (X[lo] - X[j]) / 4.1) < 1e-12
+
+
+def test_brockett_symmetries(orc, pr):
+    """Brockett's integrator: f is invariant under a quarter turn about x3
+    (with the control turned, {-5,0,5}^2 maps to itself) and under swapping
+    x1, x2 with x3 -> -x3; the discrete values inherit both to rounding, and
+    every node reaches the target."""
+    n = 33
+    B = pr.brockett_3d(n, 8)
+    v, _ = orc.solve_global(B)
+    V = v.reshape(n, n, n)
+    assert np.abs(V - np.rot90(V, k=1, axes=(1, 2))).max() < 1e-12
+    assert np.abs(V - np.transpose(V, (0, 2, 1))[::-1]).max() < 1e-12
+    assert v.max() < 1.0
+
+
+def test_lunar_landing_point_symmetry(orc, pr):
+    """Lunar landing: f(-x, -a) = -f(x, a) with a symmetric control set and
+    target, so v(x) = v(-x) to rounding."""
+    n = 81
+    L = pr.lunar_landing_2d(n, 0.12, 1)
+    v, _ = orc.solve_global(L)
+    W = v.reshape(n, n)
+    assert np.abs(W - W[::-1, ::-1]).max() < 1e-12
+
+
+def test_zermelo_patchy_error_decreases_with_N(orc, pr):
+    """Section 4.2, Table patchy_error_zermelo: the patchy error E1 of the
+    Zermelo problem (paper's domain, dynamics and step rule, R = 16)
+    decreases as the fine grid is refined at a fixed coarse grid."""
+    c = pr.zermelo_paper_2d(33, 32, 16)
+    e1 = []
+    for n in (65, 129, 257):
+        f = pr.zermelo_paper_2d(n, 32, 16)
+        out = orc.patchy(f, c)
+        vg, _ = orc.solve_global(f)
+        e1.append(np.abs(out["v"] - vg).mean())
+    assert e1[0] > e1[1] > e1[2]
