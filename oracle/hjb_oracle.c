@@ -99,9 +99,10 @@ typedef struct {
    * NULL for the scalar beta. */
   const double *beta_node;
   /* Tabulated dynamics (any f, with the step rule of Section 2.1 per node
-   * and control): foot[(q Nc + k) dim + d] is the foot-point displacement in
-   * cells, beta_pk[q Nc + k] the factor exp(-h_{q,k}); either may be NULL
-   * (displacement s (c a + w); beta per node or scalar). */
+   * and control), control-major: foot[(k N + q) dim + d] is the foot-point
+   * displacement in cells, beta_pk[k N + q] the factor exp(-h_{q,k});
+   * either may be NULL (displacement s (c a + w); beta per node or
+   * scalar). */
   const double *foot;
   const double *beta_pk;
 } orc_problem;
@@ -168,7 +169,7 @@ static void orc_displacement(const orc_problem *P, long long q, int k, double di
   for (int d = 0; d < 3; ++d) disp[d] = 0.0;
   if (P->foot) {
     for (int d = 0; d < P->dim; ++d)
-      disp[d] = P->foot[((long long)q * P->n_controls + k) * P->dim + d];
+      disp[d] = P->foot[((long long)k * orc_N(P) + q) * P->dim + d];
     return;
   }
   for (int d = 0; d < P->dim; ++d) {
@@ -224,7 +225,7 @@ static double orc_F_node(const orc_problem *P, const double *v, const orc_active
     double disp[3];
     orc_displacement(P, q, k, disp);
     double I = orc_interp(P, v, A, px, py, pz, disp, 1.0);
-    double b = P->beta_pk     ? P->beta_pk[(long long)q * P->n_controls + k]
+    double b = P->beta_pk     ? P->beta_pk[(long long)k * orc_N(P) + q]
                : P->beta_node ? P->beta_node[q]
                               : P->beta;
     double omb = (P->beta_pk || P->beta_node) ? 1.0 - b : P->omb;
@@ -458,7 +459,7 @@ int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sw
       double disp[3];
       orc_displacement(F, q, fb[q], disp);
       double I = orc_interp(F, phi, NULL, x, y, z, disp, 0.0);
-      double b = F->beta_pk     ? F->beta_pk[(long long)q * F->n_controls + fb[q]]
+      double b = F->beta_pk     ? F->beta_pk[(long long)fb[q] * N + q]
                  : F->beta_node ? F->beta_node[q]
                                 : F->beta;
       double bI = b * I;

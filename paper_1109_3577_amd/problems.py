@@ -59,8 +59,8 @@ class Problem:
     # variable step of Section 2.1 (h_i with |h_i f| = k): per-node
     # beta_i = exp(-h_i), or None for the scalar beta
     beta_node: Optional[np.ndarray] = None
-    # tabulated dynamics: foot-point displacement in cells [N, Nc, dim] and
-    # beta per node and control [N, Nc] (either may be None)
+    # tabulated dynamics, control-major: foot-point displacement in cells
+    # [Nc, N, dim] and beta per control and node [Nc, N] (either may be None)
     foot: Optional[np.ndarray] = None
     beta_pk: Optional[np.ndarray] = None
 
@@ -415,14 +415,14 @@ def tabulate(P: Problem, f, fp32: bool = False) -> Problem:
     assert max(k) - min(k) <= 1e-12 * max(k), "equal grid spacing required"
     kk = float(k[0])
     X = np.stack(P.coords(), axis=1)
-    foot = np.zeros((P.N, P.n_controls, P.dim))
-    bpk = np.zeros((P.N, P.n_controls))
+    foot = np.zeros((P.n_controls, P.N, P.dim))
+    bpk = np.zeros((P.n_controls, P.N))
     for i, a in enumerate(P.controls):
         F = np.broadcast_to(np.asarray(f(X, a), dtype=np.float64), (P.N, P.dim))
         nf = np.linalg.norm(F, axis=1)
         ok = nf > 0.0
-        foot[ok, i, :] = F[ok] / nf[ok, None]
-        bpk[ok, i] = np.exp(-kk / nf[ok])
+        foot[i, ok, :] = F[ok] / nf[ok, None]
+        bpk[i, ok] = np.exp(-kk / nf[ok])
     if fp32:
         bpk = bpk.astype(np.float32).astype(np.float64)
     b = _beta(kk, fp32)

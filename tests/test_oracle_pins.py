@@ -885,12 +885,12 @@ def test_table_reproduces_model(orc, pr):
     """A displacement table holding s (c a_k + w) at every node (formed in
     the same order) is the model c(x) a + w(x), bit for bit."""
     f, _ = pr.variable_speed_2d(3, 65, 17, 20, 4, 0.1, False, drift_sign=1)
-    foot = np.zeros((f.N, f.n_controls, 2))
+    foot = np.zeros((f.n_controls, f.N, 2))
     for k in range(f.n_controls):
         for d in range(2):
             g = f.speed * f.controls[k, d]
             g = g + f.drift[:, d]
-            foot[:, k, d] = f.step[d] * g
+            foot[k, :, d] = f.step[d] * g
     v1, _ = orc.solve_global(f)
     v2, _ = orc.solve_global(dataclasses.replace(f, foot=foot))
     assert np.array_equal(v1, v2)
@@ -906,7 +906,7 @@ def test_zermelo_axis_recurrence(orc, pr):
     Z = pr.zermelo_paper_2d(n, 32, 1)
     v, _ = orc.solve_global(Z)
     V = v.reshape(n, n)
-    Bk = Z.beta_pk.reshape(n, n, 32)
+    Bk = Z.beta_pk.reshape(32, n, n).transpose(1, 2, 0)
     mid = n // 2
     X = -2.0 + 4.0 / (n - 1) * np.arange(n)
     tgt = Z.target_part.reshape(n, n)[mid] >= 0
