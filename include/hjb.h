@@ -126,6 +126,19 @@ typedef struct {
                                  For f = c(x) a with unit controls the caller
                                  passes speed 1, step 1 and
                                  beta_i = exp(-k / c_i). */
+  const double *foot;         /* [N_c][N][dim] or NULL.  Tabulated dynamics
+                                 (any f, e.g. with the step rule of Section
+                                 2.1 per node and control): the foot-point
+                                 displacement of node p under control k, in
+                                 cells, replacing s (c a_k + w); |foot| must
+                                 stay below 2 cells.  Patch and global
+                                 solves in rounds (not HJB_SCHED_ASYNC, not
+                                 control_cone, not in batches or the
+                                 server). */
+  const double *beta_pk;      /* [N_c][N] or NULL: beta per control and node
+                                 (exp(-h_{p,k})), in [0, 1), replacing beta /
+                                 beta_node; 1 - beta formed in FP64.  Needs
+                                 foot. */
 } hjb_problem;
 
 /* Per-call statistics. */

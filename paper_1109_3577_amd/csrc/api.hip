@@ -39,7 +39,16 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
                  const hjb_solve_opts *opts, double tol, int32_t max_sweeps, hipStream_t s,
                  hjb_stats *st, double t0, const ConeArgs *cone, const double *dbc,
                  const double *u0) {
-  const SolveConfig cfg = make_config(P.dim, fp64, opts, tol, max_sweeps);
+  SolveConfig cfg = make_config(P.dim, fp64, opts, tol, max_sweeps);
+  cfg.tab = P.foot64 != nullptr;
+  if (cfg.tab) {
+    HJB_REQUIRE(!cfg.async && cfg.cone_r == 0.0,
+                "tabulated dynamics run in rounds, without control_cone");
+    HJB_REQUIRE(sweep_tab_shape_supported(cfg.shape.dim, cfg.shape.tx, cfg.shape.ty,
+                                          cfg.shape.tz, cfg.shape.nt),
+                "tabulated dynamics support the tile shapes 2D 16x16, 32x8 and 3D 8x8x8 with "
+                "256 threads");
+  }
   HJB_REQUIRE(!cfg.start_u0 || u0 != nullptr, "start_u0 needs the Step 2 values");
   HJB_HIP(launch_init_values(fp64, code, P.N, v, s, cfg.start_u0 ? u0 : nullptr));
   HJB_REQUIRE((cfg.cone_r > 0.0) == (cone != nullptr), "control cone tables missing");
@@ -151,6 +160,8 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   a.drift64 = F.drift64;
   a.target_part = tp_eff.as<int16_t>();
   a.beta_node = F.beta64;
+  a.foot = F.foot64;
+  a.beta_pk = F.bpk64;
   a.feedback = H.feedback.as<uint8_t>();
   a.N = N;
   HJB_HIP(launch_feedback(dim, a, H.u0.as<double>(), H.feedback.as<uint8_t>(), s));

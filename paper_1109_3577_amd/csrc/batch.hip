@@ -94,6 +94,8 @@ std::unique_ptr<Prepared> prepare(const hjb_problem *fine, const hjb_problem *co
   const double t0 = now_ms();
   std::vector<double> ctrl;
   validate_problem(fine, s, &ctrl);
+  HJB_REQUIRE(fine->foot == nullptr && (!coarse || coarse->foot == nullptr),
+              "tabulated dynamics (foot) are not supported in batches and the server");
   HJB_REQUIRE(coarse && coarse->dim == fine->dim, "coarse problem missing or of another dimension");
   int cst = HJB_OK;
   auto C = coarse_solve_impl(coarse, 0.0, 0, s, &cst);

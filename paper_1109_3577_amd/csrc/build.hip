@@ -72,6 +72,11 @@ hipError_t launch_prolong(int dim, const int32_t nf[3], const int32_t nc[3], con
 // Foot-point displacement d = s (c a_k + w), FP64, separate operations.
 template <int DIM>
 __device__ __forceinline__ void displacement64(const TraceArgs &a, size_t g, int k, double *d) {
+  if (a.foot) {  // tabulated dynamics
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) d[q] = a.foot[((size_t)k * a.N + g) * DIM + q];
+    return;
+  }
   const double c = a.speed64[g];
 #pragma unroll
   for (int q = 0; q < DIM; ++q) {
@@ -284,7 +289,10 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
       own[j] = (lx + HALO) + LX * ((ly + HALO) + LY * (DIM == 3 ? lz + HALO : 0));
       base[j] = own[j];
       t0[j] = t1[j] = t2[j] = 0.0;
-      bt[j] = (a.beta_node && act[j]) ? a.beta_node[g] : a.beta;
+      bt[j] = !act[j]       ? a.beta
+              : a.beta_pk   ? a.beta_pk[(size_t)a.feedback[g] * a.N + g]
+              : a.beta_node ? a.beta_node[g]
+                            : a.beta;
       if (act[j]) {
         double d[DIM];
         displacement64<DIM>(a, g, a.feedback[g], d);

@@ -59,6 +59,11 @@ struct DevProblem {
   const double *beta64;   // [N] per-node beta of the variable step, or null
   const float *beta32;    // [N] beta_i and 1 - beta_i rounded to FP32, or null
   const float *omb32;
+  const double *foot64;   // [nc][N][dim] tabulated displacement (cells), or null
+  const float *foot32;
+  const double *bpk64;    // [nc][N] tabulated beta, or null
+  const float *bpk32;     // and beta, 1 - beta rounded to FP32
+  const float *opk32;
   const double *drift64;  // [N][dim] or null
   const float *drift32;   // [N][dim] s_d * w_d rounded to FP32, or null
   const int16_t *code;    // [N]
@@ -146,6 +151,8 @@ struct TraceArgs {
   const double *drift64;
   const int16_t *target_part;
   const double *beta_node;  // [N] per-node beta (variable step) or null
+  const double *foot;       // [nc][N][dim] tabulated displacement or null
+  const double *beta_pk;    // [nc][N] tabulated beta or null
   const uint8_t *feedback;
   double *phi;       // [R][N], zero-initialised
   uint32_t *masks;   // [ntiles][words]: parts nonzero somewhere in the tile
@@ -165,6 +172,10 @@ hipError_t launch_sweep_async(bool fp64, SweepShape sh, int grid, const DevProbl
                               hipStream_t s);
 hipError_t launch_sweep(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
                         const Item *items, const RoundArgs &ra, hipStream_t s);
+// Sweep of problems with tabulated dynamics (foot / beta tables).
+bool sweep_tab_shape_supported(int dim, int tx, int ty, int tz, int nt);
+hipError_t launch_sweep_tab(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
+                            const Item *items, const RoundArgs &ra, hipStream_t s);
 // Sweep with the control cones of add-on AO3 (one problem, probs[0]); nc and
 // cone_stride size the LDS tables.
 bool sweep_cone_shape_supported(int dim, int tx, int ty, int tz, int nt);

@@ -120,15 +120,18 @@ struct ProblemDev {
   double step[3] = {0, 0, 0};
   double beta = 0, omb = 0;
   // FP64 inputs on the device (owned copies when the caller passed host data)
-  DBuf own_ctrl64, own_speed64, own_drift64, own_tp, own_beta64;
+  DBuf own_ctrl64, own_speed64, own_drift64, own_tp, own_beta64, own_foot64, own_bpk64;
   const double *ctrl64 = nullptr;
   const double *speed64 = nullptr;
   const double *drift64 = nullptr;
   const int16_t *tp = nullptr;
   const double *beta64 = nullptr;  // per-node beta (variable step) or null
+  const double *foot64 = nullptr;  // [nc][N][dim] tabulated displacement or null
+  const double *bpk64 = nullptr;   // [nc][N] tabulated beta or null
   // FP32 copies (s_d folded into controls and drift)
   DBuf ctrl32, speed32, drift32;
   DBuf beta32, omb32;              // per-node beta and 1 - beta (FP64) rounded to FP32
+  DBuf foot32, bpk32, opk32;       // the tables rounded to FP32 (1 - beta from FP64)
   std::vector<double> ctrl_host;         // controls on the host
   std::unique_ptr<PinnedBuf> ctrl_stage;  // pinned staging of the padded tables
 };
@@ -156,6 +159,7 @@ struct SolveConfig {
   bool dbc = false;    // HJB_BC_DIRICHLET: patch boundaries hold U^(0)
   double win_dt = 0.0; // add-on AO2 ordering window per round (> 0: on)
   bool start_u0 = false; // add-on AO1: start at U^(0), plain v <- F(v)
+  bool tab = false;      // tabulated dynamics (set from the problem)
   double tol = 0.0;
   long long max_rounds = 1000000;
 };

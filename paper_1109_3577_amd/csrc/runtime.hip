@@ -259,6 +259,30 @@ void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *
     std::memcpy(&t, &h[3], sizeof(double));
     maxpart = (int)t - 2;
   }
+  HJB_REQUIRE(!P->beta_pk || P->foot, "beta_pk needs foot (tabulated dynamics)");
+  if (P->foot) {
+    // tabulated dynamics: every displacement within the halo, beta in [0, 1)
+    const size_t M = (size_t)nc * N;
+    bool ok = true;
+    if (P->mem == HJB_MEM_HOST) {
+      for (size_t i = 0; i < M * dim && ok; ++i)
+        ok = P->foot[i] >= -kReachLimit && P->foot[i] <= kReachLimit;
+      for (size_t i = 0; P->beta_pk && i < M && ok; ++i)
+        ok = P->beta_pk[i] >= 0.0 && P->beta_pk[i] < 1.0;
+    } else {
+      DBuf bad(sizeof(int));
+      HJB_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), s));
+      HJB_HIP(launch_check_range(P->foot, M * dim, -kReachLimit,
+                                 std::nextafter(kReachLimit, 3.0), bad.as<int>(), s));
+      if (P->beta_pk) HJB_HIP(launch_check_range(P->beta_pk, M, 0.0, 1.0, bad.as<int>(), s));
+      int hb = 0;
+      HJB_HIP(hipMemcpyAsync(&hb, bad.get(), sizeof hb, hipMemcpyDeviceToHost, s));
+      HJB_HIP(hipStreamSynchronize(s));
+      ok = hb == 0;
+    }
+    HJB_REQUIRE(ok, "foot must stay within %.3f cells and beta_pk in [0, 1)", kReachLimit);
+    for (int d = 0; d < 3; ++d) reach[d] = 0.0;  // speed and drift are not used
+  }
   if (P->beta_node) {
     // per-node beta of the variable step: finite, in [0, 1)
     bool ok = true;
@@ -312,6 +336,19 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
                              hipMemcpyHostToDevice, s));
       D->beta64 = D->own_beta64.as<double>();
     }
+    const size_t M = (size_t)P.n_controls * N;
+    if (P.foot) {
+      D->own_foot64.reset(M * P.dim * sizeof(double));
+      HJB_HIP(hipMemcpyAsync(D->own_foot64.get(), P.foot, M * P.dim * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      D->foot64 = D->own_foot64.as<double>();
+    }
+    if (P.beta_pk) {
+      D->own_bpk64.reset(M * sizeof(double));
+      HJB_HIP(hipMemcpyAsync(D->own_bpk64.get(), P.beta_pk, M * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      D->bpk64 = D->own_bpk64.as<double>();
+    }
     if (P.drift) {
       D->own_drift64.reset(N * P.dim * sizeof(double));
       HJB_HIP(hipMemcpyAsync(D->own_drift64.get(), P.drift, N * P.dim * sizeof(double),
@@ -329,6 +366,8 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
     D->drift64 = P.drift;
     D->tp = P.target_part;
     D->beta64 = P.beta_node;
+    D->foot64 = P.foot;
+    D->bpk64 = P.beta_pk;
   }
   // Control tables padded to a whole number of groups of 4 plus one more
   // group, the extra rows repeating the last control: the sweep reads the
@@ -362,6 +401,16 @@ std::unique_ptr<ProblemDev> upload_problem(const hjb_problem &P, bool need32, hi
       D->beta32.reset(N * sizeof(float));
       D->omb32.reset(N * sizeof(float));
       HJB_HIP(launch_beta_f32(D->beta64, D->beta32.as<float>(), D->omb32.as<float>(), N, s));
+    }
+    const size_t M = (size_t)P.n_controls * N;
+    if (D->foot64) {
+      D->foot32.reset(M * P.dim * sizeof(float));
+      HJB_HIP(launch_f64_to_f32(D->foot64, D->foot32.as<float>(), M * P.dim, s));
+    }
+    if (D->bpk64) {
+      D->bpk32.reset(M * sizeof(float));
+      D->opk32.reset(M * sizeof(float));
+      HJB_HIP(launch_beta_f32(D->bpk64, D->bpk32.as<float>(), D->opk32.as<float>(), M, s));
     }
     if (P.drift) {
       D->drift32.reset(N * P.dim * sizeof(float));
@@ -551,6 +600,11 @@ int SweepEngine::add_problem(const ProblemDev &P, const int16_t *code, const Pro
   d.beta64 = P.beta64;
   d.beta32 = P.beta32.as<float>();
   d.omb32 = P.omb32.as<float>();
+  d.foot64 = P.foot64;
+  d.foot32 = P.foot32.as<float>();
+  d.bpk64 = P.bpk64;
+  d.bpk32 = P.bpk32.as<float>();
+  d.opk32 = P.opk32.as<float>();
   d.speed64 = P.speed64;
   d.speed32 = P.speed32.as<float>();
   d.drift64 = P.drift64;
@@ -652,7 +706,10 @@ void SweepEngine::launch_round(uint32_t r) {
   ra.inner_sweeps = cfg_.inner_sweeps;
   ra.nprob = (int)dps_.size();
   ra.tol = cfg_.tol;
-  if (cone_)
+  if (cfg_.tab)
+    HJB_HIP(launch_sweep_tab(cfg_.fp64, cfg_.shape, grid_, probs_d_.as<DevProblem>(),
+                             items_d_.as<Item>(), ra, s_));
+  else if (cone_)
     HJB_HIP(launch_sweep_cone(cfg_.fp64, cfg_.shape, grid_, probs_d_.as<DevProblem>(),
                               items_d_.as<Item>(), ra, dps_[0].nc, dps_[0].cone_stride, s_));
   else
@@ -965,6 +1022,11 @@ int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out,
   d.beta64 = P.beta64;
   d.beta32 = P.beta32.as<float>();
   d.omb32 = P.omb32.as<float>();
+  d.foot64 = P.foot64;
+  d.foot32 = P.foot32.as<float>();
+  d.bpk64 = P.bpk64;
+  d.bpk32 = P.bpk32.as<float>();
+  d.opk32 = P.opk32.as<float>();
   d.speed64 = P.speed64;
   d.speed32 = P.speed32.as<float>();
   d.drift64 = P.drift64;

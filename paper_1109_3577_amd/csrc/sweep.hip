@@ -69,16 +69,19 @@ __host__ __device__ constexpr size_t cone_idx_offset(int nc) {
 // One activation of a work item.  ASYNC: values are exchanged with other
 // workgroups of the same launch (device-scope loads and stores, a release
 // fence before the pushes) and neighbours go to the work queue; otherwise
-// to the next round's list.  CONE: each node minimises over the controls of
-// its feedback's cone only (add-on AO3), read per lane from the LDS tables
-// at s_cone.  Returns whether the tile settled.
+// to the next round's list.  MODE 1 (cones): each node minimises over the
+// controls of its feedback's cone only (add-on AO3), read per lane from the
+// LDS tables at s_cone.  MODE 2 (tabulated dynamics): displacement and beta
+// per control and node come from the tables.  Returns whether the tile
+// settled.
 template <typename T, int DIM, int TX, int TY, int TZ, int NT, bool DRIFT, bool ASYNC,
-          bool CONE = false>
+          int MODE = 0>
 __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item, int item_id,
                                            uint32_t fl, const RoundArgs &ra, const AsyncQ &aq,
                                            T *s_v, int *s_int, double *s_red,
                                            unsigned long long *s_wrk, uint32_t *s_msk,
                                            const unsigned char *s_cone = nullptr) {
+  constexpr bool CONE = MODE == 1, TAB = MODE == 2;
   constexpr int LX = TX + 2 * HALO;
   constexpr int LY = TY + 2 * HALO;
   constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
@@ -288,6 +291,35 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
           else
             group(std::integral_constant<int, 3>{}, w4);
         }
+      } else if constexpr (TAB) {
+        // mI collects the candidates beta I + 1 - beta themselves
+        const size_t Nn = (size_t)n0 * n1 * n2;
+        const int b2 = off[j] - 2 - 2 * LXS - (DIM == 3 ? 2 * LXS * LY : 0);
+        for (int k = 0; k < P.nc; ++k) {
+          const size_t e = act[j] ? (size_t)k * Nn + gid[j] : 0;
+          T b = bb[j], o = oo[j], I;
+          if constexpr (sizeof(T) == 4) {
+            float y[DIM];
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) y[q] = P.foot32[e * DIM + q] + 2.0f;
+            I = interp_lds_f32<DIM, LXS, LY>(s_v, b2, y);
+            if (P.bpk32) {
+              b = P.bpk32[e];
+              o = P.opk32[e];
+            }
+          } else {
+            T d[DIM];
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) d[q] = P.foot64[e * DIM + q];
+            I = interp_lds_f64<DIM, LXS, LY>(s_v, off[j], d);
+            if (P.bpk64) {
+              b = P.bpk64[e];
+              o = 1.0 - b;
+            }
+          }
+          const T ck = Ar<T>::kruzkov(b, I, o);
+          mI = ck < mI ? ck : mI;
+        }
       } else if constexpr (sizeof(T) == 4) {
         const int b2 = off[j] - 2 - 2 * LXS - (DIM == 3 ? 2 * LXS * LY : 0);
         for (int g4 = 0; g4 < ng; ++g4) {
@@ -321,7 +353,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
         // monotone, also after rounding.  The iteration only decreases
         // v, except from a start below the fixed point (add-on AO1: plain
         // v <- F(v)).
-        const T cand = Ar<T>::kruzkov(bb[j], mI, oo[j]);
+        const T cand = TAB ? mI : Ar<T>::kruzkov(bb[j], mI, oo[j]);
         const T cur = s_v[off[j]];
         if (plain ? cand != cur : cand < cur) {
           s_v[off[j]] = cand;
@@ -516,8 +548,54 @@ k_sweep(const DevProblem *__restrict__ probs, const Item *__restrict__ items, Ro
       sweep_item<T, DIM, TX, TY, TZ, NT, false, false>(P, item, it, fl, ra, AsyncQ{}, s_v, s_int,
                                                        s_red, s_wrk, s_msk);
     __syncthreads();
+  }}
+
+// Rounds schedule of problems with tabulated dynamics (as k_sweep).
+template <typename T, int DIM, int TX, int TY, int TZ, int NT>
+__global__ void __launch_bounds__(NT)
+k_sweep_tab(const DevProblem *__restrict__ probs, const Item *__restrict__ items, RoundArgs ra) {
+  constexpr int LX = TX + 2 * HALO;
+  constexpr int LY = TY + 2 * HALO;
+  constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
+  constexpr int LXS = lds_stride<T, DIM, LX>();
+  __shared__ T s_v[LXS * LY * LZ];
+  __shared__ int s_int[8];
+  __shared__ uint32_t s_msk[4];
+  __shared__ double s_red[NT / 64];
+  __shared__ unsigned long long s_wrk[NT / 64];
+  const uint32_t r = ra.round;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) ra.count[(r + 2) % 3] = 0u;
+    for (int p = threadIdx.x; p < ra.nprob * kSlots; p += NT) {
+      const int q = p / kSlots, k = p % kSlots;
+      if (k == 0) {
+        probs[q].pactive[(r + 2) % 3] = 0u;
+        if (probs[q].item_key) window_advance(probs[q], r);
+      }
+      probs[q].residual[((r + 2) % 3) * kSlots + k] = 0ull;
+    }
   }
-}
+  const uint32_t nin = ra.count[r % 3];
+  for (uint32_t li = blockIdx.x; li < nin; li += gridDim.x) {
+    const int it = ra.list_in[li];
+    const Item item = items[it];
+    const DevProblem &P = probs[item.prob];
+    const uint32_t fl = ra.flags_in[it];
+    __syncthreads();  // every thread has read the flag before it is cleared
+    if (threadIdx.x == 0) ra.flags_in[it] = 0u;
+    if (P.item_key) {
+      const int ntiles = P.ntile[0] * P.ntile[1] * P.ntile[2];
+      const float key = P.item_key[(size_t)item.patch * ntiles + item.tile];
+      if (key > window_threshold(P, r)) {
+        if (threadIdx.x == 0) window_defer(P, ra, it, fl, key);
+        continue;
+      }
+    }
+    // tabulated dynamics: speed and drift are not used
+    sweep_item<T, DIM, TX, TY, TZ, NT, false, false, 2>(P, item, it, fl, ra, AsyncQ{}, s_v, s_int,
+                                                        s_red, s_wrk, s_msk);
+    __syncthreads();
+  }}
 
 // Rounds schedule with the control cones of add-on AO3 (one problem).  The
 // controls and the cone index rows are staged in dynamic LDS once per
@@ -577,11 +655,11 @@ k_sweep_cone(const DevProblem *__restrict__ probs, const Item *__restrict__ item
       }
     }
     if (P.has_drift)
-      sweep_item<T, DIM, TX, TY, TZ, NT, true, false, true>(P, item, it, fl, ra, AsyncQ{}, s_v,
-                                                            s_int, s_red, s_wrk, s_msk, s_cone);
+      sweep_item<T, DIM, TX, TY, TZ, NT, true, false, 1>(P, item, it, fl, ra, AsyncQ{}, s_v,
+                                                         s_int, s_red, s_wrk, s_msk, s_cone);
     else
-      sweep_item<T, DIM, TX, TY, TZ, NT, false, false, true>(P, item, it, fl, ra, AsyncQ{}, s_v,
-                                                             s_int, s_red, s_wrk, s_msk, s_cone);
+      sweep_item<T, DIM, TX, TY, TZ, NT, false, false, 1>(P, item, it, fl, ra, AsyncQ{}, s_v,
+                                                          s_int, s_red, s_wrk, s_msk, s_cone);
     __syncthreads();
   }
 }
@@ -735,6 +813,36 @@ hipError_t launch_sweep_cone(bool fp64, SweepShape sh, int grid, const DevProble
   return hipErrorInvalidValue;
 }
 
+#define HJB_TAB_SHAPES(X) \
+  X(2, 16, 16, 1, 256)      \
+  X(2, 32, 8, 1, 256)       \
+  X(3, 8, 8, 8, 256)
+
+bool sweep_tab_shape_supported(int dim, int tx, int ty, int tz, int nt) {
+#define HJB_CHECK_SHAPE(D, A, B, C, NT) \
+  if (dim == D && tx == A && ty == B && tz == C && nt == NT) return true;
+  HJB_TAB_SHAPES(HJB_CHECK_SHAPE)
+#undef HJB_CHECK_SHAPE
+  return false;
+}
+
+hipError_t launch_sweep_tab(bool fp64, SweepShape sh, int grid, const DevProblem *probs,
+                            const Item *items, const RoundArgs &ra, hipStream_t s) {
+#define HJB_LAUNCH_TAB(D, A, B, C, NT)                                                     \
+  if (sh.dim == D && sh.tx == A && sh.ty == B && sh.tz == C && sh.nt == NT) {              \
+    if (fp64)                                                                              \
+      hipLaunchKernelGGL((k_sweep_tab<double, D, A, B, C, NT>), dim3(grid), dim3(NT), 0, s, \
+                         probs, items, ra);                                                \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_sweep_tab<float, D, A, B, C, NT>), dim3(grid), dim3(NT), 0, s,  \
+                         probs, items, ra);                                                \
+    return hipGetLastError();                                                              \
+  }
+  HJB_TAB_SHAPES(HJB_LAUNCH_TAB)
+#undef HJB_LAUNCH_TAB
+  return hipErrorInvalidValue;
+}
+
 // ---------------------------------------------------------------- plain Jacobi
 
 // One full-grid Jacobi sweep: vout = min(vin, F(vin)); the plain global solve.
@@ -765,23 +873,6 @@ k_jacobi(const DevProblem *__restrict__ Pp, const T *__restrict__ vin, T *__rest
         c = P.speed64[g];
         for (int a = 0; a < DIM; ++a) w[a] = P.has_drift ? P.drift64[g * DIM + a] : 0.0;
       }
-      T mI = T(3);
-      for (int k = 0; k < P.nc; ++k) {
-        T d[DIM];
-        for (int q = 0; q < DIM; ++q) {
-          if constexpr (sizeof(T) == 4) {
-            const float a = ((cf32p)P.ctrl32)[k * DIM + q];
-            d[q] = __builtin_fmaf(c, a, w[q]);
-          } else {
-            const double a = ((cf64p)P.ctrl64)[k * DIM + q];
-            double gg = c * a;
-            if (P.has_drift) gg = gg + w[q];
-            d[q] = P.step[q] * gg;
-          }
-        }
-        const T I = interp_global<T, DIM>(vin, P.n, px, py, pz, d);
-        mI = I < mI ? I : mI;
-      }
       T beta, omb;
       if constexpr (sizeof(T) == 4) {
         beta = P.beta32 ? P.beta32[g] : P.betaf;
@@ -790,7 +881,52 @@ k_jacobi(const DevProblem *__restrict__ Pp, const T *__restrict__ vin, T *__rest
         beta = P.beta64 ? P.beta64[g] : P.beta;
         omb = P.beta64 ? 1.0 - beta : P.omb;
       }
-      const T cand = Ar<T>::kruzkov(beta, mI, omb);
+      // tabulated dynamics: displacement (and beta) per control and node
+      const bool tab = sizeof(T) == 4 ? P.foot32 != nullptr : P.foot64 != nullptr;
+      T mI = T(3), best = T(3);
+      for (int k = 0; k < P.nc; ++k) {
+        T d[DIM];
+        const size_t e = (size_t)k * N + g;
+        for (int q = 0; q < DIM; ++q) {
+          if constexpr (sizeof(T) == 4) {
+            if (tab) {
+              d[q] = P.foot32[e * DIM + q] + 2.0f;
+            } else {
+              const float a = ((cf32p)P.ctrl32)[k * DIM + q];
+              d[q] = __builtin_fmaf(c, a, w[q]);
+            }
+          } else {
+            if (tab) {
+              d[q] = P.foot64[e * DIM + q];
+            } else {
+              const double a = ((cf64p)P.ctrl64)[k * DIM + q];
+              double gg = c * a;
+              if (P.has_drift) gg = gg + w[q];
+              d[q] = P.step[q] * gg;
+            }
+          }
+        }
+        const T I = interp_global<T, DIM>(vin, P.n, px, py, pz, d);
+        if (tab) {
+          T b = beta, o = omb;
+          if constexpr (sizeof(T) == 4) {
+            if (P.bpk32) {
+              b = P.bpk32[e];
+              o = P.opk32[e];
+            }
+          } else {
+            if (P.bpk64) {
+              b = P.bpk64[e];
+              o = 1.0 - b;
+            }
+          }
+          const T ck = Ar<T>::kruzkov(b, I, o);
+          best = ck < best ? ck : best;
+        } else {
+          mI = I < mI ? I : mI;
+        }
+      }
+      const T cand = tab ? best : Ar<T>::kruzkov(beta, mI, omb);
       nv = cand < old ? cand : old;
       dd = (double)old - (double)nv;
     }

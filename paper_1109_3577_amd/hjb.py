@@ -39,7 +39,8 @@ class hjb_problem(C.Structure):
                 ("beta", C.c_double), ("one_minus_beta", C.c_double),
                 ("n_controls", C.c_int32), ("controls", C.c_void_p), ("speed", C.c_void_p),
                 ("drift", C.c_void_p), ("target_part", C.c_void_p), ("n_parts", C.c_int32),
-                ("mem", C.c_int32), ("beta_node", C.c_void_p)]
+                ("mem", C.c_int32), ("beta_node", C.c_void_p), ("foot", C.c_void_p),
+                ("beta_pk", C.c_void_p)]
 
 
 class hjb_stats(C.Structure):
@@ -182,11 +183,14 @@ class Problem:
         s.n_controls = int(source.controls.shape[0])
         s.n_parts = int(source.n_parts)
         bn = getattr(source, "beta_node", None)
+        ft, bp = getattr(source, "foot", None), getattr(source, "beta_pk", None)
         arrs = [np.ascontiguousarray(source.controls, dtype=np.float64),
                 np.ascontiguousarray(source.speed, dtype=np.float64),
                 None if source.drift is None else np.ascontiguousarray(source.drift, dtype=np.float64),
                 np.ascontiguousarray(source.target_part, dtype=np.int16),
-                None if bn is None else np.ascontiguousarray(bn, dtype=np.float64)]
+                None if bn is None else np.ascontiguousarray(bn, dtype=np.float64),
+                None if ft is None else np.ascontiguousarray(ft, dtype=np.float64),
+                None if bp is None else np.ascontiguousarray(bp, dtype=np.float64)]
         if device:
             import torch
             arrs = [None if a is None else torch.from_numpy(a).cuda() for a in arrs]
@@ -194,7 +198,8 @@ class Problem:
         else:
             s.mem = HJB_MEM_HOST
         self.keep = arrs
-        s.controls, s.speed, s.drift, s.target_part, s.beta_node = (_ptr(a) for a in arrs)
+        (s.controls, s.speed, s.drift, s.target_part, s.beta_node, s.foot,
+         s.beta_pk) = (_ptr(a) for a in arrs)
         self.s = s
 
     @property
