@@ -82,7 +82,8 @@ def parse():
     ap.add_argument("--no-addons", action="store_true",
                     help="skip the side measurement of the add-ons (dbc data, AO3 cones)")
     ap.add_argument("--ao3-r", type=float, default=4.0, help="AO3 reduction factor r")
-    ap.add_argument("--mode", choices=("solve", "solve3d", "batch", "serve", "copy"), default="solve",
+    ap.add_argument("--mode", choices=("solve", "solve3d", "batch", "serve", "copy", "paper"),
+                    default="solve",
                     help="solve: the 1025^2 patchy problem (default, the headline line); "
                          "solve3d: the 257^3 patchy problem (98 controls, 64 parts); "
                          "batch: many uneven problems in shared rounds; serve: Poisson "
@@ -104,6 +105,106 @@ def bench_copy(args):
     torch.cuda.synchronize()
     print(json.dumps({"mode": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
                       "copies": 3}))
+
+
+def bench_paper(args):
+    """The paper's own tables replayed on the GPU with its dynamics, domains
+    and step rule: patchy error E1 (E_inf) against the global solve for
+    Eikonal, Fan and Zermelo in 2D (R = 16, N_c = 32, coarse 51^2 and
+    101^2), the 3D tests with the add-ons on, and the add-ons table
+    (R = 8).  Errors are reported in the Kruzkov variable and in the time
+    variable T = -ln(1 - v) where both solutions are finite."""
+    import numpy as np
+    import torch
+
+    from paper_1109_3577_amd import hjb, problems
+
+    def solve(fine, coarse, opts=None, tol=0.0):
+        P, Cp = hjb.Problem(fine, device=True), hjb.Problem(coarse, device=True)
+        ch = hjb.hjb_coarse_solve(Cp)
+        ph = hjb.hjb_build_patches(P, ch)
+        v = torch.empty(P.N, dtype=torch.float32, device="cuda")
+        st = hjb.hjb_solve_patches(P, ph, hjb.HJB_F32, v, tol, 0,
+                                   opts if opts is not None else hjb.make_opts(time_kernels=True))
+        g = torch.empty(P.N, dtype=torch.float32, device="cuda")
+        hjb.hjb_solve_global(P, hjb.HJB_F32, g, tol, 0, None)
+        torch.cuda.synchronize()
+        return v.double().cpu().numpy(), g.double().cpu().numpy(), st, ph.stats
+
+    def errors(vp, vg):
+        e = np.abs(vp - vg)
+        fin = (vp < 1.0) & (vg < 1.0)
+        et = np.abs(np.log1p(-vp[fin]) - np.log1p(-vg[fin])) if fin.any() else np.zeros(1)
+        return {"E1": float(e.mean()), "Einf": float(e.max()),
+                "E1_T": float(et.mean()), "Einf_T": float(et.max())}
+
+    gens = {"eikonal": lambda n, fp32: problems.eikonal_paper_2d(n, 32, 16, fp32),
+            "fan": lambda n, fp32: problems.fan_2d(n, 32, 16, fp32),
+            "zermelo": lambda n, fp32: problems.zermelo_paper_2d(n, 32, 16, fp32)}
+    sides = [101, 201, 401, 801]
+    out = {"mode": "paper", "tables": {}}
+    for name, gen in gens.items():
+        tab = {}
+        for nc in (51, 101):
+            coarse = gen(nc, False)
+            for n in sides:
+                if n < nc:
+                    continue
+                vp, vg, st, bst = solve(gen(n, True), coarse)
+                tab[f"{nc}->{n}"] = {**errors(vp, vg), "solve_ms": st["ms_wall"],
+                                     "build_ms": bst["ms_wall"]}
+                print(f"[paper] {name} {nc}->{n} {tab[f'{nc}->{n}']}", file=sys.stderr, flush=True)
+        out["tables"][f"patchy_error_{name}"] = tab
+
+    # add-ons table: R = 8, N_c = 32, controls reduced by factor 4 (r = 4)
+    gens8 = {"eikonal": lambda n, fp32: problems.eikonal_paper_2d(n, 32, 8, fp32),
+             "fan": lambda n, fp32: problems.fan_2d(n, 32, 8, fp32),
+             "zermelo": lambda n, fp32: problems.zermelo_paper_2d(n, 32, 8, fp32)}
+    addons = {}
+    for name, gen in gens8.items():
+        coarse = gen(101, False)
+        for n in (201, 401, 801):
+            P, Cp = hjb.Problem(gen(n, True), device=True), hjb.Problem(coarse, device=True)
+            ch = hjb.hjb_coarse_solve(Cp)
+            ph = hjb.hjb_build_patches(P, ch)
+            v = torch.empty(P.N, dtype=torch.float32, device="cuda")
+            row = {}
+            tabulated = name == "zermelo"
+            variants = {"basic": {}, "AO1": {"start_u0": 1}, "AO2": {"order_window": 6.0}}
+            if not tabulated:
+                variants["AO3"] = {"control_cone": 4.0}
+            variants["all"] = {**variants["AO1"], **variants["AO2"],
+                               **({} if tabulated else variants["AO3"]),
+                               "patch_bc": hjb.HJB_BC_DIRICHLET}
+            for vname, kw in variants.items():
+                o = hjb.make_opts(time_kernels=True, **kw)
+                runs = [hjb.hjb_solve_patches(P, ph, hjb.HJB_F32, v, 1e-6, 0, o) for _ in range(3)]
+                row[vname] = min(r["ms_kernel"] for r in runs)
+            addons[f"101->{n}"] = addons.get(f"101->{n}", {})
+            addons[f"101->{n}"][name] = row
+            print(f"[paper] add-ons {name} 101->{n} {row}", file=sys.stderr, flush=True)
+    out["tables"]["addons_kernel_ms"] = addons
+
+    # 3D tests with the add-ons on (Eikonal and Fan: cones r = 4; Brockett:
+    # no cones), R = 8
+    gens3 = {"eikonal3d": lambda n, fp32: problems.eikonal_paper_3d(n, 189, 8, fp32),
+             "fan3d": lambda n, fp32: problems.fan_3d(n, 189, 8, fp32),
+             "brockett3d": lambda n, fp32: problems.brockett_3d(n, 8, fp32)}
+    t3 = {}
+    for name, gen in gens3.items():
+        coarse = gen(51, False)
+        for n in (101,) + ((201,) if args.count >= 201 else ()):
+            kw = {"patch_bc": hjb.HJB_BC_DIRICHLET, "order_window": 2.5, "inner_sweeps": 4}
+            if name != "brockett3d":
+                kw["control_cone"] = 4.0
+            vp, vg, st, bst = solve(gen(n, True), coarse, hjb.make_opts(time_kernels=True, **kw),
+                                    1e-6)
+            t3[f"51->{n}"] = t3.get(f"51->{n}", {})
+            t3[f"51->{n}"][name] = {**errors(vp, vg), "solve_ms": st["ms_wall"],
+                                    "build_ms": bst["ms_wall"], "kernel_ms": st["ms_kernel"]}
+            print(f"[paper] 3D {name} 51->{n} {t3[f'51->{n}'][name]}", file=sys.stderr, flush=True)
+    out["tables"]["3d"] = t3
+    print(json.dumps(out))
 
 
 def bench_batch(args):
@@ -220,6 +321,8 @@ def main():
         return bench_serve(args)
     if args.mode == "copy":
         return bench_copy(args)
+    if args.mode == "paper":
+        return bench_paper(args)
     stream = torch.cuda.Stream()
     dim = 3 if args.mode == "solve3d" else 2
     if dim == 2:

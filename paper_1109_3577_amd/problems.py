@@ -432,6 +432,18 @@ def tabulate(P: Problem, f, fp32: bool = False) -> Problem:
         beta_pk=np.ascontiguousarray(bpk), name=P.name + "-tab", meta={**P.meta, "tabulated": True})
 
 
+def eikonal_paper_3d(n: int = 51, nc: int = 189, R: int = 8, fp32: bool = False) -> Problem:
+    """Eikonal 3D of Table test3d: f = a on [-2,2]^3, nc quasi-uniform unit
+    controls, target B(0, 0.5) in R parts (2 bands x R/2 sectors)."""
+    lo, hi = (-2.0,) * 3, (2.0,) * 3
+    k = 4.0 / (n - 1)
+    X, Y, Z = grid_coords(3, (n, n, n), lo, hi)
+    tp = _sphere_parts(X, Y, Z, (0.0, 0.0, 0.0), 0.5, 2, max(1, R // 2))
+    return _make(3, (n, n, n), k, fibonacci_controls_3d(nc), np.ones(n ** 3), None, tp,
+                 2 * max(1, R // 2), fp32, f"eikonal-paper-3d-{n}", lo=lo, hi=hi,
+                 meta=dict(r=0.5, c=1.0))
+
+
 def zermelo_paper_2d(n: int = 101, nc: int = 32, R: int = 16, fp32: bool = False) -> Problem:
     """Zermelo of Table test2d: f = 2.1 a + (2, 0) on [-2,2]^2, unit
     controls, target B(0, 0.5) in R sectors, with the paper's step rule
