@@ -599,6 +599,31 @@ int orc_cone_allowed(const orc_problem *P, double r, uint8_t *allow) {
   return lmax;
 }
 
+/* Public: F at a list of nodes for the patch solve with the options of the
+ * add-ons section (cones of AO3 around fb when cone_r > 1, Dirichlet data
+ * u0 when given), so that a large result can be checked node by node. */
+int orc_F_at_ex(const orc_problem *P, const int16_t *labels, int patch, const uint8_t *fb,
+                double cone_r, const double *u0, const double *v, const long long *idx,
+                long long count, double *out) {
+  if (orc_check(P) || patch < 0) return ORC_EINVAL;
+  uint8_t *allow = NULL;
+  if (fb && cone_r > 1.0) {
+    allow = (uint8_t *)malloc((size_t)P->n_controls * (size_t)P->n_controls);
+    if (!allow) return ORC_ENOMEM;
+    orc_cone_allowed(P, cone_r, allow);
+  }
+  orc_active A = {labels, patch, fb, allow, u0, 0};
+  long long nx = P->n[0], ny = P->n[1];
+  for (long long i = 0; i < count; ++i) {
+    long long q = idx[i];
+    long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
+    if (P->target_part[q] >= 0) out[i] = 0.0;
+    else out[i] = orc_F_node(P, v, &A, q, x, y, z);
+  }
+  free(allow);
+  return ORC_OK;
+}
+
 /* Public: Step 3.2 + Step 4 -- independent value iteration in every patch,
  * then merge.  `only_patch` >= 0 solves that single patch (other nodes of v
  * are left at 1 / 0).  Patch boundary: state constraint (other patches'

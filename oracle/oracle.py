@@ -66,6 +66,7 @@ def lib():
         L.orc_solve_patches_ex.argtypes = [vp, vp, vp, d, vp, vp, d, i32, i32, vp, vp, vp]
         L.orc_cone_allowed.argtypes = [vp, d, vp]
         L.orc_exclude.argtypes = [vp, vp, d, vp]
+        L.orc_F_at_ex.argtypes = [vp, vp, i32, vp, d, vp, vp, vp, C.c_longlong, vp]
         L.orc_exclude.restype = C.c_longlong
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
@@ -145,6 +146,22 @@ def F_at(P, v: np.ndarray, idx: np.ndarray, labels: Optional[np.ndarray] = None,
     lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.int16).ravel()
     _check(lib().orc_F_at(H.ref, _p(lab), int(patch), _p(v), _p(idx), idx.shape[0], _p(out)),
            "F_at")
+    return out
+
+
+def F_at_ex(P, v: np.ndarray, idx: np.ndarray, labels: np.ndarray, patch: int,
+            fb: Optional[np.ndarray] = None, r: float = 0.0, u0: Optional[np.ndarray] = None):
+    """F of patch `patch` at the listed nodes with the add-on options (AO3
+    cones around fb for r > 1, Dirichlet data u0)."""
+    H = _Held(P)
+    v = np.ascontiguousarray(v, dtype=np.float64).ravel()
+    idx = np.ascontiguousarray(idx, dtype=np.int64).ravel()
+    out = np.empty(idx.shape[0], dtype=np.float64)
+    lab = np.ascontiguousarray(labels, dtype=np.int16).ravel()
+    fbc = None if fb is None else np.ascontiguousarray(fb, dtype=np.uint8).ravel()
+    u0c = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64).ravel()
+    _check(lib().orc_F_at_ex(H.ref, _p(lab), int(patch), _p(fbc), float(r), _p(u0c), _p(v),
+                             _p(idx), idx.shape[0], _p(out)), "F_at_ex")
     return out
 
 

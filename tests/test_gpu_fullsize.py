@@ -122,3 +122,49 @@ def test_config3_fullsize(H, orc, pr, stream):
         m = lab[idx] == j
         Fv[m] = orc.F_at(f, vn, idx[m], labels=lab, patch=int(j))
     assert np.abs(Fv - vn[idx]).max() <= 2e-6
+
+
+def test_config2_fullsize_addons(H, orc, pr, stream):
+    """The add-ons at the benchmark's full size (1025^2, launch defaults):
+    AO3 cones with the Dirichlet data of eq. dbc satisfy the fixed-point
+    equation of their own operator at sampled nodes (the oracle evaluates
+    it); the cones alone never go below the basic values; AO2's order gives
+    the basic FP32 bits; AO1 stays within its contraction bound."""
+    import torch
+    f, c = pr.config2(0)
+    gold = np.load(os.path.join(GOLDEN, "config2_s0_full.npz"))
+    F = H.Problem(f, device=True)
+    Cp = H.Problem(c, device=True)
+    with torch.cuda.stream(stream):
+        ch = H.hjb_coarse_solve(Cp, 0.0, 0, stream)
+        ph = H.hjb_build_patches(F, ch, stream)
+        lab = ph.labels()
+        assert np.array_equal(lab, gold["labels"])
+        fb, u0 = ph.feedback(), ph.u0()
+        res = {}
+        for name, kw in (("basic", {}), ("cone", {"control_cone": 4.0}),
+                         ("cone_dbc", {"control_cone": 4.0, "patch_bc": H.HJB_BC_DIRICHLET}),
+                         ("ao2", {"order_window": 6.0})):
+            v = torch.empty(f.N, dtype=torch.float32, device="cuda")
+            st = H.hjb_solve_patches(F, ph, H.HJB_F32, v, 0.0, 0, H.make_opts(**kw), stream)
+            assert st["status"] == H.HJB_OK
+            res[name] = v
+        va = torch.empty(f.N, dtype=torch.float32, device="cuda")
+        H.hjb_solve_patches(F, ph, H.HJB_F32, va, 1e-7, 0, H.make_opts(start_u0=True), stream)
+        torch.cuda.synchronize()
+    r = {k: v.double().cpu().numpy() for k, v in res.items()}
+    assert np.array_equal(r["ao2"], r["basic"])
+    assert np.all(r["cone"] >= r["basic"]) and np.any(r["cone"] > r["basic"])
+    assert np.abs(va.double().cpu().numpy() - r["basic"]).max() <= 4 * 1e-7 * f.beta / (1 - f.beta)
+    vn = r["cone_dbc"]
+    tgt = f.target_part >= 0
+    rng = np.random.default_rng(1)
+    border = np.flatnonzero(np.diff(lab.reshape(f.shape), axis=1).ravel() != 0)[:500]
+    idx = _sample(rng, f.N, 6000, border)
+    idx = idx[~tgt[idx]]
+    Fv = np.empty(idx.size)
+    for j in np.unique(lab[idx]):
+        m = lab[idx] == j
+        Fv[m] = orc.F_at_ex(f, vn, idx[m], lab, int(j), fb, 4.0, u0)
+    assert np.abs(np.minimum(vn[idx], Fv) - vn[idx]).max() <= 2e-7
+    assert np.abs(Fv - vn[idx]).max() <= 2e-6
