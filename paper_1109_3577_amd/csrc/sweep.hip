@@ -881,23 +881,41 @@ k_jacobi(const DevProblem *__restrict__ Pp, const T *__restrict__ vin, T *__rest
         beta = P.beta64 ? P.beta64[g] : P.beta;
         omb = P.beta64 ? 1.0 - beta : P.omb;
       }
-      // tabulated dynamics: displacement (and beta) per control and node
-      const bool tab = sizeof(T) == 4 ? P.foot32 != nullptr : P.foot64 != nullptr;
-      T mI = T(3), best = T(3);
-      for (int k = 0; k < P.nc; ++k) {
-        T d[DIM];
-        const size_t e = (size_t)k * N + g;
-        for (int q = 0; q < DIM; ++q) {
+      T cand;
+      if (sizeof(T) == 4 ? P.foot32 != nullptr : P.foot64 != nullptr) {
+        // tabulated dynamics: displacement (and beta) per control and node;
+        // the minimum is taken over the candidates themselves
+        T best = T(3);
+        for (int k = 0; k < P.nc; ++k) {
+          T d[DIM];
+          const size_t e = (size_t)k * N + g;
+          T b = beta, o = omb;
           if constexpr (sizeof(T) == 4) {
-            if (tab) {
-              d[q] = P.foot32[e * DIM + q] + 2.0f;
-            } else {
-              const float a = ((cf32p)P.ctrl32)[k * DIM + q];
-              d[q] = __builtin_fmaf(c, a, w[q]);
+            for (int q = 0; q < DIM; ++q) d[q] = P.foot32[e * DIM + q] + 2.0f;
+            if (P.bpk32) {
+              b = P.bpk32[e];
+              o = P.opk32[e];
             }
           } else {
-            if (tab) {
-              d[q] = P.foot64[e * DIM + q];
+            for (int q = 0; q < DIM; ++q) d[q] = P.foot64[e * DIM + q];
+            if (P.bpk64) {
+              b = P.bpk64[e];
+              o = 1.0 - b;
+            }
+          }
+          const T I = interp_global<T, DIM>(vin, P.n, px, py, pz, d);
+          const T ck = Ar<T>::kruzkov(b, I, o);
+          best = ck < best ? ck : best;
+        }
+        cand = best;
+      } else {
+        T mI = T(3);
+        for (int k = 0; k < P.nc; ++k) {
+          T d[DIM];
+          for (int q = 0; q < DIM; ++q) {
+            if constexpr (sizeof(T) == 4) {
+              const float a = ((cf32p)P.ctrl32)[k * DIM + q];
+              d[q] = __builtin_fmaf(c, a, w[q]);
             } else {
               const double a = ((cf64p)P.ctrl64)[k * DIM + q];
               double gg = c * a;
@@ -905,28 +923,11 @@ k_jacobi(const DevProblem *__restrict__ Pp, const T *__restrict__ vin, T *__rest
               d[q] = P.step[q] * gg;
             }
           }
-        }
-        const T I = interp_global<T, DIM>(vin, P.n, px, py, pz, d);
-        if (tab) {
-          T b = beta, o = omb;
-          if constexpr (sizeof(T) == 4) {
-            if (P.bpk32) {
-              b = P.bpk32[e];
-              o = P.opk32[e];
-            }
-          } else {
-            if (P.bpk64) {
-              b = P.bpk64[e];
-              o = 1.0 - b;
-            }
-          }
-          const T ck = Ar<T>::kruzkov(b, I, o);
-          best = ck < best ? ck : best;
-        } else {
+          const T I = interp_global<T, DIM>(vin, P.n, px, py, pz, d);
           mI = I < mI ? I : mI;
         }
+        cand = Ar<T>::kruzkov(beta, mI, omb);
       }
-      const T cand = tab ? best : Ar<T>::kruzkov(beta, mI, omb);
       nv = cand < old ? cand : old;
       dd = (double)old - (double)nv;
     }
