@@ -209,7 +209,8 @@ typedef struct {
   int32_t patch_bc;        /* HJB_BC_* (patch solves: hjb_solve_patches,
                               batches, the server); 0 = HJB_BC_STATE */
   double order_window;     /* add-on AO2 (Section "Patchy method's add-ons"),
-                              hjb_solve_patches only, rounds schedule: > 0
+                              patch solves (also batches and the server),
+                              rounds schedule: > 0
                               runs the tiles in the order of their Step 2
                               values.  A tile's key is the smallest minimal
                               time -ln(1 - U^(0)) of its patch nodes; a
@@ -221,8 +222,9 @@ typedef struct {
                               (h = -ln beta).  The fixed point (and so the
                               result, bit for bit) is the same; only the
                               order and the work change.  0 = off. */
-  int32_t start_u0;        /* add-on AO1 (same section), hjb_solve_patches
-                              only, rounds schedule: 1 starts every patch
+  int32_t start_u0;        /* add-on AO1 (same section), patch solves (also
+                              batches and the server, with their tol),
+                              rounds schedule: 1 starts every patch
                               node at U^(0) of Step 2.  U^(0) is not above
                               the fixed point, so the iteration becomes
                               v <- F(v) (values may rise) and stops when no

@@ -80,10 +80,11 @@ SweepShape engine_shape(int dim, bool fp64, const hjb_solve_opts *opts) {
               "batches and the server run in rounds (HJB_SCHED_ASYNC is for single solves)");
   HJB_REQUIRE(!opts || opts->control_cone == 0.0,
               "control_cone is an option of hjb_solve_patches only");
-  HJB_REQUIRE(!opts || opts->order_window == 0.0,
-              "order_window is an option of hjb_solve_patches only");
-  HJB_REQUIRE(!opts || opts->start_u0 == 0, "start_u0 is an option of hjb_solve_patches only");
-  return make_config(dim, fp64, opts, 0.0, 0).shape;
+  HJB_REQUIRE(!opts || opts->start_u0 == 0 || opts->start_u0 == 1, "start_u0 must be 0 or 1");
+  if (!opts) return make_config(dim, fp64, nullptr, 0.0, 0).shape;
+  hjb_solve_opts o = *opts;
+  o.start_u0 = 0;  // the tolerance it needs is checked with the batch's own
+  return make_config(dim, fp64, &o, 0.0, 0).shape;
 }
 
 // Host threads that prepare the problems of a batch at once.
@@ -105,10 +106,21 @@ std::unique_ptr<Prepared> prepare(const hjb_problem *fine, const hjb_problem *co
   pr->P = upload_problem(*fine, !fp64, s, &ctrl);
   pr->patches = build_patches_impl(*pr->P, *C, s);
   const size_t N = pr->P->N;
+  const bool start_u0 = opts && opts->start_u0 == 1;
   pr->v.reset(N * (fp64 ? sizeof(double) : sizeof(float)));
-  HJB_HIP(launch_init_values(fp64, pr->patches->code.as<int16_t>(), N, pr->v.get(), s));
-  pr->items = build_items(*pr->P, pr->patches->code.as<int16_t>(), pr->P->n_parts,
-                          engine_shape(fine->dim, fp64, opts), s);
+  // add-on AO1: every patch node starts at U^(0)
+  HJB_HIP(launch_init_values(fp64, pr->patches->code.as<int16_t>(), N, pr->v.get(), s,
+                             start_u0 ? pr->patches->u0.as<double>() : nullptr));
+  const SweepShape sh = engine_shape(fine->dim, fp64, opts);
+  pr->items = build_items(*pr->P, pr->patches->code.as<int16_t>(), pr->P->n_parts, sh, s);
+  // add-on AO2: keys of the value-ordered schedule from U^(0)
+  if (opts && opts->order_window > 0.0)
+    build_item_keys(*pr->P, pr->patches->code.as<int16_t>(), pr->patches->u0.as<double>(), sh,
+                    pr->items, s);
+  if (start_u0) {  // every item starts away from its fixed point
+    pr->items.seeds.resize(pr->items.items.size());
+    for (size_t i = 0; i < pr->items.seeds.size(); ++i) pr->items.seeds[i] = (int32_t)i;
+  }
   // keep only what the sweeps need (U^(0) as Dirichlet data of eq. dbc)
   if (!opts || opts->patch_bc != HJB_BC_DIRICHLET) pr->patches->u0.release();
   pr->patches->feedback.release();

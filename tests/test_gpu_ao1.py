@@ -90,5 +90,21 @@ def test_ao1_rejections(H, pr):
         H.hjb_solve_global(f, H.HJB_F32, v, 1e-6, opts=o)
     assert e.value.status == H.HJB_EINVAL
     with pytest.raises(H.HjbError) as e:
-        H.hjb_batch_create([f], [c], tol=1e-6, opts=o)
+        H.hjb_batch_create([f], [c], tol=1e-9, opts=o)
     assert e.value.status == H.HJB_EINVAL
+
+
+def test_ao1_batch_within_bound(H, orc, pr):
+    """AO1 in a batch: every problem lies within the contraction bound of
+    the oracle's basic fixed point (the iteration is not monotone, so the
+    bits may differ from a solve alone)."""
+    probs = [pr.variable_speed_2d(7, 97, 17, 24, 6, 0.1, True),
+             pr.variable_speed_2d(8, 130, 17, 32, 12, 0.1, True, drift_sign=-1)]
+    tol = 1e-10
+    b = H.hjb_batch_create([f for f, _ in probs], [c for _, c in probs], H.HJB_F64, tol=tol,
+                           opts=H.make_opts(start_u0=True))
+    H.hjb_batch_run(b)
+    for i, (f, c) in enumerate(probs):
+        got, _ = H.hjb_batch_result(b, i)
+        ref = orc.patchy(f, c)["v"]
+        assert np.abs(got - ref).max() <= 4.0 * tol * f.beta / (1.0 - f.beta), i

@@ -94,6 +94,38 @@ def test_ordered_rejections(H, pr):
     with pytest.raises(H.HjbError) as e:
         H.hjb_solve_global(f, H.HJB_F32, v, opts=H.make_opts(order_window=0.1))
     assert e.value.status == H.HJB_EINVAL
-    with pytest.raises(H.HjbError) as e:
-        H.hjb_batch_create([f], [c], opts=H.make_opts(order_window=0.1))
-    assert e.value.status == H.HJB_EINVAL
+
+
+def test_ordered_batch_and_server_equal_alone(H, pr):
+    """The ordered schedule in a batch and in the server: every problem
+    keeps the FP32 bits of its unordered solve alone."""
+    probs = [pr.variable_speed_2d(7, 97, 17, 24, 6, 0.1, True),
+             pr.variable_speed_2d(8, 130, 17, 32, 12, 0.1, True, drift_sign=-1),
+             pr.variable_speed_3d(3, 29, 9, 98, 2, 4, 0.3, True, "b3d")]
+    alone = []
+    for f, c in probs:
+        ch = H.hjb_coarse_solve(c)
+        ph = H.hjb_build_patches(f, ch)
+        v = _zeros(f.N, False)
+        H.hjb_solve_patches(f, ph, H.HJB_F32, v)
+        alone.append(v.cpu().numpy())
+    o = H.make_opts(order_window=3.0)
+    b = H.hjb_batch_create([f for f, _ in probs], [c for _, c in probs], H.HJB_F32, opts=o)
+    H.hjb_batch_run(b)
+    for i in range(len(probs)):
+        got, _ = H.hjb_batch_result(b, i)
+        assert np.array_equal(got, alone[i]), i
+    S = H.hjb_server_create(2 << 30, H.HJB_F32, opts=o)
+    tickets = [S.submit(f, c) for f, c in probs]
+    done = {}
+    for _ in range(20000):
+        S.step(4)
+        for i, t in enumerate(tickets):
+            if i not in done:
+                v, st = S.poll(t)
+                if v is not None:
+                    done[i] = v
+        if len(done) == len(probs):
+            break
+    for i in range(len(probs)):
+        assert np.array_equal(done[i], alone[i]), i
