@@ -225,6 +225,13 @@ def bench_batch(args):
     coarses = [hjb.Problem(c, device=True) for _, c in probs]
     choice, _ = autotune.tune_batch(fines, coarses, hjb.HJB_F32, args.tol, sample=16)
     opts = autotune.opts_from(choice)
+    # the first preparation also fills the library's device allocation pool
+    # (hipMalloc of the colour fields); the second is the steady state
+    t = time.perf_counter()
+    b = hjb.hjb_batch_create(fines, coarses, hjb.HJB_F32, args.tol, 0, opts)
+    torch.cuda.synchronize()
+    t_prep_cold = time.perf_counter() - t
+    b.free()
     t = time.perf_counter()
     b = hjb.hjb_batch_create(fines, coarses, hjb.HJB_F32, args.tol, 0, opts)
     torch.cuda.synchronize()
@@ -234,6 +241,18 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t_run = time.perf_counter() - t
     nodes = sum(p.N for p in fines)
+    # a few problems solved alone: at tol > 0 the stopping point depends on
+    # the schedule, so the batch may differ from them within the tolerance
+    sampled = []
+    for i in (0, count // 3, (2 * count) // 3, count - 1):
+        got, _ = hjb.hjb_batch_result(b, i)
+        ch = hjb.hjb_coarse_solve(coarses[i])
+        ph = hjb.hjb_build_patches(fines[i], ch)
+        v = torch.empty(fines[i].N, dtype=torch.float32, device="cuda")
+        hjb.hjb_solve_patches(fines[i], ph, hjb.HJB_F32, v, args.tol, 0, opts)
+        sampled.append(float(np.abs(got.astype(np.float64) - v.cpu().double().numpy()).max()))
+        ph.free()
+        ch.free()
     # baseline: the plain global solve of every problem, one after the other
     t = time.perf_counter()
     gupd = 0
@@ -247,8 +266,10 @@ def bench_batch(args):
     print(json.dumps({
         "metric": "batched patchy solve: node-control updates/s and wall time vs sequential "
                   "plain solves", "mode": "batch", "problems": count, "nodes": nodes,
-        "autotuned": choice, "prepare_s": t_prep, "sweep_s": t_run,
-        "batch_total_s": t_prep + t_run, "updates": st["updates"],
+        "autotuned": choice, "prepare_s": t_prep, "prepare_first_call_s": t_prep_cold,
+        "sweep_s": t_run,
+        "batch_total_s": t_prep + t_run, "sampled_max_diff_vs_alone": max(sampled),
+        "updates": st["updates"],
         "updates_per_s": st["updates"] / t_run, "items": st["items"], "rounds": st["rounds"],
         "sequential_plain_global_s": t_seq, "sequential_plain_updates": gupd,
         "speedup_vs_sequential_plain": t_seq / (t_prep + t_run)}))

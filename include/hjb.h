@@ -178,17 +178,20 @@ typedef struct {
 /* Tuning options; NULL or zero fields select the defaults. */
 typedef struct {
   int32_t tile[3];         /* tile shape in nodes; supported (tile, threads):
-                              2D 16x16 and 32x8 with 256; 64x8, 32x16,
-                              64x16 and 32x32 with 256 or 512;
+                              2D 16x16 and 32x8 with 256, 512 or 1024;
+                              32x16 with 256, 512 or 1024; 64x8, 64x16 and
+                              32x32 with 256 or 512;
                               3D 8x8x8 with 256 or 512, 16x8x8 with 256 or
-                              512, 32x8x4 with 256 */
+                              512, 32x8x4 with 256.  More threads than tile
+                              nodes split each node's controls into
+                              threads / nodes slices (same results). */
   int32_t inner_sweeps;    /* max in-LDS sweeps per tile activation */
   int32_t rounds_per_poll; /* sweep rounds enqueued between host polls */
   int32_t schedule;        /* HJB_SCHED_* (JACOBI: hjb_solve_global only) */
   int32_t time_kernels;    /* 1: HIP events around each polled block of
                               sweep launches (kernel time in hjb_stats) */
   int32_t use_graph;       /* 1: replay the polled rounds as a hipGraph */
-  int32_t threads;         /* workgroup size of the sweep kernel: 256 or 512 */
+  int32_t threads;         /* workgroup size of the sweep kernel (see tile) */
   const uint8_t *patch_select; /* host [n_parts] 0/1, NULL = all patches
                                   (hjb_solve_patches only): nodes of
                                   unselected patches are left at 1 */

@@ -84,9 +84,11 @@ def lookup(dim: int, precision: int, N: int, nc: int) -> Optional[dict]:
 
 
 def tune_batch(fines: Sequence, coarses: Sequence, precision: int = hjb.HJB_F32,
-               tol: float = 1e-5, sample: int = 8, verbose: bool = False) -> Tuple[dict, float]:
+               tol: float = 1e-5, sample: int = 8, verbose: bool = False,
+               repeats: int = 2) -> Tuple[dict, float]:
     """Picks tile / threads / sweeps for a batch by timing hjb_batch_run on a
-    sample of its problems; returns (choice, ms of the best sample run)."""
+    sample of its problems (best of `repeats` runs, a fresh batch each);
+    returns (choice, ms of the best sample run)."""
     step = max(1, len(fines) // sample)
     fs, cs = list(fines)[::step][:sample], list(coarses)[::step][:sample]
     dims = {hjb._as_problem(f).s.dim for f in fs}
@@ -95,11 +97,13 @@ def tune_batch(fines: Sequence, coarses: Sequence, precision: int = hjb.HJB_F32,
     for tile, nt in CANDIDATES[dim]:
         for K in SWEEPS[dim]:
             o = hjb.make_opts(tile=tile, threads=nt, inner_sweeps=K)
-            b = hjb.hjb_batch_create(fs, cs, precision, tol, 0, o)
-            t = time.perf_counter()
-            b.run()
-            ms = (time.perf_counter() - t) * 1e3
-            b.free()
+            ms = float("inf")
+            for _ in range(max(1, repeats)):
+                b = hjb.hjb_batch_create(fs, cs, precision, tol, 0, o)
+                t = time.perf_counter()
+                b.run()
+                ms = min(ms, (time.perf_counter() - t) * 1e3)
+                b.free()
             if verbose:
                 print(f"[autotune] batch tile {tile} threads {nt} K {K}: {ms:.2f} ms", flush=True)
             if best is None or ms < best["ms"]:

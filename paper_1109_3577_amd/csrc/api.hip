@@ -46,8 +46,8 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
                 "tabulated dynamics run in rounds, without control_cone");
     HJB_REQUIRE(sweep_tab_shape_supported(cfg.shape.dim, cfg.shape.tx, cfg.shape.ty,
                                           cfg.shape.tz, cfg.shape.nt),
-                "tabulated dynamics support the tile shapes 2D 16x16, 32x8 and 3D 8x8x8 with "
-                "256 threads");
+                "tabulated dynamics support the tile shapes 2D 16x16 (256 or 512 threads), "
+                "32x8 and 3D 8x8x8 (256 threads)");
   }
   HJB_REQUIRE(!cfg.start_u0 || u0 != nullptr, "start_u0 needs the Step 2 values");
   HJB_HIP(launch_init_values(fp64, code, P.N, v, s, cfg.start_u0 ? u0 : nullptr));
@@ -93,18 +93,22 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
 // In-tile sweeps of one colour-transport tile activation before it is
 // queued again.
 
-// Steps 2 and 3.1: prolongation, feedback, chunked colour transport, labels.
-std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const CoarseHandle &C,
-                                                  hipStream_t s, double exclude_at) {
-  auto hp = std::make_unique<PatchesHandle>();
-  PatchesHandle &H = *hp;
+// Steps 2 and 3.1, first stage: prolongation, obstacles and exclusion,
+// feedback, colour fields and part masks of one problem.
+std::unique_ptr<TraceJob> trace_begin(const ProblemDev &F, const CoarseHandle &C, hipStream_t s,
+                                      double exclude_at) {
+  auto job = std::make_unique<TraceJob>();
+  job->h = std::make_unique<PatchesHandle>();
+  PatchesHandle &H = *job->h;
   H.dim = F.dim;
   for (int d = 0; d < 3; ++d) H.n[d] = F.n[d];
   H.N = F.N;
   H.n_parts = F.n_parts;
   const size_t N = F.N;
   const int dim = F.dim;
-  double t0 = now_ms();
+  job->t0 = now_ms();
+  HJB_REQUIRE(H.n_parts <= trace_max_parts(), "at most %d target parts are supported (got %d)",
+              trace_max_parts(), H.n_parts);
   H.u0.reset(N * sizeof(double));
   H.feedback.reset(N);
   H.labels.reset(N * sizeof(int16_t));
@@ -138,12 +142,13 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
                          H.u0.as<double>(), s));
   // Obstacle nodes, and the unreachable nodes excluded after Step 1, hold
   // U^(0) = 1 and take no part in Steps 2 and 3.
-  DBuf tp_eff(N * sizeof(int16_t)), nex(sizeof(unsigned long long));
-  HJB_HIP(launch_fill_u32(nex.as<uint32_t>(), 0u, 2, s));
-  HJB_HIP(launch_obstacles(F.tp, H.u0.as<double>(), N, exclude_at, tp_eff.as<int16_t>(),
-                           nex.as<unsigned long long>(), s));
+  job->tp_eff.reset(N * sizeof(int16_t));
+  job->nex.reset(sizeof(unsigned long long));
+  HJB_HIP(launch_fill_u32(job->nex.as<uint32_t>(), 0u, 2, s));
+  HJB_HIP(launch_obstacles(F.tp, H.u0.as<double>(), N, exclude_at, job->tp_eff.as<int16_t>(),
+                           job->nex.as<unsigned long long>(), s));
 
-  TraceArgs a;
+  TraceArgs &a = job->a;
   std::memset(&a, 0, sizeof a);
   const SweepShape tsh = trace_shape(dim);
   const int TT[3] = {tsh.tx, tsh.ty, dim == 3 ? tsh.tz : 1};
@@ -158,7 +163,7 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   a.ctrl64 = F.ctrl64;
   a.speed64 = F.speed64;
   a.drift64 = F.drift64;
-  a.target_part = tp_eff.as<int16_t>();
+  a.target_part = job->tp_eff.as<int16_t>();
   a.beta_node = F.beta64;
   a.foot = F.foot64;
   a.beta_pk = F.bpk64;
@@ -166,16 +171,56 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   a.N = N;
   HJB_HIP(launch_feedback(dim, a, H.u0.as<double>(), H.feedback.as<uint8_t>(), s));
   HJB_HIP(hipStreamSynchronize(s));
-  const double t1 = now_ms();
+  job->t1 = now_ms();
 
-  // Colour transport of all parts in one pass (Step 3.1), then labels.
-  HJB_REQUIRE(H.n_parts <= trace_max_parts(), "at most %d target parts are supported (got %d)",
-              trace_max_parts(), H.n_parts);
+  // Colour fields (Step 3.1): zero, then 1 on the target nodes of their own
+  // part, with the part bits of their tiles.
   const int ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
   a.n_parts = H.n_parts;
   a.words = (H.n_parts + 31) / 32;
-  DBuf phi((size_t)H.n_parts * N * sizeof(double));
-  DBuf masks((size_t)ntiles * a.words * sizeof(uint32_t));
+  job->phi.reset((size_t)H.n_parts * N * sizeof(double));
+  job->masks.reset((size_t)ntiles * a.words * sizeof(uint32_t));
+  a.phi = job->phi.as<double>();
+  a.masks = job->masks.as<uint32_t>();
+  HJB_HIP(launch_fill_f64(a.phi, 0.0, (size_t)H.n_parts * N, s));
+  HJB_HIP(launch_fill_u32(a.masks, 0u, (size_t)ntiles * a.words, s));
+  HJB_HIP(launch_trace_init(dim, a, s));
+  return job;
+}
+
+size_t trace_job_bytes(const hjb_problem &F) {
+  const size_t N = (size_t)F.n[0] * F.n[1] * F.n[2];
+  return N * ((size_t)F.n_parts * sizeof(double) + 8 + 1 + 2 + 2 + 2) + (1u << 16);
+}
+
+// Second stage: the colour transport of every job (all of one dimension)
+// to its exact fixed point, in rounds shared by the jobs.  A tile id is the
+// job's tile_base plus its tile index.
+void trace_rounds(const std::vector<TraceJob *> &jobs, hipStream_t s) {
+  if (jobs.empty()) return;
+  const int dim = jobs[0]->h->dim;
+  const double t0 = now_ms();
+  std::vector<TraceArgs> args;
+  std::vector<int32_t> tile_prob;
+  int max_words = 1;
+  long long total = 0;
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    TraceArgs &a = jobs[j]->a;
+    HJB_REQUIRE(jobs[j]->h->dim == dim, "colour transport jobs of mixed dimensions");
+    const long long nt = (long long)a.ntile[0] * a.ntile[1] * a.ntile[2];
+    HJB_REQUIRE(total + nt < (1ll << 31), "too many tiles in one colour transport");
+    a.tile_base = (int32_t)total;
+    total += nt;
+    max_words = std::max(max_words, a.words);
+    args.push_back(a);
+    if (jobs.size() > 1) tile_prob.insert(tile_prob.end(), (size_t)nt, (int32_t)j);
+  }
+  const int ntiles = (int)total;
+  DBuf args_d(args.size() * sizeof(TraceArgs)), prob_d(tile_prob.size() * sizeof(int32_t));
+  HJB_HIP(hipMemcpyAsync(args_d.get(), args.data(), args_d.bytes(), hipMemcpyHostToDevice, s));
+  if (!tile_prob.empty())
+    HJB_HIP(hipMemcpyAsync(prob_d.get(), tile_prob.data(), prob_d.bytes(), hipMemcpyHostToDevice,
+                           s));
   DBuf lists[2], flags[2], count(4 * sizeof(uint32_t)),
       work(2 * kSlots * sizeof(unsigned long long));
   for (int i = 0; i < 2; ++i) {
@@ -183,13 +228,8 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
     flags[i].reset((size_t)ntiles * sizeof(uint32_t));
     HJB_HIP(launch_fill_u32(flags[i].as<uint32_t>(), 0u, ntiles, s));
   }
-  a.phi = phi.as<double>();
-  a.masks = masks.as<uint32_t>();
-  HJB_HIP(launch_fill_f64(a.phi, 0.0, (size_t)H.n_parts * N, s));
-  HJB_HIP(launch_fill_u32(a.masks, 0u, (size_t)ntiles * a.words, s));
   HJB_HIP(launch_fill_u32(count.as<uint32_t>(), 0u, 4, s));
-  HJB_HIP(hipMemsetAsync(work.get(), 0, work.bytes(), s));
-  HJB_HIP(launch_trace_init(dim, a, s));
+  HJB_HIP(launch_fill_u32(work.as<uint32_t>(), 0u, 4 * kSlots, s));
   PinnedBuf host(64);
   RoundArgs ra;
   std::memset(&ra, 0, sizeof ra);
@@ -200,8 +240,10 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
   ra.list_out = lists[0].as<int32_t>();
   ra.flags_out = flags[0].as<uint32_t>();
   ra.round = 2;
-  HJB_HIP(launch_trace_seed(dim, a, ra, s));
+  for (const TraceJob *j : jobs) HJB_HIP(launch_trace_seed(dim, j->a, ra, s));
   const int grid = std::min(ntiles, 4096);
+  const TraceArgs *args_dev = args_d.as<TraceArgs>();
+  const int32_t *prob_dev = tile_prob.empty() ? nullptr : prob_d.as<int32_t>();
   // Rounds in blocks of 16; the next block is enqueued before the host
   // reads the queue count that the previous one left (pipelined polling).
   const int rpp = 16;
@@ -224,7 +266,7 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
       ra.flags_in = flags[r & 1].as<uint32_t>();
       ra.flags_out = flags[(r + 1) & 1].as<uint32_t>();
       ra.round = r;
-      HJB_HIP(launch_trace(dim, grid, a, ra, s));
+      HJB_HIP(launch_trace(dim, grid, args_dev, prob_dev, max_words, ra, s));
     }
     rounds += rpp;
     HJB_HIP(hipMemcpyAsync(hc + slot, count.as<uint32_t>() + (r % 3), sizeof(uint32_t),
@@ -243,13 +285,7 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
     }
     cur = 1 - cur;
   }
-  HJB_HIP(hipStreamSynchronize(s));
-  DBuf unreached(sizeof(uint32_t) * 2);
-  HJB_HIP(launch_fill_u32(unreached.as<uint32_t>(), 0u, 1, s));
-  HJB_HIP(launch_labels(dim, a, H.labels.as<int16_t>(), unreached.as<uint32_t>(), s));
-  uint32_t un = 0;
   unsigned long long ws[2 * kSlots];
-  HJB_HIP(hipMemcpyAsync(&un, unreached.get(), sizeof un, hipMemcpyDeviceToHost, s));
   HJB_HIP(hipMemcpyAsync(ws, work.get(), sizeof ws, hipMemcpyDeviceToHost, s));
   HJB_HIP(hipStreamSynchronize(s));
   unsigned long long w[2] = {0, 0};
@@ -257,11 +293,38 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
     w[0] += ws[k];
     w[1] += ws[kSlots + k];
   }
+  const SweepShape tsh = trace_shape(dim);
+  const double ms = now_ms() - t0;
+  for (TraceJob *j : jobs) {
+    j->rounds = rounds;
+    // tile activations x parts loaded x tile nodes (upper bound of the
+    // per-node colour updates of one in-tile sweep), over all jobs
+    j->trace_node_updates = (int64_t)w[0] * tsh.tx * tsh.ty * (dim == 3 ? tsh.tz : 1);
+    j->item_runs = (int64_t)w[1];
+    j->ms_rounds = ms;
+  }
+}
+
+// Third stage: labels (with the fill of Remark 3.1 where no colour
+// arrived), codes and statistics; frees the colour fields.
+std::unique_ptr<PatchesHandle> trace_end(TraceJob &job, hipStream_t s) {
+  PatchesHandle &H = *job.h;
+  const TraceArgs &a = job.a;
+  const int dim = H.dim;
+  const size_t N = H.N;
+  const double t1 = now_ms();
+  DBuf unreached(sizeof(uint32_t) * 2);
+  HJB_HIP(launch_fill_u32(unreached.as<uint32_t>(), 0u, 1, s));
+  HJB_HIP(launch_labels(dim, a, H.labels.as<int16_t>(), unreached.as<uint32_t>(), s));
+  uint32_t un = 0;
+  PinnedBuf host(64);
+  HJB_HIP(hipMemcpyAsync(&un, unreached.get(), sizeof un, hipMemcpyDeviceToHost, s));
+  HJB_HIP(hipStreamSynchronize(s));
   if (un > 0) {
     // Remark 3.1 fill of the nodes no colour reached, layer by layer
     DBuf tmp(N * sizeof(int16_t));
     int16_t *cur = H.labels.as<int16_t>(), *nxt = tmp.as<int16_t>();
-    const int32_t n3[3] = {F.n[0], F.n[1], F.n[2]};
+    const int32_t n3[3] = {H.n[0], H.n[1], H.n[2]};
     uint32_t *flag = unreached.as<uint32_t>() + 1;
     uint32_t *hflag = host.as<uint32_t>();
     for (long long layer = 0;; ++layer) {
@@ -276,25 +339,34 @@ std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const Coa
     if (cur != H.labels.as<int16_t>())
       HJB_HIP(hipMemcpyAsync(H.labels.get(), cur, N * sizeof(int16_t), hipMemcpyDeviceToDevice, s));
   }
-  HJB_HIP(launch_make_code(tp_eff.as<int16_t>(), H.labels.as<int16_t>(), nullptr, N,
+  HJB_HIP(launch_make_code(job.tp_eff.as<int16_t>(), H.labels.as<int16_t>(), nullptr, N,
                            H.code.as<int16_t>(), s));
   unsigned long long excluded = 0;
-  HJB_HIP(hipMemcpyAsync(&excluded, nex.get(), sizeof excluded, hipMemcpyDeviceToHost, s));
+  HJB_HIP(hipMemcpyAsync(&excluded, job.nex.get(), sizeof excluded, hipMemcpyDeviceToHost, s));
   HJB_HIP(hipStreamSynchronize(s));
+  job.phi.release();
+  job.masks.release();
   const double t2 = now_ms();
   std::memset(&H.st, 0, sizeof H.st);
-  H.st.ms_prolong_feedback = t1 - t0;
-  H.st.ms_trace = t2 - t1;
-  // tile activations x parts loaded x tile nodes (upper bound of the
-  // per-node colour updates of one in-tile sweep)
-  H.st.trace_node_updates = (int64_t)w[0] * TT[0] * TT[1] * TT[2];
+  H.st.ms_prolong_feedback = job.t1 - job.t0;
+  H.st.ms_trace = job.ms_rounds + (t2 - t1);
+  H.st.trace_node_updates = job.trace_node_updates;
   H.st.unreached = (int32_t)un;
   H.st.excluded = (int32_t)excluded;
-  H.st.rounds = (int32_t)rounds;
-  H.st.item_runs = (int64_t)w[1];
-  H.st.updates = (int64_t)F.N * F.nc;  // feedback evaluations
-  H.st.ms_wall = t2 - t0;
-  return hp;
+  H.st.rounds = (int32_t)job.rounds;
+  H.st.item_runs = job.item_runs;
+  H.st.updates = (int64_t)N * a.nc;  // feedback evaluations
+  H.st.ms_wall = H.st.ms_prolong_feedback + H.st.ms_trace;
+  return std::move(job.h);
+}
+
+// Steps 2 and 3.1 of one problem: prolongation, feedback, colour transport
+// of all parts, labels.
+std::unique_ptr<PatchesHandle> build_patches_impl(const ProblemDev &F, const CoarseHandle &C,
+                                                  hipStream_t s, double exclude_at) {
+  auto job = trace_begin(F, C, s, exclude_at);
+  trace_rounds({job.get()}, s);
+  return trace_end(*job, s);
 }
 
 std::unique_ptr<CoarseHandle> coarse_solve_impl(const hjb_problem *coarse, double tol,
@@ -310,23 +382,25 @@ std::unique_ptr<CoarseHandle> coarse_solve_impl(const hjb_problem *coarse, doubl
   h->v.reset(P->N * sizeof(double));
   DBuf code(P->N * sizeof(int16_t));
   HJB_HIP(launch_make_code(P->tp, nullptr, nullptr, P->N, code.as<int16_t>(), s));
-  // The coarse grid is small (tens of nodes a side): small tiles keep the
-  // per-round latency down.
   hjb_solve_opts eo;
-  std::memset(&eo, 0, sizeof eo);
-  const hjb_solve_opts *op = nullptr;
-  if (P->dim == 2) {
-    eo.tile[0] = 16;
-    eo.tile[1] = 16;
-    eo.tile[2] = 1;
-    eo.threads = 256;
-    eo.inner_sweeps = 8;
-    eo.rounds_per_poll = 16;
-    op = &eo;
-  }
-  *status = engine_solve(*P, code.as<int16_t>(), 1, h->v.get(), true, op, tol, max_sweeps, s,
-                         &h->st, t0);
+  *status = engine_solve(*P, code.as<int16_t>(), 1, h->v.get(), true, coarse_opts(P->dim, &eo),
+                         tol, max_sweeps, s, &h->st, t0);
   return h;
+}
+
+const hjb_solve_opts *coarse_opts(int dim, hjb_solve_opts *buf) {
+  // The coarse grid is small (tens of nodes a side): small tiles keep the
+  // per-round latency down, and two control slices per tile (512 threads
+  // for 16 x 16 nodes) shorten each FP64 sweep.
+  std::memset(buf, 0, sizeof *buf);
+  if (dim != 2) return nullptr;
+  buf->tile[0] = 16;
+  buf->tile[1] = 16;
+  buf->tile[2] = 1;
+  buf->threads = 512;
+  buf->inner_sweeps = 8;
+  buf->rounds_per_poll = 16;
+  return buf;
 }
 
 }  // namespace hjb

@@ -89,15 +89,48 @@ SweepShape engine_shape(int dim, bool fp64, const hjb_solve_opts *opts) {
 
 // Host threads that prepare the problems of a batch at once.
 constexpr int kPrepareThreads = 8;
+// Device bytes of colour fields (and the rest of Steps 2-3.1) that one
+// shared colour transport of a batch may hold; larger batches go in chunks.
+constexpr size_t kTraceBatchBytes = size_t(8) << 30;
 
+// The rest of the preparation after Step 3.1: value grid (add-on AO1 starts
+// it at U^(0)), work items, keys of the value-ordered schedule (add-on AO2),
+// and release of what the sweeps do not read.
+void finish_prepared(Prepared &pr, bool fp64, const hjb_solve_opts *opts, hipStream_t s) {
+  const size_t N = pr.P->N;
+  const bool start_u0 = opts && opts->start_u0 == 1;
+  pr.v.reset(N * (fp64 ? sizeof(double) : sizeof(float)));
+  HJB_HIP(launch_init_values(fp64, pr.patches->code.as<int16_t>(), N, pr.v.get(), s,
+                             start_u0 ? pr.patches->u0.as<double>() : nullptr));
+  const SweepShape sh = engine_shape(pr.P->dim, fp64, opts);
+  pr.items = build_items(*pr.P, pr.patches->code.as<int16_t>(), pr.P->n_parts, sh, s);
+  if (opts && opts->order_window > 0.0)
+    build_item_keys(*pr.P, pr.patches->code.as<int16_t>(), pr.patches->u0.as<double>(), sh,
+                    pr.items, s);
+  if (start_u0) {  // every item starts away from its fixed point
+    pr.items.seeds.resize(pr.items.items.size());
+    for (size_t i = 0; i < pr.items.seeds.size(); ++i) pr.items.seeds[i] = (int32_t)i;
+  }
+  // keep only what the sweeps need (U^(0) as Dirichlet data of eq. dbc);
+  // the stream is synchronised first since the buffers return to the pool
+  HJB_HIP(hipStreamSynchronize(s));
+  if (!opts || opts->patch_bc != HJB_BC_DIRICHLET) pr.patches->u0.release();
+  pr.patches->feedback.release();
+}
+
+void check_batchable(const hjb_problem *fine, const hjb_problem *coarse) {
+  HJB_REQUIRE(fine->foot == nullptr && (!coarse || coarse->foot == nullptr),
+              "tabulated dynamics (foot) are not supported in batches and the server");
+  HJB_REQUIRE(coarse && coarse->dim == fine->dim, "coarse problem missing or of another dimension");
+}
+
+// One problem on its own (a server request): Steps 1-3.1 and the rest.
 std::unique_ptr<Prepared> prepare(const hjb_problem *fine, const hjb_problem *coarse, bool fp64,
                                   const hjb_solve_opts *opts, hipStream_t s) {
   const double t0 = now_ms();
   std::vector<double> ctrl;
   validate_problem(fine, s, &ctrl);
-  HJB_REQUIRE(fine->foot == nullptr && (!coarse || coarse->foot == nullptr),
-              "tabulated dynamics (foot) are not supported in batches and the server");
-  HJB_REQUIRE(coarse && coarse->dim == fine->dim, "coarse problem missing or of another dimension");
+  check_batchable(fine, coarse);
   int cst = HJB_OK;
   auto C = coarse_solve_impl(coarse, 0.0, 0, s, &cst);
   HJB_REQUIRE(cst == HJB_OK, "coarse solve did not converge");
@@ -105,40 +138,20 @@ std::unique_ptr<Prepared> prepare(const hjb_problem *fine, const hjb_problem *co
   pr->dim = fine->dim;
   pr->P = upload_problem(*fine, !fp64, s, &ctrl);
   pr->patches = build_patches_impl(*pr->P, *C, s);
-  const size_t N = pr->P->N;
-  const bool start_u0 = opts && opts->start_u0 == 1;
-  pr->v.reset(N * (fp64 ? sizeof(double) : sizeof(float)));
-  // add-on AO1: every patch node starts at U^(0)
-  HJB_HIP(launch_init_values(fp64, pr->patches->code.as<int16_t>(), N, pr->v.get(), s,
-                             start_u0 ? pr->patches->u0.as<double>() : nullptr));
-  const SweepShape sh = engine_shape(fine->dim, fp64, opts);
-  pr->items = build_items(*pr->P, pr->patches->code.as<int16_t>(), pr->P->n_parts, sh, s);
-  // add-on AO2: keys of the value-ordered schedule from U^(0)
-  if (opts && opts->order_window > 0.0)
-    build_item_keys(*pr->P, pr->patches->code.as<int16_t>(), pr->patches->u0.as<double>(), sh,
-                    pr->items, s);
-  if (start_u0) {  // every item starts away from its fixed point
-    pr->items.seeds.resize(pr->items.items.size());
-    for (size_t i = 0; i < pr->items.seeds.size(); ++i) pr->items.seeds[i] = (int32_t)i;
-  }
-  // keep only what the sweeps need (U^(0) as Dirichlet data of eq. dbc)
-  if (!opts || opts->patch_bc != HJB_BC_DIRICHLET) pr->patches->u0.release();
-  pr->patches->feedback.release();
+  finish_prepared(*pr, fp64, opts, s);
   pr->ms_prepare = now_ms() - t0;
   return pr;
 }
 
-void prepare_all(const hjb_problem *const *fine, const hjb_problem *const *coarse, int count,
-                 bool fp64, const hjb_solve_opts *opts, hipStream_t s,
-                 std::vector<std::unique_ptr<Prepared>> &out) {
+// Runs fn(i, stream) for every i < count on up to kPrepareThreads host
+// threads, each with a stream of its own that is synchronised before the
+// call returns.  The first error is raised again on the calling thread.
+template <typename Fn>
+void for_each_prepare(int count, Fn &&fn) {
+  if (count <= 0) return;
   const int workers = std::min(count, kPrepareThreads);
-  if (workers <= 1) {
-    for (int i = 0; i < count; ++i) out[i] = prepare(fine[i], coarse[i], fp64, opts, s);
-    return;
-  }
   int dev = 0;
   HJB_HIP(hipGetDevice(&dev));
-  HJB_HIP(hipStreamSynchronize(s));  // inputs the caller produced on s are ready
   std::atomic<int> next{0};
   std::mutex em;
   int err_code = HJB_OK;
@@ -153,7 +166,7 @@ void prepare_all(const hjb_problem *const *fine, const hjb_problem *const *coars
           std::lock_guard<std::mutex> g(em);
           if (err_code != HJB_OK) break;
         }
-        out[i] = prepare(fine[i], coarse[i], fp64, opts, ws);
+        fn(i, ws);
       }
       HJB_HIP(hipStreamSynchronize(ws));
     } catch (const ApiError &e) {
@@ -178,6 +191,105 @@ void prepare_all(const hjb_problem *const *fine, const hjb_problem *const *coars
   for (int t = 0; t < workers; ++t) pool.emplace_back(work);
   for (auto &t : pool) t.join();
   if (err_code != HJB_OK) throw_error(err_code, "%s", err_msg.c_str());
+}
+
+// A batch's Step 1 problem on the device, solved with the others.
+struct CoarseJob {
+  std::unique_ptr<ProblemDev> P;
+  DBuf code;
+  ProblemItems items;
+  std::unique_ptr<CoarseHandle> h;
+};
+
+// Prepares every problem of a batch.  The per-problem parts (checks,
+// uploads, feedback, labels, items) run on host threads, a stream each; the
+// iterative parts share their rounds across problems: the Step 1 solves of
+// all problems in one FP64 engine per dimension, and the colour transports
+// (Step 3.1) of a chunk of problems in one round list per dimension.  Every
+// problem gets the bits it gets alone: both iterations are monotone and
+// stop at their exact fixed points.
+void prepare_all(const hjb_problem *const *fine, const hjb_problem *const *coarse, int count,
+                 bool fp64, const hjb_solve_opts *opts, hipStream_t s,
+                 std::vector<std::unique_ptr<Prepared>> &out) {
+  const double t0 = now_ms();
+  HJB_HIP(hipStreamSynchronize(s));  // inputs the caller produced on s are ready
+  std::vector<CoarseJob> cj(count);
+  for_each_prepare(count, [&](int i, hipStream_t ws) {
+    std::vector<double> ctrl, cctrl;
+    validate_problem(fine[i], ws, &ctrl);
+    check_batchable(fine[i], coarse[i]);
+    validate_problem(coarse[i], ws, &cctrl);
+    auto pr = std::make_unique<Prepared>();
+    pr->dim = fine[i]->dim;
+    pr->P = upload_problem(*fine[i], !fp64, ws, &ctrl);
+    CoarseJob &J = cj[i];
+    J.P = upload_problem(*coarse[i], false, ws, &cctrl);
+    const size_t Nc = J.P->N;
+    J.code.reset(Nc * sizeof(int16_t));
+    HJB_HIP(launch_make_code(J.P->tp, nullptr, nullptr, Nc, J.code.as<int16_t>(), ws));
+    J.h = std::make_unique<CoarseHandle>();
+    J.h->dim = J.P->dim;
+    for (int d = 0; d < 3; ++d) J.h->n[d] = J.P->n[d];
+    J.h->N = Nc;
+    J.h->v.reset(Nc * sizeof(double));
+    HJB_HIP(launch_init_values(true, J.code.as<int16_t>(), Nc, J.h->v.get(), ws, nullptr));
+    hjb_solve_opts eo;
+    const SweepShape sh = make_config(J.P->dim, true, coarse_opts(J.P->dim, &eo), 0.0, 0).shape;
+    J.items = build_items(*J.P, J.code.as<int16_t>(), 1, sh, ws);
+    out[i] = std::move(pr);
+  });
+  // Step 1 of every problem: one FP64 engine per dimension, exact fixed point
+  for (int dim = 2; dim <= 3; ++dim) {
+    hjb_solve_opts eo;
+    const SolveConfig cfg = make_config(dim, true, coarse_opts(dim, &eo), 0.0, 0);
+    std::unique_ptr<SweepEngine> e;
+    std::vector<int> idx;
+    for (int i = 0; i < count; ++i) {
+      if (cj[i].P->dim != dim) continue;
+      if (!e) e = std::make_unique<SweepEngine>(cfg, s);
+      e->add_problem(*cj[i].P, cj[i].code.as<int16_t>(), &cj[i].items, cj[i].h->v.get());
+      idx.push_back(i);
+    }
+    if (!e) continue;
+    e->begin();
+    HJB_REQUIRE(e->run() == HJB_OK, "coarse solve did not converge");
+    const std::vector<EngineResult> res = e->results();
+    for (size_t k = 0; k < idx.size(); ++k) {
+      hjb_stats &st = cj[idx[k]].h->st;
+      st.node_updates = (int64_t)res[k].work_nodes;
+      st.updates = (int64_t)res[k].work_nodes * cj[idx[k]].P->nc;
+      st.item_runs = (int64_t)res[k].item_runs;
+      st.rounds = (int32_t)e->rounds();
+      st.residual = res[k].residual;
+    }
+  }
+  // Steps 2 and 3.1 in chunks bounded by the colour-field budget
+  for (int i0 = 0; i0 < count;) {
+    int i1 = i0;
+    size_t bytes = 0;
+    while (i1 < count && (i1 == i0 || bytes + trace_job_bytes(*fine[i1]) <= kTraceBatchBytes))
+      bytes += trace_job_bytes(*fine[i1++]);
+    std::vector<std::unique_ptr<TraceJob>> tj(i1 - i0);
+    for_each_prepare(i1 - i0, [&](int k, hipStream_t ws) {
+      tj[k] = trace_begin(*out[i0 + k]->P, *cj[i0 + k].h, ws);
+    });
+    for (int dim = 2; dim <= 3; ++dim) {
+      std::vector<TraceJob *> js;
+      for (auto &j : tj)
+        if (j->h->dim == dim) js.push_back(j.get());
+      trace_rounds(js, s);
+    }
+    for_each_prepare(i1 - i0, [&](int k, hipStream_t ws) {
+      Prepared &pr = *out[i0 + k];
+      pr.patches = trace_end(*tj[k], ws);
+      tj[k].reset();
+      cj[i0 + k] = CoarseJob();
+      finish_prepared(pr, fp64, opts, ws);
+    });
+    i0 = i1;
+  }
+  const double ms = now_ms() - t0;
+  for (auto &p : out) p->ms_prepare = ms;
 }
 
 size_t footprint_bytes(const hjb_problem &f, const hjb_problem &c, bool fp64) {

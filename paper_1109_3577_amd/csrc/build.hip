@@ -198,8 +198,13 @@ __device__ __forceinline__ double colour_step(const double *c, double t0, double
   return I;
 }
 
+// A round of tile activations.  The list holds tile ids of one or several
+// problems of the same dimension: tile_prob (null: every tile is of
+// problem 0) names the problem of a tile id, whose tiles are numbered from
+// its tile_base.
 template <int DIM, int TX, int TY, int TZ, int NT, int CL>
-__global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
+__global__ void __launch_bounds__(NT)
+k_trace(const TraceArgs *__restrict__ args, const int32_t *__restrict__ tile_prob, RoundArgs ra) {
   constexpr int LX = TX + 2 * HALO;
   constexpr int LY = TY + 2 * HALO;
   constexpr int LZ = (DIM == 3) ? TZ + 2 * HALO : 1;
@@ -225,13 +230,15 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
   const uint32_t r = ra.round;
   if (blockIdx.x == 0 && tid == 0) ra.count[(r + 2) % 3] = 0u;
   const uint32_t nin = ra.count[r % 3];
-  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-  const int W = a.words;
   const int K = ra.inner_sweeps;
 
   for (uint32_t li = blockIdx.x; li < nin; li += gridDim.x) {
-    const int tt = ra.list_in[li];
-    if (tid == 0) ra.flags_in[tt] = 0u;
+    const int gt = ra.list_in[li];
+    const TraceArgs a = args[tile_prob ? tile_prob[gt] : 0];
+    const int tt = gt - a.tile_base;
+    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+    const int W = a.words;
+    if (tid == 0) ra.flags_in[gt] = 0u;
     const int tix = tt % a.ntile[0];
     const int tiy = (tt / a.ntile[0]) % a.ntile[1];
     const int tiz = tt / (a.ntile[0] * a.ntile[1]);
@@ -436,7 +443,7 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
         const int nx = tix + dx, ny = tiy + dy, nz = tiz + dz;
         if (need && nx >= 0 && ny >= 0 && nz >= 0 && nx < a.ntile[0] && ny < a.ntile[1] &&
             nz < a.ntile[2]) {
-          const int t2 = nx + a.ntile[0] * (ny + a.ntile[1] * nz);
+          const int t2 = a.tile_base + nx + a.ntile[0] * (ny + a.ntile[1] * nz);
           if (atomicCAS(&ra.flags_out[t2], 0u, 1u) == 0u) qt = t2;
         }
       }
@@ -451,14 +458,15 @@ __global__ void __launch_bounds__(NT) k_trace(TraceArgs a, RoundArgs ra) {
   }
 }
 
-hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &ra, hipStream_t s) {
-  if (a.words > kMaxTraceWords) return hipErrorInvalidValue;
+hipError_t launch_trace(int dim, int grid, const TraceArgs *args, const int32_t *tile_prob,
+                        int max_words, const RoundArgs &ra, hipStream_t s) {
+  if (max_words > kMaxTraceWords) return hipErrorInvalidValue;
   if (dim == 2)
     hipLaunchKernelGGL((k_trace<2, TR2_TX, TR2_TY, 1, TR2_NT, TR2_CL>), dim3(grid), dim3(TR2_NT),
-                       0, s, a, ra);
+                       0, s, args, tile_prob, ra);
   else
     hipLaunchKernelGGL((k_trace<3, TR3_TX, TR3_TY, TR3_TZ, TR3_NT, TR3_CL>), dim3(grid),
-                       dim3(TR3_NT), 0, s, a, ra);
+                       dim3(TR3_NT), 0, s, args, tile_prob, ra);
   return hipGetLastError();
 }
 
@@ -483,8 +491,8 @@ __global__ void k_trace_seed(TraceArgs a, RoundArgs ra) {
           for (int w = 0; w < a.words; ++w) near = near || a.masks[nb * a.words + w] != 0u;
         }
     if (near) {
-      ra.flags_out[t] = 1u;
-      q = t;
+      ra.flags_out[a.tile_base + t] = 1u;
+      q = a.tile_base + t;
     }
   }
   queue_items(ra, q, nullptr);

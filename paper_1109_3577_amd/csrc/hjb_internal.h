@@ -144,6 +144,7 @@ struct TraceArgs {
   int32_t has_drift;
   int32_t n_parts;   // R
   int32_t words;     // mask words per tile, ceil(R / 32)
+  int32_t tile_base; // id of the problem's first tile in a shared round list
   double step[3];
   double beta;       // per-step factor of the colour transport
   const double *ctrl64;
@@ -225,7 +226,12 @@ int trace_chunk_capacity(int dim);
 int trace_max_parts();
 SweepShape trace_shape(int dim);
 int trace_inner_sweeps(int dim);
-hipError_t launch_trace(int dim, int grid, const TraceArgs &a, const RoundArgs &ra, hipStream_t s);
+// One round of colour transport over the tile ids in ra.list_in: `args`
+// (device) holds the problems, `tile_prob` (device, null for one problem)
+// the problem of every tile id, `max_words` the largest words of them.
+hipError_t launch_trace(int dim, int grid, const TraceArgs *args, const int32_t *tile_prob,
+                        int max_words, const RoundArgs &ra, hipStream_t s);
+// Queues the problem's tiles next to target nodes (ids from a.tile_base).
 hipError_t launch_trace_seed(int dim, const TraceArgs &a, const RoundArgs &ra, hipStream_t s);
 hipError_t launch_labels(int dim, const TraceArgs &a, int16_t *labels, uint32_t *unreached,
                          hipStream_t s);

@@ -295,9 +295,30 @@ struct PatchesHandle {
   hjb_stats st{};
 };
 
+// Engine options of the Step 1 solves (null: the defaults); buf holds them.
+const hjb_solve_opts *coarse_opts(int dim, hjb_solve_opts *buf);
 // Step 1: coarse solve (FP64 exact fixed point for tol = 0).
 std::unique_ptr<CoarseHandle> coarse_solve_impl(const hjb_problem *coarse, double tol,
                                                 int32_t max_sweeps, hipStream_t s, int *status);
+// Steps 2 and 3.1 in three stages, so that problems of one dimension can
+// share the rounds of the colour transport.
+struct TraceJob {
+  std::unique_ptr<PatchesHandle> h;
+  TraceArgs a{};
+  DBuf phi, masks, tp_eff, nex;
+  double t0 = 0.0, t1 = 0.0, ms_rounds = 0.0;
+  long long rounds = 0;
+  int64_t trace_node_updates = 0, item_runs = 0;  // of the shared rounds
+};
+// Prolongation, obstacles and exclusion, feedback, colour fields.
+std::unique_ptr<TraceJob> trace_begin(const ProblemDev &F, const CoarseHandle &C, hipStream_t s,
+                                      double exclude_at = 0.0);
+// Device bytes a job holds until trace_end (colour fields included).
+size_t trace_job_bytes(const hjb_problem &F);
+// Colour transport of the jobs (one dimension) in shared rounds.
+void trace_rounds(const std::vector<TraceJob *> &jobs, hipStream_t s);
+// Labels, codes, statistics; releases the colour fields.
+std::unique_ptr<PatchesHandle> trace_end(TraceJob &job, hipStream_t s);
 // Steps 2 and 3.1 on an uploaded fine problem.
 // exclude_at > 0: nodes off the target with U^(0) >= exclude_at are
 // excluded (Section 4.6) and treated as obstacle nodes.

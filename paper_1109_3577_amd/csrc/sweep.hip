@@ -36,6 +36,12 @@ constexpr int lds_stride() {
   return (DIM == 2 && sizeof(T) == 4) ? LX + ((8 - LX % 32) + 32) % 32 : LX;
 }
 
+// Control slices of a workgroup: a block with more threads than its tile
+// has nodes splits each node's controls over NT / TN threads.
+template <int DIM, int TX, int TY, int TZ, int NT>
+constexpr int ctrl_slices() {
+  return NT > TX * TY * (DIM == 3 ? TZ : 1) ? NT / (TX * TY * (DIM == 3 ? TZ : 1)) : 1;
+}
 
 // Bricks on side (sx, sy, sz) of a tile of NBX x NBY x NBZ bricks: for each
 // axis, the first layer (s = -1), the last (s = +1) or all (s = 0).
@@ -88,16 +94,31 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
   constexpr int LXS = lds_stride<T, DIM, LX>();
   constexpr int LN = LX * LY * LZ;
   constexpr int TN = TX * TY * (DIM == 3 ? TZ : 1);
-  constexpr int NPT = TN / NT;  // bricks per wave
-  constexpr int NW = NT / 64;
+  // CS > 1 control slices: the workgroup holds CS copies of the tile's
+  // bricks, slice c evaluating the c-th share of the controls; slice 0
+  // takes the minimum over the slices and owns the update.  The minimum is
+  // exact, so the values are the same bits as with CS = 1.
+  constexpr int CS = ctrl_slices<DIM, TX, TY, TZ, NT>();
+  constexpr int NTS = NT / CS;    // threads per slice
+  constexpr int NPT = TN / NTS;   // bricks per wave
+  constexpr int NW = NTS / 64;    // waves per slice (brick stride)
+  constexpr int NWT = NT / 64;    // waves of the workgroup
+  static_assert(CS == 1 || MODE != 1, "control cones run with one control slice");
+  __shared__ T s_part[CS > 1 ? (CS - 1) * TN : 1];  // partial minima of slices 1..CS-1
   constexpr int BX = Brick<DIM>::X, BY = Brick<DIM>::Y, BZ = Brick<DIM>::Z;
   constexpr int NBX = TX / BX, NBY = TY / BY, NBZ = (DIM == 3) ? TZ / BZ : 1;
-  static_assert(TN % NT == 0 && NT % 64 == 0, "tile must be a multiple of the block");
+  static_assert(TN % NTS == 0 && NTS % 64 == 0 && NT % CS == 0,
+                "tile must be a multiple of the block");
   static_assert(TX % BX == 0 && TY % BY == 0 && (DIM == 2 || TZ % BZ == 0), "brick tiling");
   static_assert(NBX * NBY * NBZ <= 32, "brick mask is one word");
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
+  // control slice (wave-uniform, so that its control range stays scalar) and
+  // wave within the slice
+  const int slice = CS == 1 ? 0 : __builtin_amdgcn_readfirstlane(wave / NW);
+  const int wv = CS == 1 ? wave : wave % NW;
+  const bool owner = CS == 1 || slice == 0;
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const int tt = item.tile;
   const int tix = tt % P.ntile[0];
@@ -132,7 +153,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
     s_v[lx + LXS * (ly + LY * lz)] = val;
   }
 
-  // This thread's nodes: lane `lane` of brick `wave + j NW`, j < NPT.
+  // This thread's nodes: lane `lane` of brick `wv + j NW`, j < NPT.
   T cc[NPT];
   T ww[NPT][DIM];
   T bb[NPT], oo[NPT];  // beta and 1 - beta of the node (variable step) or the scalars
@@ -144,7 +165,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
   bool bact[NPT];     // brick j holds a node of this patch
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int b = wave + j * NW;
+    const int b = wv + j * NW;
     const int bx = b % NBX, by = (b / NBX) % NBY, bz = b / (NBX * NBY);
     const int lx = bx * BX + lane % BX;
     const int ly = by * BY + (lane / BX) % BY;
@@ -212,22 +233,45 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
   const T tolT = (T)ra.tol;
   const bool plain = P.plain != 0;
   const int ng = (P.nc + 3) >> 2;  // groups of 4 controls (table is padded)
+  // this slice's share of the control groups (of the controls, tabulated)
+  const int g_lo = slice * ng / CS, g_hi = (slice + 1) * ng / CS;
+  const int k_lo = slice * P.nc / CS, k_hi = (slice + 1) * P.nc / CS;
   const int K = ra.inner_sweeps;
   unsigned long long upd = 0;
   bool converged = false;
+  // the owner's update of node j from the minimum over the controls
+  auto update = [&](int j, T mI, uint32_t &mine) {
+    bool chg = false;
+    if (act[j]) {
+      // min_k (beta I_k + omb) == beta (min_k I_k) + omb: the map is
+      // monotone, also after rounding.  The iteration only decreases
+      // v, except from a start below the fixed point (add-on AO1: plain
+      // v <- F(v)).
+      const T cand = TAB ? mI : Ar<T>::kruzkov(bb[j], mI, oo[j]);
+      const T cur = s_v[off[j]];
+      if (plain ? cand != cur : cand < cur) {
+        s_v[off[j]] = cand;
+        chg = cur - cand > tolT || cand - cur > tolT;
+      }
+    }
+    if (__ballot(chg) != 0ull) mine |= 1u << (wv + j * NW);
+  };
   for (int it = 0; it < K; ++it) {
     const uint32_t prev = s_msk[(it + 2) % 3];
     if (tid == 0) s_msk[(it + 1) % 3] = 0u;
     uint32_t mine = 0u;
+    bool run[NPT];
+    T mIs[NPT];
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
       // Skip the brick when nothing within its reach changed in the last
       // sweep: its update would read the same values and change nothing.
       // A brick with no node of this patch (tiles that straddle patches) has
-      // nothing to update either.
-      const uint32_t bj = 1u << (wave + j * NW);
-      if (!bact[j] || (it == 0 ? (first & bj) == 0u : (prev & nbm[j]) == 0u)) continue;
-      upd += act[j] ? 1u : 0u;
+      // nothing to update either.  Every slice takes the same decision.
+      const uint32_t bj = 1u << (wv + j * NW);
+      run[j] = bact[j] && (it == 0 ? (first & bj) != 0u : (prev & nbm[j]) != 0u);
+      if (!run[j]) continue;
+      if (owner) upd += act[j] ? 1u : 0u;
       T mI = T(3);
       if constexpr (CONE) {
         // the node's cone: its index row holds four control indices per
@@ -295,7 +339,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
         // mI collects the candidates beta I + 1 - beta themselves
         const size_t Nn = (size_t)n0 * n1 * n2;
         const int b2 = off[j] - 2 - 2 * LXS - (DIM == 3 ? 2 * LXS * LY : 0);
-        for (int k = 0; k < P.nc; ++k) {
+        for (int k = k_lo; k < k_hi; ++k) {
           const size_t e = act[j] ? (size_t)k * Nn + gid[j] : 0;
           T b = bb[j], o = oo[j], I;
           if constexpr (sizeof(T) == 4) {
@@ -322,7 +366,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
         }
       } else if constexpr (sizeof(T) == 4) {
         const int b2 = off[j] - 2 - 2 * LXS - (DIM == 3 ? 2 * LXS * LY : 0);
-        for (int g4 = 0; g4 < ng; ++g4) {
+        for (int g4 = g_lo; g4 < g_hi; ++g4) {
           float a[4 * DIM];
 #pragma unroll
           for (int q = 0; q < 4 * DIM; ++q) a[q] = ((cf32p)P.ctrl32)[g4 * 4 * DIM + q];
@@ -335,7 +379,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
           }
         }
       } else {
-        for (int k = 0; k < 4 * ng; ++k) {
+        for (int k = 4 * g_lo; k < 4 * g_hi; ++k) {
           T d[DIM];
 #pragma unroll
           for (int q = 0; q < DIM; ++q) {
@@ -347,20 +391,30 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
           mI = I < mI ? I : mI;
         }
       }
-      bool chg = false;
-      if (act[j]) {
-        // min_k (beta I_k + omb) == beta (min_k I_k) + omb: the map is
-        // monotone, also after rounding.  The iteration only decreases
-        // v, except from a start below the fixed point (add-on AO1: plain
-        // v <- F(v)).
-        const T cand = TAB ? mI : Ar<T>::kruzkov(bb[j], mI, oo[j]);
-        const T cur = s_v[off[j]];
-        if (plain ? cand != cur : cand < cur) {
-          s_v[off[j]] = cand;
-          chg = cur - cand > tolT || cand - cur > tolT;
+      if constexpr (CS == 1) {
+        update(j, mI, mine);
+      } else if (owner) {
+        mIs[j] = mI;
+      } else {
+        s_part[(slice - 1) * TN + (wv + j * NW) * 64 + lane] = mI;
+      }
+    }
+    if constexpr (CS > 1) {
+      // the partial minima of the other slices are in LDS after the barrier
+      __syncthreads();
+      if (owner) {
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+          if (!run[j]) continue;
+          T mI = mIs[j];
+#pragma unroll
+          for (int c = 1; c < CS; ++c) {
+            const T pc = s_part[(c - 1) * TN + (wv + j * NW) * 64 + lane];
+            mI = pc < mI ? pc : mI;
+          }
+          update(j, mI, mine);
         }
       }
-      if (__ballot(chg) != 0ull) mine |= 1u << (wave + j * NW);
     }
     if (lane == 0 && mine) atomicOr(&s_msk[it % 3], mine);
     __syncthreads();
@@ -378,7 +432,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     bool big = false;
-    if (act[j]) {
+    if (owner && act[j]) {
       const T nv = s_v[off[j]];
       if (nv != old[j]) {
         if (ASYNC) st_dev(&v[gid[j]], nv);
@@ -388,7 +442,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
         big = old[j] - nv > tolT || nv - old[j] > tolT;
       }
     }
-    brick_box<DIM, NBX, NBY>(__ballot(big), wave + j * NW, bx0, bx1, by0, by1, bz0, bz1);
+    brick_box<DIM, NBX, NBY>(__ballot(big), wv + j * NW, bx0, bx1, by0, by1, bz0, bz1);
   }
   // The value stores are device-scope (written through to the coherent
   // level); each wave waits for its stores to complete, so after the
@@ -420,7 +474,7 @@ __device__ __forceinline__ bool sweep_item(const DevProblem &P, const Item &item
   if (tid == 0) {
     double m = 0.0;
     unsigned long long wsum = 0;
-    for (int w = 0; w < NW; ++w) {
+    for (int w = 0; w < NWT; ++w) {
       m = s_red[w] > m ? s_red[w] : m;
       wsum += s_wrk[w];
     }
@@ -724,6 +778,11 @@ k_sweep_async(const DevProblem *__restrict__ probs, const Item *__restrict__ ite
   X(2, 32, 16, 1, 512)     \
   X(2, 64, 16, 1, 512)     \
   X(2, 32, 32, 1, 512)     \
+  X(2, 32, 8, 1, 512)      \
+  X(2, 32, 8, 1, 1024)     \
+  X(2, 16, 16, 1, 512)     \
+  X(2, 16, 16, 1, 1024)    \
+  X(2, 32, 16, 1, 1024)    \
   X(3, 16, 8, 8, 256)      \
   X(3, 8, 8, 8, 256)       \
   X(3, 32, 8, 4, 256)      \
@@ -815,6 +874,7 @@ hipError_t launch_sweep_cone(bool fp64, SweepShape sh, int grid, const DevProble
 
 #define HJB_TAB_SHAPES(X) \
   X(2, 16, 16, 1, 256)      \
+  X(2, 16, 16, 1, 512)      \
   X(2, 32, 8, 1, 256)       \
   X(3, 8, 8, 8, 256)
 

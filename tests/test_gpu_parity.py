@@ -292,3 +292,38 @@ def test_device_resident_inputs(H, orc, pr):
     v = _zeros(f.N, True)
     H.hjb_solve_patches(f, ph, H.HJB_F64, v, device=True)
     assert np.array_equal(_np(v), out["v"])
+
+
+@pytest.mark.parametrize("case", ["2d", "2d_drift"])
+def test_control_slices_bitwise_equal(H, orc, pr, case):
+    """Workgroups with more threads than tile nodes split each node's
+    controls over 2 or 4 slices; the minimum is exact, so FP64 stays
+    bit-exact against the oracle and FP32 keeps the bits of one slice."""
+    if case == "2d":
+        f, c = pr.variable_speed_2d(5, 131, 17, 32, 8, 0.1, True)
+    else:
+        f, c = pr.variable_speed_2d(6, 97, 17, 20, 6, 0.1, True, drift_sign=-1)
+    out = orc.patchy(f, c)
+    ch = H.hjb_coarse_solve(c)
+    ph = H.hjb_build_patches(f, ch)
+    ref32 = _zeros(f.N, False)
+    H.hjb_solve_patches(f, ph, H.HJB_F32, ref32)
+    for tile, nt, K, sched in [((32, 8, 1), 512, 8, H.HJB_SCHED_TILED),
+                               ((32, 8, 1), 1024, 12, H.HJB_SCHED_TILED),
+                               ((16, 16, 1), 512, 3, H.HJB_SCHED_TILED),
+                               ((16, 16, 1), 1024, 8, H.HJB_SCHED_ASYNC),
+                               ((32, 16, 1), 1024, 16, H.HJB_SCHED_TILED)]:
+        o = H.make_opts(tile=tile, threads=nt, inner_sweeps=K, schedule=sched)
+        v64 = _zeros(f.N, True)
+        st = H.hjb_solve_patches(f, ph, H.HJB_F64, v64, opts=o)
+        assert st["threads"] == nt
+        assert np.array_equal(_np(v64), out["v"]), (tile, nt)
+        v32 = _zeros(f.N, False)
+        H.hjb_solve_patches(f, ph, H.HJB_F32, v32, opts=o)
+        assert np.array_equal(_np(v32), _np(ref32)), (tile, nt)
+    # the global solve (and so the coarse solve) with slices is the exact
+    # fixed point of the oracle's Jacobi iteration
+    g = _zeros(c.N, True)
+    H.hjb_solve_global(c, H.HJB_F64, g, opts=H.make_opts(tile=(16, 16, 1), threads=1024,
+                                                          inner_sweeps=8))
+    assert np.array_equal(_np(g), orc.solve_global(c)[0])
