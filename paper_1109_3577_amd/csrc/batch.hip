@@ -89,8 +89,9 @@ SweepShape engine_shape(int dim, bool fp64, const hjb_solve_opts *opts) {
 
 // Host threads that prepare the problems of a batch at once.
 constexpr int kPrepareThreads = 8;
-// Device bytes of colour fields (and the rest of Steps 2-3.1) that one
-// shared colour transport of a batch may hold; larger batches go in chunks.
+// Default device bytes of colour fields (and the rest of Steps 2-3.1) that
+// one shared colour transport of a batch may hold; larger batches go in
+// chunks.
 constexpr size_t kTraceBatchBytes = size_t(8) << 30;
 
 // The rest of the preparation after Step 3.1: value grid (add-on AO1 starts
@@ -209,7 +210,7 @@ struct CoarseJob {
 // problem gets the bits it gets alone: both iterations are monotone and
 // stop at their exact fixed points.
 void prepare_all(const hjb_problem *const *fine, const hjb_problem *const *coarse, int count,
-                 bool fp64, const hjb_solve_opts *opts, hipStream_t s,
+                 bool fp64, const hjb_solve_opts *opts, size_t chunk_bytes, hipStream_t s,
                  std::vector<std::unique_ptr<Prepared>> &out) {
   const double t0 = now_ms();
   HJB_HIP(hipStreamSynchronize(s));  // inputs the caller produced on s are ready
@@ -267,7 +268,7 @@ void prepare_all(const hjb_problem *const *fine, const hjb_problem *const *coars
   for (int i0 = 0; i0 < count;) {
     int i1 = i0;
     size_t bytes = 0;
-    while (i1 < count && (i1 == i0 || bytes + trace_job_bytes(*fine[i1]) <= kTraceBatchBytes))
+    while (i1 < count && (i1 == i0 || bytes + trace_job_bytes(*fine[i1]) <= chunk_bytes))
       bytes += trace_job_bytes(*fine[i1++]);
     std::vector<std::unique_ptr<TraceJob>> tj(i1 - i0);
     for_each_prepare(i1 - i0, [&](int k, hipStream_t ws) {
@@ -339,7 +340,8 @@ int hjb_batch_create(const hjb_problem *const *fine, const hjb_problem *const *c
     // chain of short, mostly latency-bound steps per problem: several host
     // threads prepare problems at once, each on a stream of its own.
     b->probs.resize(count);
-    prepare_all(fine, coarse, count, b->fp64, &b->opts.solve, b->s, b->probs);
+    const size_t chunk = b->opts.prepare_bytes ? (size_t)b->opts.prepare_bytes : kTraceBatchBytes;
+    prepare_all(fine, coarse, count, b->fp64, &b->opts.solve, chunk, b->s, b->probs);
     for (int d = 0; d < 2; ++d) {
       const int dim = d + 2;
       SolveConfig cfg = make_config(dim, b->fp64, &b->opts.solve, b->opts.tol, b->opts.max_sweeps);

@@ -76,7 +76,7 @@ class hjb_build_opts(C.Structure):
 
 class hjb_batch_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("max_sweeps", C.c_int32),
-                ("solve", hjb_solve_opts)]
+                ("solve", hjb_solve_opts), ("prepare_bytes", C.c_uint64)]
 
 
 class hjb_server_opts(C.Structure):
@@ -357,7 +357,7 @@ def _check_out(v_out, N, precision):
 class Batch:
     def __init__(self, fines: Sequence, coarses: Sequence, precision: int = HJB_F32,
                  tol: float = 0.0, max_sweeps: int = 0, opts: Optional[hjb_solve_opts] = None,
-                 stream=None, device: bool = False):
+                 stream=None, device: bool = False, prepare_bytes: int = 0):
         self.fines = [_as_problem(f, device) for f in fines]
         self.coarses = [_as_problem(c, device) for c in coarses]
         n = len(self.fines)
@@ -367,6 +367,7 @@ class Batch:
         bo.precision = int(precision)
         bo.tol = float(tol)
         bo.max_sweeps = int(max_sweeps)
+        bo.prepare_bytes = int(prepare_bytes)
         if opts is not None:
             bo.solve = opts
         self.precision = precision
@@ -400,8 +401,8 @@ class Batch:
 
 
 def hjb_batch_create(fines, coarses, precision=HJB_F32, tol=0.0, max_sweeps=0, opts=None,
-                     stream=None, device=False) -> Batch:
-    return Batch(fines, coarses, precision, tol, max_sweeps, opts, stream, device)
+                     stream=None, device=False, prepare_bytes=0) -> Batch:
+    return Batch(fines, coarses, precision, tol, max_sweeps, opts, stream, device, prepare_bytes)
 
 
 def hjb_batch_run(b: Batch) -> dict:

@@ -118,3 +118,18 @@ def test_server_admission_by_budget(H, pr):
             break
         S.step(4)
     assert np.array_equal(out[t1], out[t2])
+
+
+@pytest.mark.parametrize("prepare_bytes", [1, 10 << 20])
+def test_batch_preparation_chunks_equal_alone(H, pr, prepare_bytes):
+    """The shared colour transport of a batch's preparation in chunks (one
+    problem per chunk, or a few): every result keeps the bits of its solve
+    alone."""
+    probs = _mixed_problems(pr)
+    b = H.hjb_batch_create([f for f, _ in probs], [c for _, c in probs], H.HJB_F32,
+                           prepare_bytes=prepare_bytes)
+    H.hjb_batch_run(b)
+    for i, (f, c) in enumerate(probs):
+        got, _ = H.hjb_batch_result(b, i)
+        ref, _ = _alone(H, f, c, H.HJB_F32)
+        assert np.array_equal(got, ref), i
