@@ -223,7 +223,9 @@ def bench_batch(args):
           file=sys.stderr, flush=True)
     fines = [hjb.Problem(f, device=True) for f, _ in probs]
     coarses = [hjb.Problem(c, device=True) for _, c in probs]
-    choice, _ = autotune.tune_batch(fines, coarses, hjb.HJB_F32, args.tol, sample=16)
+    # a sample large enough that its rounds are throughput-bound like the
+    # full batch's (small samples favour small tiles)
+    choice, _ = autotune.tune_batch(fines, coarses, hjb.HJB_F32, args.tol, sample=64)
     opts = autotune.opts_from(choice)
     # the first preparation also fills the library's device allocation pool
     # (hipMalloc of the colour fields); the second is the steady state
