@@ -38,8 +38,10 @@
  *     conditions"): in patch j, non-target nodes with another label are
  *     ghosts with value 1; all target nodes are 0 in every patch;
  *   - feedback: the first control (ascending k) attaining the minimum of the
- *     interpolated value I[U^(0)] (raw I, before the affine Kruzkov map);
- *     target nodes carry no feedback (255);
+ *     scheme's right-hand side beta_k I[U^(0)] + 1 - beta_k; when beta does
+ *     not depend on the control this is the minimum of the raw I (compared
+ *     before the affine Kruzkov map, which could round distinct I to equal
+ *     values); target nodes carry no feedback (255);
  *   - colours: target nodes are fixed (1 on their own part, 0 elsewhere),
  *     non-target nodes start at 0 and rise as phi <- max(phi, beta I[phi])
  *     until nothing changes.  The factor beta = exp(-h) is the scheme's own
@@ -381,9 +383,26 @@ int orc_prolong(const orc_problem *C, const double *vc, const orc_problem *F, do
   return ORC_OK;
 }
 
+/* The quantity the feedback minimises over k at node q, given the
+ * interpolated Step 2 value I at the foot point of control k.  Eq.
+ * feedbackcontrol minimises I[U^(0)](foot) + h_{i,a} in the time variable,
+ * i.e. the scheme's own right-hand side; in the Kruzkov variable that is
+ * beta_k I + (1 - beta_k).  When beta does not depend on the control (one
+ * beta, or one per node) that map is increasing in I, so I itself is
+ * compared (the affine map could round distinct I to equal values); with
+ * per-control factors (the step rule on tabulated dynamics) the step must
+ * enter, or slow controls win on the value of their foot alone. */
+static double orc_feedback_key(const orc_problem *F, long long q, int k, double I) {
+  if (!F->beta_pk) return I;
+  double b = F->beta_pk[(long long)k * orc_N(F) + q];
+  double bI = b * I;
+  return bI + (1.0 - b);
+}
+
 /* Public: Step 2, discrete feedback (eq. feedbackcontrol): for every
- * non-target fine node the first k minimising I[U^(0)](p + s(c a_k + w)),
- * ghost 1 outside the box, every node active.  Target nodes get 255. */
+ * non-target fine node the first k minimising the scheme's right-hand side
+ * at I[U^(0)](p + s(c a_k + w)) (orc_feedback_key), ghost 1 outside the
+ * box, every node active.  Target nodes get 255. */
 int orc_feedback(const orc_problem *F, const double *u0, uint8_t *fb) {
   if (orc_check(F) || F->n_controls > 255) return ORC_EINVAL;
   long long nx = F->n[0], ny = F->n[1], nz = F->n[2];
@@ -398,7 +417,7 @@ int orc_feedback(const orc_problem *F, const double *u0, uint8_t *fb) {
         for (int k = 0; k < F->n_controls; ++k) {
           double disp[3];
           orc_displacement(F, q, k, disp);
-          double I = orc_interp(F, u0, NULL, x, y, z, disp, 1.0);
+          double I = orc_feedback_key(F, q, k, orc_interp(F, u0, NULL, x, y, z, disp, 1.0));
           if (I < best) { best = I; bk = k; }
         }
         fb[q] = (uint8_t)bk;
@@ -422,7 +441,7 @@ int orc_feedback_at(const orc_problem *F, const double *u0, const long long *idx
     for (int k = 0; k < F->n_controls; ++k) {
       double disp[3];
       orc_displacement(F, q, k, disp);
-      double I = orc_interp(F, u0, NULL, x, y, z, disp, 1.0);
+      double I = orc_feedback_key(F, q, k, orc_interp(F, u0, NULL, x, y, z, disp, 1.0));
       if (I < best) { best = I; bk = k; }
     }
     fb[i] = (uint8_t)bk;

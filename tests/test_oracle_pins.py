@@ -949,6 +949,49 @@ def test_lunar_landing_point_symmetry(orc, pr):
     assert np.abs(W - W[::-1, ::-1]).max() < 1e-12
 
 
+def test_feedback_attains_scheme_minimum_with_step_rule(orc, pr):
+    """Eq. feedbackcontrol minimises the value at the foot point plus the
+    step h_{i,a}, i.e. the scheme's own right-hand side.  With the step rule
+    the step depends on the control (Zermelo: |f| from 0.1 to 4.1), so with
+    the exact fine solution as Step 2 data the chosen control must attain
+    the scheme's minimum at every non-target node: the problem restricted to
+    the chosen control (one control per node, taken from the tables) has the
+    same F there, bit for bit.  Choosing on the foot value alone fails this
+    at most nodes off the current's axis."""
+    n = 61
+    Z = pr.zermelo_paper_2d(n, 32, 16)
+    v, _ = orc.solve_global(Z)
+    fb = orc.feedback(Z, v)
+    free = Z.target_part < 0
+    q = np.arange(Z.N)
+    k = np.where(free, fb, 0).astype(np.int64)
+    Z1 = dataclasses.replace(Z, controls=Z.controls[:1].copy(),
+                             foot=np.ascontiguousarray(Z.foot[k, q][None]),
+                             beta_pk=np.ascontiguousarray(Z.beta_pk[k, q][None]))
+    full = orc.apply_F(Z, v)
+    one = orc.apply_F(Z1, v)
+    assert np.array_equal(one[free], full[free])
+    assert np.array_equal(full[free], v[free])  # v is the fixed point
+
+
+def test_zermelo_patchy_error_matches_paper_magnitude(orc, pr):
+    """Table patchy_error_zermelo (N_c = 32, R = 16, coarse and fine 100^2):
+    E1 = 0.00631 in the time variable.  The same run here (101^2 / 101^2, an
+    odd side so that the grid holds the target's centre; FP64) gives E1
+    within a factor of 3 of it.  (With the feedback chosen on the foot
+    value alone, without the step, it was 1.3, some 200 times larger.)"""
+    with open(os.path.join(GOLDEN, "paper_patchy_error_trend.json")) as fh:
+        paper = json.load(fh)["zermelo"]["coarse_100"]["E1"][0]
+    f = pr.zermelo_paper_2d(101, 32, 16)
+    c = pr.zermelo_paper_2d(101, 32, 16)
+    out = orc.patchy(f, c)
+    vg, _ = orc.solve_global(f)
+    ok = (vg < 1.0) & (out["v"] < 1.0)
+    assert ok.mean() > 0.99
+    e1 = np.abs(np.log1p(-out["v"][ok]) - np.log1p(-vg[ok])).mean()
+    assert paper / 3.0 < e1 < paper * 3.0, e1
+
+
 def test_zermelo_patchy_error_decreases_with_N(orc, pr):
     """Section 4.2, Table patchy_error_zermelo: the patchy error E1 of the
     Zermelo problem (paper's domain, dynamics and step rule, R = 16)
