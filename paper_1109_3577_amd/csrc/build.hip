@@ -4,7 +4,9 @@
 //
 //   k_prolong        U^(0) = linear interpolation of the coarse values;
 //   k_feedback       discrete feedback, eq. feedbackcontrol: the first
-//                    control minimising I[U^(0)] at the foot point;
+//                    control minimising the scheme's right-hand side at the
+//                    foot point, beta_k I[U^(0)] + 1 - beta_k (I alone when
+//                    beta does not depend on the control);
 //   k_trace          colour transport with frozen feedback, eq.
 //                    HJBridotta_discreta, for a chunk of parts at once,
 //                    iterated from below (phi <- max(phi, I[phi])) on LDS
@@ -102,7 +104,14 @@ k_feedback(TraceArgs a, const double *__restrict__ u0, uint8_t *__restrict__ fb)
   for (int k = 0; k < a.nc; ++k) {
     double d[DIM];
     displacement64<DIM>(a, g, k, d);
-    const double I = interp_global<double, DIM>(u0, a.n, px, py, pz, d);
+    double I = interp_global<double, DIM>(u0, a.n, px, py, pz, d);
+    if (a.beta_pk) {
+      // the step depends on the control: compare the scheme's right-hand
+      // side beta_k I + 1 - beta_k (time at the foot plus the step)
+      const double b = a.beta_pk[(size_t)k * a.N + g];
+      const double bI = b * I;
+      I = bI + (1.0 - b);
+    }
     if (k == 0 || I < best) {
       best = I;
       bk = k;
