@@ -259,12 +259,16 @@ void hjb_coarse_free(hjb_coarse_t *c);
 /* Steps 2 and 3.1 of the Patchy Algorithm (Section 3), FP64:
  *   - U^(0) = linear interpolation of the coarse values at the fine nodes;
  *   - discrete feedback (eq. feedbackcontrol): at every non-target fine node
- *     the first control k minimising I[U^(0)](p + s (c a_k + w)) (ghost 1
- *     outside the box); target nodes carry 255;
+ *     the first control k minimising the scheme's right-hand side at the
+ *     foot point, beta_k I_k + 1 - beta_k with I_k = I[U^(0)](p + s (c a_k
+ *     + w)) (ghost 1 outside the box); when beta does not depend on the
+ *     control (no beta_pk table) the raw I_k is compared; target nodes
+ *     carry 255;
  *   - for every part j the colour transport with frozen feedback (eq.
  *     HJBridotta_discreta), phi^j = 1 on part j of the target, 0 on the rest
- *     of it, phi <- max(phi, I[phi](foot of the feedback)) from 0 until no
- *     node changes (ghost 0 outside the box);
+ *     of it, phi <- max(phi, beta I[phi](foot of the feedback)) from 0
+ *     until no node changes (ghost 0 outside the box; colours below 1e-9
+ *     count as 0);
  *   - labels (eq. proiezionecolore with Remark 3.1): target node -> its
  *     part; obstacle node -> HJB_OBSTACLE; otherwise the part of largest
  *     colour, the lowest index on ties, and where every colour is 0 the
