@@ -341,7 +341,7 @@ typedef struct {
   uint64_t prepare_bytes;  /* device bytes that the shared colour transport
                               of hjb_batch_create may hold at once (colour
                               fields and the rest of Steps 2-3.1); problems
-                              beyond it go to the next chunk.  0 = 8 GiB. */
+                              beyond it go to the next chunk.  0 = 32 GiB. */
 } hjb_batch_opts;
 
 /* fine[i] and coarse[i] describe problem i; the call runs Steps 1-3.1 for
