@@ -241,7 +241,7 @@ void trace_rounds(const std::vector<TraceJob *> &jobs, hipStream_t s) {
   ra.flags_out = flags[0].as<uint32_t>();
   ra.round = 2;
   for (const TraceJob *j : jobs) HJB_HIP(launch_trace_seed(dim, j->a, ra, s));
-  const int grid = std::min(ntiles, 4096);
+  const int grid = (int)std::min<long long>((long long)ntiles * trace_split(dim), 4096);
   const TraceArgs *args_dev = args_d.as<TraceArgs>();
   const int32_t *prob_dev = tile_prob.empty() ? nullptr : prob_d.as<int32_t>();
   // Rounds in blocks of 16; the next block is enqueued before the host

@@ -155,13 +155,14 @@ constexpr double kColourFloor = 1e-9;
 // the 64 small target parts (about 15 per tile) and the work is throughput-
 // bound, where small LDS groups (more workgroups per CU) and short
 // activations pay.
-constexpr int TR2_TX = 32, TR2_TY = 16, TR2_NT = 512, TR2_CL = 8, TR2_K = 24;
-constexpr int TR3_TX = 8, TR3_TY = 8, TR3_TZ = 8, TR3_NT = 256, TR3_CL = 2, TR3_K = 6;
+constexpr int TR2_TX = 32, TR2_TY = 16, TR2_NT = 512, TR2_CL = 8, TR2_K = 24, TR2_SPLIT = 2;
+constexpr int TR3_TX = 8, TR3_TY = 8, TR3_TZ = 8, TR3_NT = 256, TR3_CL = 2, TR3_K = 6, TR3_SPLIT = 1;
 constexpr int kMaxTraceWords = 32;  // up to 1024 parts
 
 int trace_chunk_capacity(int dim) { return dim == 2 ? TR2_CL : TR3_CL; }
 int trace_max_parts() { return kMaxTraceWords * 32; }
 int trace_inner_sweeps(int dim) { return dim == 2 ? TR2_K : TR3_K; }
+int trace_split(int dim) { return dim == 2 ? TR2_SPLIT : TR3_SPLIT; }
 SweepShape trace_shape(int dim) {
   return dim == 2 ? SweepShape{2, TR2_TX, TR2_TY, 1, TR2_NT}
                   : SweepShape{3, TR3_TX, TR3_TY, TR3_TZ, TR3_NT};
@@ -220,9 +221,14 @@ __device__ __forceinline__ T gld(const T *p, size_t i) {
 // problems of the same dimension: tile_prob (null: every tile is of
 // problem 0) names the problem of a tile id, whose tiles are numbered from
 // its tile_base.
+// Each activation is shared by SPLIT workgroups: share h transports the
+// parts whose index is h mod SPLIT.  The parts' transports are independent
+// (one frozen foot point per node, no minimum over parts), and a part
+// always has the same owner, so no two workgroups write the same field of
+// a tile; each share queues the neighbours its own changes reach.
 // In 3D the kernel is throughput-bound: asking for 4 waves per SIMD caps it
 // at 128 registers (147 otherwise, 3 waves), 8% faster despite a few spills.
-template <int DIM, int TX, int TY, int TZ, int NT, int CL>
+template <int DIM, int TX, int TY, int TZ, int NT, int CL, int SPLIT>
 __global__ void __launch_bounds__(NT, DIM == 3 ? 4 : 1)
 k_trace(const TraceArgs *__restrict__ args, const int32_t *__restrict__ tile_prob, RoundArgs ra) {
   constexpr int LX = TX + 2 * HALO;
@@ -252,7 +258,10 @@ k_trace(const TraceArgs *__restrict__ args, const int32_t *__restrict__ tile_pro
   const uint32_t nin = ra.count[r % 3];
   const int K = ra.inner_sweeps;
 
-  for (uint32_t li = blockIdx.x; li < nin; li += gridDim.x) {
+  const unsigned long long nvirt = (unsigned long long)nin * SPLIT;
+  for (unsigned long long vi = blockIdx.x; vi < nvirt; vi += gridDim.x) {
+    const uint32_t li = (uint32_t)(vi / SPLIT);
+    const int share = (int)(vi % SPLIT);
     const int gt = ra.list_in[li];
     const TraceArgs a = args[tile_prob ? tile_prob[gt] : 0];
     const int tt = gt - a.tile_base;
@@ -285,10 +294,20 @@ k_trace(const TraceArgs *__restrict__ args, const int32_t *__restrict__ tile_pro
         while (b) {
           const int j = __builtin_ctz(b);
           b &= b - 1u;
-          s_list[c++] = w * 32 + j;
+          const int part = w * 32 + j;
+          if (SPLIT == 1 || part % SPLIT == share) s_list[c++] = part;
         }
       }
       s_nact = c;
+    }
+    if constexpr (SPLIT > 1) {
+      // a share with no part of its own has nothing to transport or queue
+      __syncthreads();
+      if (s_nact == 0) {
+        if (tid == 0 && share == 0) atomicAdd(&ra.work[kSlots + blockIdx.x % kSlots], 1ull);
+        __syncthreads();  // s_act and s_list are rewritten by the next entry
+        continue;
+      }
     }
 
     // Per owned node: fixed foot point of its feedback control (FP64).
@@ -530,7 +549,7 @@ k_trace(const TraceArgs *__restrict__ args, const int32_t *__restrict__ tile_pro
     }
     if (tid == 0) {
       const int slot = blockIdx.x % kSlots;
-      atomicAdd(&ra.work[kSlots + slot], 1ull);
+      if (share == 0) atomicAdd(&ra.work[kSlots + slot], 1ull);
       atomicAdd(&ra.work[slot], (unsigned long long)nact);
     }
     __syncthreads();
@@ -541,10 +560,10 @@ hipError_t launch_trace(int dim, int grid, const TraceArgs *args, const int32_t 
                         int max_words, const RoundArgs &ra, hipStream_t s) {
   if (max_words > kMaxTraceWords) return hipErrorInvalidValue;
   if (dim == 2)
-    hipLaunchKernelGGL((k_trace<2, TR2_TX, TR2_TY, 1, TR2_NT, TR2_CL>), dim3(grid), dim3(TR2_NT),
-                       0, s, args, tile_prob, ra);
+    hipLaunchKernelGGL((k_trace<2, TR2_TX, TR2_TY, 1, TR2_NT, TR2_CL, TR2_SPLIT>), dim3(grid),
+                       dim3(TR2_NT), 0, s, args, tile_prob, ra);
   else
-    hipLaunchKernelGGL((k_trace<3, TR3_TX, TR3_TY, TR3_TZ, TR3_NT, TR3_CL>), dim3(grid),
+    hipLaunchKernelGGL((k_trace<3, TR3_TX, TR3_TY, TR3_TZ, TR3_NT, TR3_CL, TR3_SPLIT>), dim3(grid),
                        dim3(TR3_NT), 0, s, args, tile_prob, ra);
   return hipGetLastError();
 }
