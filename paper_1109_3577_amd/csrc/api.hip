@@ -241,7 +241,8 @@ void trace_rounds(const std::vector<TraceJob *> &jobs, hipStream_t s) {
   ra.flags_out = flags[0].as<uint32_t>();
   ra.round = 2;
   for (const TraceJob *j : jobs) HJB_HIP(launch_trace_seed(dim, j->a, ra, s));
-  const int grid = (int)std::min<long long>((long long)ntiles * trace_split(dim), 4096);
+  const int split = trace_split(dim, jobs.size());
+  const int grid = (int)std::min<long long>((long long)ntiles * split, 4096);
   const TraceArgs *args_dev = args_d.as<TraceArgs>();
   const int32_t *prob_dev = tile_prob.empty() ? nullptr : prob_d.as<int32_t>();
   // Rounds in blocks of 16; the next block is enqueued before the host
@@ -266,7 +267,7 @@ void trace_rounds(const std::vector<TraceJob *> &jobs, hipStream_t s) {
       ra.flags_in = flags[r & 1].as<uint32_t>();
       ra.flags_out = flags[(r + 1) & 1].as<uint32_t>();
       ra.round = r;
-      HJB_HIP(launch_trace(dim, grid, args_dev, prob_dev, max_words, ra, s));
+      HJB_HIP(launch_trace(dim, grid, split, args_dev, prob_dev, max_words, ra, s));
     }
     rounds += rpp;
     HJB_HIP(hipMemcpyAsync(hc + slot, count.as<uint32_t>() + (r % 3), sizeof(uint32_t),

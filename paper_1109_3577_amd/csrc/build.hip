@@ -156,13 +156,13 @@ constexpr double kColourFloor = 1e-9;
 // bound, where small LDS groups (more workgroups per CU) and short
 // activations pay.
 constexpr int TR2_TX = 32, TR2_TY = 16, TR2_NT = 512, TR2_CL = 8, TR2_K = 24, TR2_SPLIT = 2;
-constexpr int TR3_TX = 8, TR3_TY = 8, TR3_TZ = 8, TR3_NT = 256, TR3_CL = 2, TR3_K = 6, TR3_SPLIT = 1;
+constexpr int TR3_TX = 8, TR3_TY = 8, TR3_TZ = 8, TR3_NT = 256, TR3_CL = 2, TR3_K = 6;
 constexpr int kMaxTraceWords = 32;  // up to 1024 parts
 
 int trace_chunk_capacity(int dim) { return dim == 2 ? TR2_CL : TR3_CL; }
 int trace_max_parts() { return kMaxTraceWords * 32; }
 int trace_inner_sweeps(int dim) { return dim == 2 ? TR2_K : TR3_K; }
-int trace_split(int dim) { return dim == 2 ? TR2_SPLIT : TR3_SPLIT; }
+int trace_split(int dim, size_t jobs) { return dim == 2 && jobs == 1 ? TR2_SPLIT : 1; }
 SweepShape trace_shape(int dim) {
   return dim == 2 ? SweepShape{2, TR2_TX, TR2_TY, 1, TR2_NT}
                   : SweepShape{3, TR3_TX, TR3_TY, TR3_TZ, TR3_NT};
@@ -221,8 +221,8 @@ __device__ __forceinline__ T gld(const T *p, size_t i) {
 // problems of the same dimension: tile_prob (null: every tile is of
 // problem 0) names the problem of a tile id, whose tiles are numbered from
 // its tile_base.
-// Each activation is shared by SPLIT workgroups: share h transports the
-// parts whose index is h mod SPLIT.  The parts' transports are independent
+// Each activation is shared by SPLIT workgroups (trace_split): share h
+// transports the parts whose index is h mod SPLIT.  The parts' transports are independent
 // (one frozen foot point per node, no minimum over parts), and a part
 // always has the same owner, so no two workgroups write the same field of
 // a tile; each share queues the neighbours its own changes reach.
@@ -556,15 +556,21 @@ k_trace(const TraceArgs *__restrict__ args, const int32_t *__restrict__ tile_pro
   }
 }
 
-hipError_t launch_trace(int dim, int grid, const TraceArgs *args, const int32_t *tile_prob,
-                        int max_words, const RoundArgs &ra, hipStream_t s) {
+hipError_t launch_trace(int dim, int grid, int split, const TraceArgs *args,
+                        const int32_t *tile_prob, int max_words, const RoundArgs &ra,
+                        hipStream_t s) {
   if (max_words > kMaxTraceWords) return hipErrorInvalidValue;
-  if (dim == 2)
+  if (dim == 2 && split == TR2_SPLIT)
     hipLaunchKernelGGL((k_trace<2, TR2_TX, TR2_TY, 1, TR2_NT, TR2_CL, TR2_SPLIT>), dim3(grid),
                        dim3(TR2_NT), 0, s, args, tile_prob, ra);
-  else
-    hipLaunchKernelGGL((k_trace<3, TR3_TX, TR3_TY, TR3_TZ, TR3_NT, TR3_CL, TR3_SPLIT>), dim3(grid),
+  else if (dim == 2 && split == 1)
+    hipLaunchKernelGGL((k_trace<2, TR2_TX, TR2_TY, 1, TR2_NT, TR2_CL, 1>), dim3(grid),
+                       dim3(TR2_NT), 0, s, args, tile_prob, ra);
+  else if (dim == 3 && split == 1)
+    hipLaunchKernelGGL((k_trace<3, TR3_TX, TR3_TY, TR3_TZ, TR3_NT, TR3_CL, 1>), dim3(grid),
                        dim3(TR3_NT), 0, s, args, tile_prob, ra);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

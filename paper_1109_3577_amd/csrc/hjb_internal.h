@@ -228,9 +228,11 @@ SweepShape trace_shape(int dim);
 int trace_inner_sweeps(int dim);
 // One round of colour transport over the tile ids in ra.list_in: `args`
 // (device) holds the problems, `tile_prob` (device, null for one problem)
-// the problem of every tile id, `max_words` the largest words of them.
-hipError_t launch_trace(int dim, int grid, const TraceArgs *args, const int32_t *tile_prob,
-                        int max_words, const RoundArgs &ra, hipStream_t s);
+// the problem of every tile id, `max_words` the largest words of them;
+// `split` workgroups share each activation (trace_split).
+hipError_t launch_trace(int dim, int grid, int split, const TraceArgs *args,
+                        const int32_t *tile_prob, int max_words, const RoundArgs &ra,
+                        hipStream_t s);
 // Queues the problem's tiles next to target nodes (ids from a.tile_base).
 hipError_t launch_trace_seed(int dim, const TraceArgs &a, const RoundArgs &ra, hipStream_t s);
 hipError_t launch_labels(int dim, const TraceArgs &a, int16_t *labels, uint32_t *unreached,

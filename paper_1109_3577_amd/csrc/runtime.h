@@ -315,9 +315,12 @@ std::unique_ptr<TraceJob> trace_begin(const ProblemDev &F, const CoarseHandle &C
                                       double exclude_at = 0.0);
 // Device bytes a job holds until trace_end (colour fields included).
 size_t trace_job_bytes(const hjb_problem &F);
-// Workgroups that share one tile activation of the colour transport (each
-// takes the parts of one residue of the part index).
-int trace_split(int dim);
+// Workgroups that share one tile activation of the colour transport of
+// `jobs` problems (each takes the parts of one residue of the part index):
+// two for one 2D problem, whose rounds are short and wait for their
+// slowest activations; one for 3D and for shared rounds of several
+// problems, which are throughput-bound.
+int trace_split(int dim, size_t jobs);
 // Colour transport of the jobs (one dimension) in shared rounds.
 void trace_rounds(const std::vector<TraceJob *> &jobs, hipStream_t s);
 // Labels, codes, statistics; releases the colour fields.
