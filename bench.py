@@ -10,11 +10,13 @@ grid on [-1,1]^2, c = 1 + 0.5 sin(2 pi k1 x) sin(2 pi k2 y), 32 controls,
 target ball r = 0.1 at a seeded centre split into 16 equal-angle parts,
 stopping tolerance 1e-5 (seed 0).
 
-Prints one JSON line (rank 0).  `value` = node-control updates executed per
-second over the timed steps (coarse-solve updates + feedback evaluations +
-patch-sweep updates); beside it the solve time and the plain global GPU
-solve of the same problem, the roofline of the dominant kernel (the FP32
-tiled sweep) and the CPU oracle on a bounded sample.
+Prints one JSON line (rank 0).  `value` = node-control updates of the value
+iteration executed per second over the timed steps (the patch sweeps and the
+Step 1 coarse solve; the Step 2 feedback evaluations are listed apart);
+beside it the solve time per step, the plain global GPU solve of the same
+problem, the roofline of the dominant kernel (the FP32 tiled sweep), the
+other seeds, the 3D workload (257^3), a serving run with p50/p99 latency and
+the CPU oracle on a bounded sample.
 """
 import argparse
 import json
@@ -88,6 +90,14 @@ def parse():
                          "solve3d: the 257^3 patchy problem (98 controls, 64 parts); "
                          "batch: many uneven problems in shared rounds; serve: Poisson "
                          "request stream through the continuous-batching server")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 257^3 block of the default line")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving block of the default line")
+    ap.add_argument("--no-seeds", action="store_true",
+                    help="skip the other seeds of the 2D workload")
+    ap.add_argument("--serve-count", type=int, default=300,
+                    help="requests of the serving block of the default line")
     ap.add_argument("--count", type=int, default=0, help="problems (batch) / requests (serve)")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / capacity")
     return ap.parse_args()
@@ -247,6 +257,22 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t_run = time.perf_counter() - t
     nodes = sum(p.N for p in fines)
+    # the same batch in the other launch forms: rounds replayed as a
+    # hipGraph, and one persistent launch per dimension draining a device
+    # queue of items
+    forms = {}
+    fs = torch.cuda.Stream()  # graph capture needs a stream other than the null stream
+    for name, kw in (("graph", {"use_graph": True}), ("async", {"schedule": hjb.HJB_SCHED_ASYNC})):
+        o = autotune.opts_from(choice, **kw)
+        bf = hjb.hjb_batch_create(fines, coarses, hjb.HJB_F32, args.tol, 0, o, stream=fs)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sf = bf.run()
+        torch.cuda.synchronize()
+        forms[name] = {"sweep_s": time.perf_counter() - t, "updates": sf["updates"],
+                       "rounds": sf["rounds"]}
+        bf.free()
+        print(f"[bench] batch {name}: {forms[name]['sweep_s']:.3f} s", file=sys.stderr, flush=True)
     # a few problems solved alone: at tol > 0 the stopping point depends on
     # the schedule, so the batch may differ from them within the tolerance
     sampled = []
@@ -275,6 +301,8 @@ def bench_batch(args):
         "autotuned": choice, "prepare_s": t_prep, "prepare_first_call_s": t_prep_cold,
         "sweep_s": t_run,
         "batch_total_s": t_prep + t_run, "sampled_max_diff_vs_alone": max(sampled),
+        "sweep_forms": {"rounds": {"sweep_s": t_run, "updates": st["updates"],
+                                   "rounds": st["rounds"]}, **forms},
         "updates": st["updates"],
         "updates_per_s": st["updates"] / t_run, "items": st["items"], "rounds": st["rounds"],
         "sequential_plain_global_s": t_seq, "sequential_plain_updates": gupd,
@@ -362,72 +390,154 @@ def main():
         label = (f"3D variable-speed patchy solve 257^3 / 33^3, 98 controls, 64 parts, "
                  f"seed {args.seed}, tol {args.tol:g}")
         cfg = {"n": 257, "n_coarse": 33, "controls": 98, "parts": 64}
-    fine = hjb.Problem(fine_src, device=True)
-    coarse = hjb.Problem(coarse_src, device=True)
-    N = fine.N
-    v = torch.empty(N, dtype=torch.float32, device="cuda")
-    opts = hjb.make_opts(time_kernels=not args.graph, use_graph=bool(args.graph))
     print(f"[bench] workload {label}", file=sys.stderr, flush=True)
-
-    def step():
-        ch = hjb.hjb_coarse_solve(coarse, 0.0, 0, stream)
-        ph = hjb.hjb_build_patches(fine, ch, stream)
-        ch.free()
-        st = hjb.hjb_solve_patches(fine, ph, hjb.HJB_F32, v, args.tol, 0, opts, stream)
-        ph_stats = ph.stats
-        ph.free()
-        return st, ph_stats
-
-    with torch.cuda.stream(stream):
-        for i in range(args.warmup):
-            step()
-            print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sts = []
-        for i in range(args.steps):
-            sts.append(step())
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-    elapsed = t1 - t0
-    print(f"[bench] {args.steps} timed steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
-
-    solve_upd = sum(s[0]["updates"] for s in sts)
-    feedback_upd = sum(s[1]["updates"] for s in sts)
-    kernel_ms = sum(s[0]["ms_kernel"] for s in sts)
-    launches = sum(s[0]["kernel_launches"] for s in sts)
-    solve_ms = np.mean([s[0]["ms_wall"] for s in sts])
-    build_ms = np.mean([s[1]["ms_wall"] for s in sts])
-    trace_ms = np.mean([s[1]["ms_trace"] for s in sts])
-    # coarse solve work: re-run once with stats through the Python wrapper
-    with torch.cuda.stream(stream):
-        vc = torch.empty(coarse.N, dtype=torch.float64, device="cuda")
-        cst = hjb.hjb_solve_global(coarse, hjb.HJB_F64, vc, 0.0, 0, None, stream)
-    coarse_upd = cst["updates"] * args.steps
-    total_upd = solve_upd + feedback_upd + coarse_upd
-    ms_per_step = elapsed / args.steps * 1e3
-
+    r = run_patchy(hjb, fine_src, coarse_src, args.steps, args.warmup, args.tol, stream,
+                   graph=bool(args.graph))
     out = {
         "metric": "node-control updates/s and solve time, patchy vs global at ||dv||inf<=1e-5; p99",
-        "value": total_upd / elapsed,
+        "value": r["value"],
         "unit": "node-control updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (values), f64 (coarse solve, feedback, colours, residual)",
         "data": "synthetic (seeded generator)",
         "config": {"workload": label, **cfg, "tol": args.tol},
-        "step_ms": {"solve_patches": solve_ms, "build_patches": build_ms, "trace": trace_ms,
-                    "coarse_and_other": ms_per_step - solve_ms - build_ms},
-        "updates_per_step": {"patch_sweeps": solve_upd // args.steps,
-                             "feedback": feedback_upd // args.steps,
-                             "coarse": coarse_upd // args.steps},
+        "value_counts": "node-control updates of the value iteration: patch sweeps (FP32) and "
+                        "the Step 1 coarse solve (FP64); the Step 2 feedback evaluations are "
+                        "listed in updates_per_step and not counted",
+        "step_ms": r["step_ms"],
+        "updates_per_step": r["updates_per_step"],
+        "build": r["build"],
     }
+    if "roofline" in r:
+        out["roofline"] = r["roofline"]
+    fine, coarse, v = r["fine"], r["coarse"], r["v"]
+    N = fine.N
 
+    # Plain global GPU solve of the same fine problem (full-grid Jacobi,
+    # FP32, same tolerance) and the tiled global schedule.
+    vt = None
+    if not args.no_global:
+        g = run_global(hjb, fine, args.tol, stream)
+        vt = g.pop("v_tiled")
+        vg = g.pop("v_jacobi")
+        out["global"] = {**g, "speedup_patchy_step_vs_jacobi": g["jacobi_ms"] / r["ms_per_step"],
+                         "speedup_patch_solve_vs_jacobi": g["jacobi_ms"] / r["step_ms"]["solve_patches"],
+                         "speedup_patchy_step_vs_tiled": g["tiled_ms"] / r["ms_per_step"],
+                         **patchy_errors(v, vg)}
+        print(f"[bench] global Jacobi {g['jacobi_ms']:.1f} ms, tiled {g['tiled_ms']:.1f} ms; "
+              f"patchy E_inf {out['global']['patchy_error_Einf']:.3g}, cut-off nodes "
+              f"{out['global']['cutoff_nodes']}", file=sys.stderr, flush=True)
+
+    # The paper's add-ons beside the basic patch solve, on the same patches:
+    # the Dirichlet patch data U^(0) (eq. dbc), AO3 (control cones of
+    # half-angle pi/r around the Step 2 feedback) and both; kernel time of
+    # each and its error against the global solution (when measured).
+    if not args.no_addons:
+        out["addons"] = run_addons(hjb, fine, coarse, dim, args, stream, vt)
+
+    # The other seeds of the 2D workload (same shapes, other speed fields
+    # and target centres).
+    if dim == 2 and not args.no_seeds and args.n == 1025:
+        seeds = {}
+        for sd in (1, 2):
+            f2, c2 = problems.config2(sd, args.n, args.ncoarse)
+            rs = run_patchy(hjb, f2, c2, 3, 1, args.tol, stream)
+            seeds[str(sd)] = {"ms_per_step": rs["ms_per_step"], "value": rs["value"],
+                              "step_ms": rs["step_ms"],
+                              "roofline_frac": rs.get("roofline", {}).get("frac")}
+            print(f"[bench] seed {sd}: {rs['ms_per_step']:.2f} ms per step", file=sys.stderr,
+                  flush=True)
+        out["seeds"] = seeds
+
+    # The 3D workload: 257^3 / 33^3, 98 controls, 64 parts.
+    if dim == 2 and not args.no_c3:
+        f3, c3 = problems.config3(args.seed)
+        r3 = run_patchy(hjb, f3, c3, 2, 1, args.tol, stream)
+        g3 = run_global(hjb, r3["fine"], args.tol, stream)
+        e3 = patchy_errors(r3["v"], g3.pop("v_jacobi"))
+        g3.pop("v_tiled")
+        out["c3"] = {"workload": "3D variable-speed patchy solve 257^3 / 33^3, 98 controls, "
+                                 f"64 parts, seed {args.seed}, tol {args.tol:g}",
+                     "value": r3["value"], "ms_per_step": r3["ms_per_step"],
+                     "step_ms": r3["step_ms"], "updates_per_step": r3["updates_per_step"],
+                     "roofline": r3.get("roofline"), "global": g3,
+                     "speedup_patchy_step_vs_jacobi": g3["jacobi_ms"] / r3["ms_per_step"],
+                     "speedup_patch_solve_vs_jacobi":
+                         g3["jacobi_ms"] / r3["step_ms"]["solve_patches"],
+                     "speedup_patchy_step_vs_tiled": g3["tiled_ms"] / r3["ms_per_step"], **e3}
+        print(f"[bench] 3D: {r3['ms_per_step']:.1f} ms per step, Jacobi {g3['jacobi_ms']:.1f} ms, "
+              f"tiled {g3['tiled_ms']:.1f} ms", file=sys.stderr, flush=True)
+        del r3, f3, c3
+
+    # Serving: a Poisson stream at a fixed rate, 0.7 x the closed-loop
+    # capacity measured on the same requests in the same run.
+    if dim == 2 and not args.no_serve:
+        out["serve"] = run_serve(args.serve_count, args.tol, args.load)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(hjb, args, stream)
+    print(json.dumps(out))
+
+
+def run_patchy(hjb, fine_src, coarse_src, steps, warmup, tol, stream, graph=False):
+    """Timed patchy steps (coarse solve, build, patch solve) of one problem;
+    node-control updates counted as in the header of this file."""
+    import numpy as np
+    import torch
+    fine = hjb.Problem(fine_src, device=True)
+    coarse = hjb.Problem(coarse_src, device=True)
+    dim = fine_src.dim
+    v = torch.empty(fine.N, dtype=torch.float32, device="cuda")
+    opts = hjb.make_opts(time_kernels=not graph, use_graph=graph)
+
+    def step():
+        ch = hjb.hjb_coarse_solve(coarse, 0.0, 0, stream)
+        ph = hjb.hjb_build_patches(fine, ch, stream)
+        ch.free()
+        st = hjb.hjb_solve_patches(fine, ph, hjb.HJB_F32, v, tol, 0, opts, stream)
+        ph_stats = ph.stats
+        ph.free()
+        return st, ph_stats
+
+    with torch.cuda.stream(stream):
+        for i in range(warmup):
+            step()
+            print(f"[bench] warmup {i + 1}/{warmup} done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    elapsed = t1 - t0
+    print(f"[bench] {steps} timed steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    solve_upd = sum(s[0]["updates"] for s in sts)
+    feedback_upd = sum(s[1]["updates"] for s in sts)
+    kernel_ms = sum(s[0]["ms_kernel"] for s in sts)
+    launches = sum(s[0]["kernel_launches"] for s in sts)
+    solve_ms = float(np.mean([s[0]["ms_wall"] for s in sts]))
+    build_ms = float(np.mean([s[1]["ms_wall"] for s in sts]))
+    trace_ms = float(np.mean([s[1]["ms_trace"] for s in sts]))
+    # coarse solve work: the same FP64 solve once more, with statistics
+    with torch.cuda.stream(stream):
+        vc = torch.empty(coarse.N, dtype=torch.float64, device="cuda")
+        cst = hjb.hjb_solve_global(coarse, hjb.HJB_F64, vc, 0.0, 0, None, stream)
+    coarse_upd = cst["updates"] * steps
+    ms_per_step = elapsed / steps * 1e3
+    out = {"fine": fine, "coarse": coarse, "v": v,
+           "value": (solve_upd + coarse_upd) / elapsed, "ms_per_step": ms_per_step,
+           "step_ms": {"solve_patches": solve_ms, "build_patches": build_ms, "trace": trace_ms,
+                       "coarse_and_other": ms_per_step - solve_ms - build_ms},
+           "updates_per_step": {"patch_sweeps": solve_upd // steps,
+                                "coarse": coarse_upd // steps,
+                                "feedback_evaluations": feedback_upd // steps},
+           "build": {"unreached": sts[0][1]["unreached"], "detached": sts[0][1]["detached"],
+                     "trace_rounds": sts[0][1]["rounds"]}}
     # Dominant kernel: the FP32 tiled sweep, HIP events around every block of
     # launches on the solve's stream.
     if launches:
@@ -449,88 +559,172 @@ def main():
             "updates_per_launch": solve_upd / launches,
             "inner_sweeps": s0["inner_sweeps"],
         }
+    return out
 
-    # Plain global GPU solve of the same fine problem (full-grid Jacobi,
-    # FP32, same tolerance) and the tiled global schedule.
-    if not args.no_global:
-        with torch.cuda.stream(stream):
-            vg = torch.empty(N, dtype=torch.float32, device="cuda")
-            gj = hjb.hjb_solve_global(fine, hjb.HJB_F32, vg, args.tol, 0,
-                                      hjb.make_opts(schedule=hjb.HJB_SCHED_JACOBI, rounds_per_poll=8),
-                                      stream)
-            vt = torch.empty(N, dtype=torch.float32, device="cuda")
-            gt = hjb.hjb_solve_global(fine, hjb.HJB_F32, vt, args.tol, 0, None, stream)
+
+def run_global(hjb, fine, tol, stream):
+    """The plain global GPU solve (full-grid Jacobi, FP32) and the tiled
+    global schedule of the same problem."""
+    import torch
+    N = fine.N
+    with torch.cuda.stream(stream):
+        vg = torch.empty(N, dtype=torch.float32, device="cuda")
+        gj = hjb.hjb_solve_global(fine, hjb.HJB_F32, vg, tol, 0,
+                                  hjb.make_opts(schedule=hjb.HJB_SCHED_JACOBI, rounds_per_poll=8),
+                                  stream)
+        vt = torch.empty(N, dtype=torch.float32, device="cuda")
+        gt = hjb.hjb_solve_global(fine, hjb.HJB_F32, vt, tol, 0, None, stream)
+        torch.cuda.synchronize()
+    return {"jacobi_ms": gj["ms_wall"], "jacobi_sweeps": gj["sweeps"],
+            "jacobi_updates": gj["updates"], "tiled_ms": gt["ms_wall"],
+            "tiled_updates": gt["updates"], "v_jacobi": vg, "v_tiled": vt}
+
+
+def patchy_errors(v, vg):
+    """Patchy error against the global solve in the Kruzkov variable, and
+    the nodes the patchy solve leaves at v = 1 (T = +inf) where the global
+    solve reaches the target."""
+    E = (v.double() - vg.double()).abs()
+    cut = int(((v == 1.0) & (vg < 1.0)).sum().item())
+    return {"patchy_error_E1": float(E.mean()), "patchy_error_Einf": float(E.max()),
+            "cutoff_nodes": cut}
+
+
+def run_addons(hjb, fine, coarse, dim, args, stream, vt):
+    import torch
+    N = fine.N
+    # AO2 window (time steps per round) and in-tile sweeps that suit it
+    ao2 = {"order_window": 6.0} if dim == 2 else {"order_window": 2.5, "inner_sweeps": 4}
+    dbc = {"patch_bc": hjb.HJB_BC_DIRICHLET}
+    ao3 = {"control_cone": args.ao3_r}
+    variants = {"basic": {}, "dbc": dbc, "ao2": ao2, "ao3": ao3,
+                "dbc_ao2_ao3": {**dbc, **ao2, **ao3}}
+    if args.tol >= 1e-7:  # AO1 iterates v <- F(v) and needs a tolerance
+        variants["ao1"] = {"start_u0": 1}
+    res = {}
+    with torch.cuda.stream(stream):
+        ch = hjb.hjb_coarse_solve(coarse, 0.0, 0, stream)
+        ph = hjb.hjb_build_patches(fine, ch, stream)
+        va = torch.empty(N, dtype=torch.float32, device="cuda")
+        for name, kw in variants.items():
+            o = hjb.make_opts(time_kernels=True, **kw)
+            runs = [hjb.hjb_solve_patches(fine, ph, hjb.HJB_F32, va, args.tol, 0, o, stream)
+                    for _ in range(3)]
             torch.cuda.synchronize()
-            E = (v.double() - vg.double()).abs()
-        out["global"] = {"jacobi_ms": gj["ms_wall"], "jacobi_sweeps": gj["sweeps"],
-                         "jacobi_updates": gj["updates"], "tiled_ms": gt["ms_wall"],
-                         "tiled_updates": gt["updates"],
-                         "speedup_patchy_step_vs_jacobi": gj["ms_wall"] / ms_per_step,
-                         "speedup_patch_solve_vs_jacobi": gj["ms_wall"] / solve_ms,
-                         "patchy_error_E1": float(E.mean()), "patchy_error_Einf": float(E.max())}
-        print(f"[bench] global Jacobi {gj['ms_wall']:.1f} ms, tiled {gt['ms_wall']:.1f} ms",
-              file=sys.stderr, flush=True)
+            r = {"opts": {k: float(v) for k, v in kw.items()},
+                 "kernel_ms": min(x["ms_kernel"] for x in runs),
+                 "wall_ms": min(x["ms_wall"] for x in runs),
+                 "updates": runs[0]["updates"], "node_updates": runs[0]["node_updates"],
+                 "rounds": runs[0]["rounds"],
+                 "controls_per_node_update": runs[0]["updates"] / max(1, runs[0]["node_updates"]),
+                 "inner_sweeps": runs[0]["inner_sweeps"]}
+            if vt is not None:
+                e = patchy_errors(va, vt)
+                r["E1_vs_global"] = e["patchy_error_E1"]
+                r["Einf_vs_global"] = e["patchy_error_Einf"]
+                r["cutoff_nodes"] = e["cutoff_nodes"]
+            res[name] = r
+        ph.free()
+        ch.free()
+    for name in [k for k in res if k != "basic"]:
+        res[name]["speedup_kernel_vs_basic"] = res["basic"]["kernel_ms"] / res[name]["kernel_ms"]
+    print(f"[bench] add-ons (kernel ms): " + ", ".join(
+        f"{k} {v['kernel_ms']:.2f}" for k, v in res.items()), file=sys.stderr, flush=True)
+    return {"r": args.ao3_r, **res}
 
-    # The paper's add-ons beside the basic patch solve, on the same patches:
-    # the Dirichlet patch data U^(0) (eq. dbc), AO3 (control cones of
-    # half-angle pi/r around the Step 2 feedback) and both; kernel time of
-    # each and its error against the global solution (when measured).
-    if not args.no_addons:
-        # AO2 window (time steps per round) and in-tile sweeps that suit it
-        ao2 = {"order_window": 6.0} if dim == 2 else {"order_window": 2.5, "inner_sweeps": 4}
-        dbc = {"patch_bc": hjb.HJB_BC_DIRICHLET}
-        ao3 = {"control_cone": args.ao3_r}
-        variants = {"basic": {}, "dbc": dbc, "ao2": ao2, "ao3": ao3,
-                    "dbc_ao2_ao3": {**dbc, **ao2, **ao3}}
-        if args.tol >= 1e-7:  # AO1 iterates v <- F(v) and needs a tolerance
-            variants["ao1"] = {"start_u0": 1}
-        res = {}
-        with torch.cuda.stream(stream):
-            ch = hjb.hjb_coarse_solve(coarse, 0.0, 0, stream)
-            ph = hjb.hjb_build_patches(fine, ch, stream)
-            va = torch.empty(N, dtype=torch.float32, device="cuda")
-            for name, kw in variants.items():
-                o = hjb.make_opts(time_kernels=True, **kw)
-                runs = [hjb.hjb_solve_patches(fine, ph, hjb.HJB_F32, va, args.tol, 0, o, stream)
-                        for _ in range(3)]
-                torch.cuda.synchronize()
-                r = {"opts": {k: float(v) for k, v in kw.items()},
-                     "kernel_ms": min(x["ms_kernel"] for x in runs),
-                     "wall_ms": min(x["ms_wall"] for x in runs),
-                     "updates": runs[0]["updates"], "node_updates": runs[0]["node_updates"],
-                     "rounds": runs[0]["rounds"],
-                     "controls_per_node_update": runs[0]["updates"] / max(1, runs[0]["node_updates"]),
-                     "inner_sweeps": runs[0]["inner_sweeps"]}
-                if not args.no_global:
-                    E = (va.double() - vt.double()).abs()
-                    r["E1_vs_global"] = float(E.mean())
-                    r["Einf_vs_global"] = float(E.max())
-                res[name] = r
-            ph.free()
-            ch.free()
-        for name in [k for k in res if k != "basic"]:
-            res[name]["speedup_kernel_vs_basic"] = res["basic"]["kernel_ms"] / res[name]["kernel_ms"]
-        out["addons"] = {"r": args.ao3_r, **res}
-        print(f"[bench] add-ons (kernel ms): " + ", ".join(
-            f"{k} {v['kernel_ms']:.2f}" for k, v in res.items()), file=sys.stderr, flush=True)
 
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        O.build(force=False)
-        threads = O.num_threads()
-        t = time.perf_counter()
-        # a bounded sample: 100 sweeps of the 2D grid, 5 of the 3D one
-        sweeps = args.cpu_sweeps if dim == 2 else max(1, args.cpu_sweeps // 20)
-        _, st = O.solve_global(fine_src, 0.0, max_sweeps=sweeps, allow_noconv=True)
-        dt = time.perf_counter() - t
-        out["cpu_baseline"] = {
-            "value": st["updates"] / dt, "unit": "node-control updates/s", "cores": threads,
+def run_serve(count, tol, load):
+    """The serving block of the default line: `count` requests of the
+    serving mix, the closed-loop capacity, then one Poisson run at
+    load x capacity."""
+    import numpy as np
+    import torch
+
+    from paper_1109_3577_amd import problems, serve
+    t = time.perf_counter()
+    reqs = []
+    for r in problems.serving_stream(count, 1.0, seed=0):
+        reqs.append(r)
+        if len(reqs) % 50 == 0:
+            print(f"[bench] serve: generated {len(reqs)}/{count} requests", file=sys.stderr,
+                  flush=True)
+    gen_s = time.perf_counter() - t
+    budget = int(0.8 * torch.cuda.mem_get_info()[0])
+    cap = serve.run(reqs, budget, tol=tol, closed_loop=True)
+    rate = load * cap["requests_per_s"]
+    rng = np.random.default_rng(1)
+    tt = 0.0
+    for r in reqs:
+        tt += float(rng.exponential(1.0 / rate))
+        r.arrival_s = tt
+    res = serve.run(reqs, budget, tol=tol)
+    print(f"[bench] serve: capacity {cap['requests_per_s']:.1f} requests/s; load {load}: "
+          f"p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    return {"requests": count, "requests_3d": sum(1 for r in reqs if r.fine.dim == 3),
+            "generate_s": gen_s, "capacity_requests_per_s": cap["requests_per_s"],
+            "load": load, "arrival_rate_per_s": rate, "p50_ms": res["p50_ms"],
+            "p99_ms": res["p99_ms"], "mean_ms": res["mean_ms"],
+            "requests_per_s": res["requests_per_s"], "updates_per_s": res["updates_per_s"],
+            "wall_s": res["wall_s"]}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(hjb, args, stream):
+    """The CPU oracle on a bounded sample of the same workload: the whole
+    patchy pipeline (Step 1 coarse solve, Steps 2-3.1 build, Steps 3.2-4
+    patch solves, same tolerance) of the 2D variable-speed generator at
+    257^2 / 17^2, timed per step on all host cores and on one core; the GPU
+    pipeline on the same sample beside it."""
+    import torch
+
+    from oracle import oracle as O
+    from paper_1109_3577_amd import problems
+    O.build(force=False)
+    n = 257
+    f, c = problems.config2(args.seed, n, problems.coarse_size_2d(n))
+
+    def oracle_pipeline():
+        t0 = time.perf_counter()
+        vc, cst = O.solve_global(c)
+        t1 = time.perf_counter()
+        u0 = O.prolong(c, vc, f)
+        fb = O.feedback(f, u0)
+        lab = O.labels(f, fb)
+        t2 = time.perf_counter()
+        _, st = O.solve_patches(f, lab, args.tol)
+        t3 = time.perf_counter()
+        upd = cst["updates"] + st["updates"]
+        return {"coarse_ms": (t1 - t0) * 1e3, "build_ms": (t2 - t1) * 1e3,
+                "solve_ms": (t3 - t2) * 1e3, "total_ms": (t3 - t0) * 1e3,
+                "updates": upd, "updates_per_s": upd / (t3 - t0)}
+
+    threads = O.num_threads()
+    allc = oracle_pipeline()
+    O.set_threads(1)
+    one = oracle_pipeline()
+    O.set_threads(threads)
+    g = run_patchy(hjb, f, c, 5, 2, args.tol, stream)
+    return {"value": allc["updates_per_s"], "unit": "node-control updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{sweeps} Jacobi sweeps of the FP64 oracle on the full fine grid "
-                      f"({cfg['n']}^{dim}, {cfg['controls']} controls), {st['updates']:.3g} "
-                      f"updates, {dt:.1f} s",
-        }
-    print(json.dumps(out))
+            "sample": f"the oracle's patchy pipeline (coarse solve, build, patch solves, tol "
+                      f"{args.tol:g}) on the 2D variable-speed generator at {n}^2 / 17^2, seed "
+                      f"{args.seed}: {allc['updates']:.3g} updates in "
+                      f"{allc['total_ms'] / 1e3:.1f} s on {threads} threads",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)),
+            "per_step_all_cores_ms": allc, "per_step_1_core_ms": one,
+            "gpu_same_sample": {"ms_per_step": g["ms_per_step"], "step_ms": g["step_ms"],
+                                "value": g["value"]}}
 
 
 if __name__ == "__main__":

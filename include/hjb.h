@@ -166,6 +166,12 @@ typedef struct {
   int32_t inner_sweeps;
   int32_t excluded;        /* hjb_build_patches_ex: nodes excluded as
                               unreachable after Step 1 */
+  int32_t detached;        /* hjb_build_patches: nodes of pieces of a patch
+                              that the projection cut off from their own
+                              target part (no node of the piece, 8 / 26
+                              neighbours, is a target node of its part);
+                              they took their neighbours' label
+                              (Remark 3.1) */
 } hjb_stats;
 
 /* target_part value of a node inside an obstacle (Section 4.5): a state
@@ -328,7 +334,9 @@ int hjb_solve_global(const hjb_problem *fine, int32_t precision, double tol, int
 /* ---------------------------------------------------------------- batching
  * Many independent patchy problems (2D and 3D, uneven sizes, control and
  * patch counts) solved together: every (problem, patch, tile) is one work
- * item of one persistent sweep launch per round, with a per-item device
+ * item of one sweep launch per round (replayed as a hipGraph with
+ * solve.use_graph), or of one persistent launch that drains a device queue
+ * of items (solve.schedule = HJB_SCHED_ASYNC), with a per-item device
  * convergence flag; a problem is finished when none of its items is active.
  * Independence of the patches (Section 3, parallelisation "Method 2") is
  * what makes the packing exact: each result is bitwise the one of a solve
@@ -337,7 +345,11 @@ typedef struct {
   int32_t precision;       /* HJB_F32 (default) or HJB_F64 */
   double tol;              /* as hjb_solve_patches */
   int32_t max_sweeps;      /* per problem, in rounds x inner sweeps */
-  hjb_solve_opts solve;    /* tile / inner sweeps / polling / graph */
+  hjb_solve_opts solve;    /* tile / inner sweeps / polling / graph /
+                              schedule (HJB_SCHED_TILED rounds or
+                              HJB_SCHED_ASYNC, the latter without
+                              order_window, start_u0, use_graph and with
+                              max_sweeps 0) */
   uint64_t prepare_bytes;  /* device bytes that the shared colour transport
                               of hjb_batch_create may hold at once (colour
                               fields and the rest of Steps 2-3.1); problems
@@ -371,8 +383,8 @@ typedef struct {
 /* hbm_budget: bytes of device memory requests may hold at once.  The
  * server starts a pool of host threads (a HIP stream each, on the calling
  * thread's current device) that prepare admitted requests; they stop in
- * hjb_server_free.  Batches and servers run in rounds (HJB_EINVAL for
- * HJB_SCHED_ASYNC). */
+ * hjb_server_free.  The server runs in rounds, since requests join between
+ * them (HJB_EINVAL for HJB_SCHED_ASYNC). */
 int hjb_server_create(size_t hbm_budget, const hjb_server_opts *opts, hjb_stream_t stream,
                       hjb_server_t **out);
 /* Queues a request (arrays are copied before returning); *ticket

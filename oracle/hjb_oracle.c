@@ -43,20 +43,22 @@
  *     before the affine Kruzkov map, which could round distinct I to equal
  *     values); target nodes carry no feedback (255);
  *   - colours: target nodes are fixed (1 on their own part, 0 elsewhere),
- *     non-target nodes start at 0 and rise as phi <- max(phi, beta I[phi])
+ *     non-target nodes start at 0 and rise as phi <- max(phi, Q(beta I[phi]))
  *     until nothing changes.  The factor beta = exp(-h) is the scheme's own
  *     per-step factor in the Kruzkov variable: a colour is the share of
  *     exp(-T) that part j carries along the frozen feedback, and the colour
- *     map is a beta-contraction (without it, near-closed loops of the
- *     frozen feedback -- rotating drifts produce them -- make the iteration
- *     contract arbitrarily slowly).  A colour below 1e-9 counts as 0 (the
- *     paper allows a very rough stopping rule here since only the
- *     projection of the colours is used; the floor keeps the supports
- *     compact).  Both maps are monotone.  The label is the part with the
- *     largest colour, lowest part index on ties; nodes whose colours are all
- *     0 then take the smallest label among their nearest labelled nodes
- *     (Remark 3.1: uncovered nodes get the colour of their neighbours), so
- *     -1 remains only where no node is labelled at all;
+ *     map is a beta-contraction (without it, near-closed loops of the frozen
+ *     feedback -- rotating drifts produce them -- make the iteration
+ *     contract arbitrarily slowly).  Q rounds down to a multiple of 2^-24:
+ *     the paper allows a very rough stopping rule here since only the
+ *     projection of the colours is used, and on this lattice increments
+ *     below 2^-24 are not pursued while the map stays monotone (the stop
+ *     does not depend on the order of the updates).  The label is the part
+ *     with the largest colour, lowest part index on ties; pieces of a patch
+ *     that hold no node of its target part (axis neighbours) are uncoloured;
+ *     uncoloured nodes then take the smallest label among their nearest
+ *     labelled nodes (Remark 3.1: uncovered nodes get the colour of their
+ *     neighbours), so -1 remains only where no node is labelled at all;
  *   - merge: target 0, label -1 gives 1, else the value of patch label.
  */
 #include <math.h>
@@ -67,9 +69,13 @@
 #include <omp.h>
 #endif
 
-/* Colours below this floor are set to zero (reading of the rough stopping
- * rule of Step 3.1: colours matter only through their final projection). */
+/* Colours below this floor are set to zero in the unrounded discounted
+ * transport (ORC_TRACE_DISCOUNTED). */
 #define ORC_COLOUR_FLOOR 1e-9
+/* 2^24: the colour lattice of the labels' transport (ORC_TRACE_LATTICE) has
+ * spacing 2^-24, the reading of the rough stopping rule of Step 3.1
+ * (colours matter only through their final projection). */
+#define ORC_COLOUR_LATTICE 16777216.0
 
 /* pi to double precision (C99 has no M_PI) */
 #define ORC_PI 3.14159265358979323846
@@ -449,13 +455,36 @@ int orc_feedback_at(const orc_problem *F, const double *u0, const long long *idx
   return ORC_OK;
 }
 
+/* Colour transport modes of orc_trace_part_mode:
+ *   ORC_TRACE_LATTICE     the reading used for the labels: the foot point
+ *                         of the feedback control under the scheme's own
+ *                         step h, the factor beta, and every new colour
+ *                         rounded down to a multiple of 2^-24 (the "very
+ *                         rough" stop of Step 3.1 made exact: increments
+ *                         below the lattice spacing are not pursued, and
+ *                         the rounded map is still monotone, so every fair
+ *                         order of updates stops at the same colours);
+ *   ORC_TRACE_DISCOUNTED  the same foot point and factor, colours below the
+ *                         floor 1e-9 set to 0, otherwise unrounded;
+ *   ORC_TRACE_PLAIN       the same foot point with no factor and no floor;
+ *   ORC_TRACE_PAPER       eq. HJBridotta_discreta as printed: no factor, no
+ *                         floor, and the step h_i with |h_i f(x_i, a*)| = k,
+ *                         i.e. the foot point one cell away along f (grids
+ *                         with equal steps on every axis only). */
+#define ORC_TRACE_DISCOUNTED 0
+#define ORC_TRACE_PLAIN 1
+#define ORC_TRACE_PAPER 2
+#define ORC_TRACE_LATTICE 3
+
 /* Public: Step 3.1 for one part j -- colour transport with the frozen
- * feedback, eq. HJBridotta_discreta with the per-step factor beta,
- * iterated (Jacobi) from below to the exact fixed point.  phi [N] is
- * output. */
-int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sweeps, double *phi,
-                   int *sweeps_out) {
-  if (orc_check(F)) return ORC_EINVAL;
+ * feedback (eq. HJBridotta_discreta, in the reading `mode`), iterated
+ * (Jacobi) from below to the exact fixed point.  phi [N] is output. */
+int orc_trace_part_mode(const orc_problem *F, const uint8_t *fb, int part, int mode,
+                        int max_sweeps, double *phi, int *sweeps_out) {
+  if (orc_check(F) || mode < 0 || mode > 3) return ORC_EINVAL;
+  if (mode == ORC_TRACE_PAPER)
+    for (int d = 1; d < F->dim; ++d)
+      if (F->step[d] != F->step[0]) return ORC_EINVAL;
   long long N = orc_N(F), nx = F->n[0], ny = F->n[1];
   long long cnt = 0;
   long long *nodes = (long long *)malloc(sizeof(long long) * (size_t)N);
@@ -477,12 +506,28 @@ int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sw
       long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
       double disp[3];
       orc_displacement(F, q, fb[q], disp);
+      if (mode == ORC_TRACE_PAPER) {
+        /* |h_i f| = k: the displacement in cells scaled to length 1; a node
+         * where f vanishes does not move */
+        double len2 = 0.0;
+        for (int d = 0; d < F->dim; ++d) len2 = len2 + disp[d] * disp[d];
+        double len = sqrt(len2);
+        for (int d = 0; d < F->dim; ++d) disp[d] = len > 0.0 ? disp[d] / len : 0.0;
+      }
       double I = orc_interp(F, phi, NULL, x, y, z, disp, 0.0);
-      double b = F->beta_pk     ? F->beta_pk[(long long)fb[q] * N + q]
-                 : F->beta_node ? F->beta_node[q]
-                                : F->beta;
-      double bI = b * I;
-      if (bI < ORC_COLOUR_FLOOR) bI = 0.0;
+      double bI = I;
+      if (mode == ORC_TRACE_DISCOUNTED || mode == ORC_TRACE_LATTICE) {
+        double b = F->beta_pk     ? F->beta_pk[(long long)fb[q] * N + q]
+                   : F->beta_node ? F->beta_node[q]
+                                  : F->beta;
+        bI = b * I;
+        if (mode == ORC_TRACE_LATTICE) {
+          /* scaling by a power of two is exact: floor to the lattice */
+          bI = floor(bI * ORC_COLOUR_LATTICE) / ORC_COLOUR_LATTICE;
+        } else if (bI < ORC_COLOUR_FLOOR) {
+          bI = 0.0;
+        }
+      }
       double nv = bI > phi[q] ? bI : phi[q];
       if (nv != phi[q]) changed = 1;
       pn[q] = nv;
@@ -497,10 +542,18 @@ int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sw
   return rc;
 }
 
+/* Public: Step 3.1 for one part j in the reading used for the labels. */
+int orc_trace_part(const orc_problem *F, const uint8_t *fb, int part, int max_sweeps, double *phi,
+                   int *sweeps_out) {
+  return orc_trace_part_mode(F, fb, part, ORC_TRACE_LATTICE, max_sweeps, phi, sweeps_out);
+}
+
 /* Remark 3.1: nodes no colour reached take the colour of their neighbours.
- * Jacobi layers: an unlabelled node with labelled neighbours (8 in 2D, 26
- * in 3D) takes the smallest of their labels; repeat until no node changes.
- * The result is the lowest label among the nearest labelled nodes.
+ * Jacobi layers: an unlabelled node with labelled axis neighbours (4 in 2D,
+ * 6 in 3D) takes the smallest of their labels; repeat until no node
+ * changes.  The result is the lowest label among the nearest labelled nodes
+ * (in steps along the axes), and a filled node joins a piece of its patch
+ * through a face.
  * *filled (optional) receives the number of nodes that were unlabelled. */
 int orc_fill_labels(const orc_problem *F, int16_t *labels, long long *filled) {
   long long N = orc_N(F), nx = F->n[0], ny = F->n[1], nz = F->n[2];
@@ -519,6 +572,7 @@ int orc_fill_labels(const orc_problem *F, int16_t *labels, long long *filled) {
       for (int dz = dz0; dz <= dz1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
           for (int dx = -1; dx <= 1; ++dx) {
+            if (abs(dx) + abs(dy) + abs(dz) != 1) continue; /* axis neighbours */
             long long X = x + dx, Y = y + dy, Z = z + dz;
             if (X < 0 || Y < 0 || Z < 0 || X >= nx || Y >= ny || Z >= nz) continue;
             int L = labels[X + nx * (Y + ny * Z)];
@@ -537,12 +591,73 @@ int orc_fill_labels(const orc_problem *F, int16_t *labels, long long *filled) {
   return ORC_OK;
 }
 
+/* Public: pieces of a patch cut off from its own target part (Section 3,
+ * Remark 3.1 and the discussion of Fig. independence).  The argmax
+ * projection can leave a piece of the nodes of label j that holds no target
+ * node of part j: no characteristic of patch j runs from it to Omega_0^j, so
+ * under the state constraint of Step 3.2 its values stay at or near 1
+ * (T = +inf).  Pieces are connected through the axis neighbours (4 in 2D, 6
+ * in 3D): nodes that touch only at a corner form a chain too thin for the
+ * interpolation stencil of the scheme to carry values along it.  Such a
+ * piece is treated like the nodes no colour reached: its labels become -1,
+ * and orc_fill_labels gives them the colour of their neighbours.  Target
+ * nodes carry their own part as label, so a piece is attached iff it
+ * contains a target node.  Obstacle (-2) and unlabelled (-1) nodes separate
+ * pieces.  *detached (optional) receives the number of relabelled nodes.
+ * Plain breadth-first search over the grid. */
+int orc_detach_fragments(const orc_problem *F, int16_t *labels, long long *detached) {
+  long long N = orc_N(F), nx = F->n[0], ny = F->n[1], nz = F->n[2];
+  long long *queue = (long long *)malloc(sizeof(long long) * (size_t)(N > 0 ? N : 1));
+  uint8_t *seen = (uint8_t *)calloc((size_t)(N > 0 ? N : 1), 1);
+  if (!queue || !seen) { free(queue); free(seen); return ORC_ENOMEM; }
+  int dz0 = nz > 1 ? -1 : 0, dz1 = nz > 1 ? 1 : 0;
+  long long cut = 0;
+  for (long long s0 = 0; s0 < N; ++s0) {
+    if (seen[s0] || labels[s0] < 0) continue;
+    int L = labels[s0];
+    long long head = 0, tail = 0;
+    int attached = 0;
+    queue[tail++] = s0;
+    seen[s0] = 1;
+    while (head < tail) {
+      long long q = queue[head++];
+      if (F->target_part[q] == L) attached = 1; /* a target node of part L */
+      long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
+      for (int dz = dz0; dz <= dz1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            if (abs(dx) + abs(dy) + abs(dz) != 1) continue; /* axis neighbours */
+            long long X = x + dx, Y = y + dy, Z = z + dz;
+            if (X < 0 || Y < 0 || Z < 0 || X >= nx || Y >= ny || Z >= nz) continue;
+            long long r = X + nx * (Y + ny * Z);
+            if (seen[r] || labels[r] != L) continue;
+            seen[r] = 1;
+            queue[tail++] = r;
+          }
+    }
+    if (!attached) {
+      /* the queue still lists the whole piece */
+      for (long long i = 0; i < tail; ++i) labels[queue[i]] = -1;
+      cut += tail;
+    }
+  }
+  free(queue);
+  free(seen);
+  if (detached) *detached = cut;
+  return ORC_OK;
+}
+
 /* Public: Step 3.1 for all parts, then the labels (projection/assembly,
  * eq. proiezionecolore with Remark 3.1): label = target part on target
  * nodes; elsewhere the part with the largest colour (lowest index on ties),
- * -1 where every colour is 0.  phi_sum (optional) receives sum_j phi^j. */
+ * -1 where every colour is 0; pieces cut off from their own target part
+ * become -1 as well (orc_detach_fragments), and every -1 node takes the
+ * colour of its neighbours (orc_fill_labels).  phi_sum (optional) receives
+ * sum_j phi^j; *unreached the nodes no colour reached, *detached the nodes
+ * of cut-off pieces. */
 int orc_labels(const orc_problem *F, const uint8_t *fb, int max_sweeps, int16_t *labels,
-               double *phi_sum, int *max_trace_sweeps, long long *unreached) {
+               double *phi_sum, int *max_trace_sweeps, long long *unreached,
+               long long *detached) {
   if (orc_check(F) || F->n_parts < 1) return ORC_EINVAL;
   long long N = orc_N(F);
   double *phi = (double *)malloc(sizeof(double) * (size_t)N);
@@ -571,7 +686,13 @@ int orc_labels(const orc_problem *F, const uint8_t *fb, int max_sweeps, int16_t 
   if (max_trace_sweeps) *max_trace_sweeps = mx;
   free(phi);
   free(best);
-  if (rc == ORC_OK) rc = orc_fill_labels(F, labels, unreached);
+  if (unreached) {
+    long long u = 0;
+    for (long long q = 0; q < N; ++q) u += labels[q] == -1;
+    *unreached = u;
+  }
+  if (rc == ORC_OK) rc = orc_detach_fragments(F, labels, detached);
+  if (rc == ORC_OK) rc = orc_fill_labels(F, labels, NULL);
   return rc;
 }
 

@@ -61,7 +61,10 @@ def lib():
         L.orc_feedback.argtypes = [vp, vp, vp]
         L.orc_feedback_at.argtypes = [vp, vp, vp, C.c_longlong, vp]
         L.orc_trace_part.argtypes = [vp, vp, i32, i32, vp, vp]
-        L.orc_labels.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+        L.orc_trace_part_mode.argtypes = [vp, vp, i32, i32, i32, vp, vp]
+        L.orc_labels.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
+        L.orc_detach_fragments.argtypes = [vp, vp, vp]
+        L.orc_fill_labels.argtypes = [vp, vp, vp]
         L.orc_solve_patches.argtypes = [vp, vp, d, i32, i32, vp, vp, vp]
         L.orc_solve_patches_ex.argtypes = [vp, vp, vp, d, vp, vp, d, i32, i32, vp, vp, vp]
         L.orc_cone_allowed.argtypes = [vp, d, vp]
@@ -205,7 +208,8 @@ def feedback_at(fine, u0: np.ndarray, idx: np.ndarray):
 
 
 def trace_part(fine, fb: np.ndarray, part: int, max_sweeps: int = 1_000_000):
-    """Step 3.1 for one part: the colour field phi^j at its fixed point."""
+    """Step 3.1 for one part in the labels' reading (the colour lattice):
+    the colour field phi^j at its fixed point."""
     H = _Held(fine)
     fb = np.ascontiguousarray(fb, dtype=np.uint8).ravel()
     phi = np.empty(fine.N, dtype=np.float64)
@@ -215,26 +219,74 @@ def trace_part(fine, fb: np.ndarray, part: int, max_sweeps: int = 1_000_000):
     return phi, sw.value
 
 
+TRACE_DISCOUNTED, TRACE_PLAIN, TRACE_PAPER, TRACE_LATTICE = 0, 1, 2, 3
+# spacing of the colour lattice of the labels' transport
+COLOUR_LATTICE = 2.0 ** -24
+
+
+def trace_part_mode(fine, fb: np.ndarray, part: int, mode: int, max_sweeps: int = 1_000_000,
+                    allow_noconv: bool = False):
+    """Step 3.1 for one part in one reading of eq. HJBridotta_discreta:
+    TRACE_LATTICE (the labels' reading: scheme step, factor beta, colours
+    rounded down to multiples of 2^-24), TRACE_DISCOUNTED (scheme step,
+    factor beta, floor 1e-9, unrounded), TRACE_PLAIN (scheme step, no
+    factor, no floor) or TRACE_PAPER (no factor, no floor, foot point one
+    cell away along f).  Returns (phi, sweeps, status)."""
+    H = _Held(fine)
+    fb = np.ascontiguousarray(fb, dtype=np.uint8).ravel()
+    phi = np.empty(fine.N, dtype=np.float64)
+    sw = C.c_int(0)
+    rc = lib().orc_trace_part_mode(H.ref, _p(fb), int(part), int(mode), int(max_sweeps), _p(phi),
+                                   C.byref(sw))
+    _check(rc, "trace_part_mode", allow_noconv)
+    return phi, sw.value, rc
+
+
 def labels(fine, fb: np.ndarray, max_sweeps: int = 1_000_000, want_sum: bool = False,
-           want_unreached: bool = False):
-    """Step 3.1 for every part plus the projection/assembly into labels
-    (with the Remark 3.1 fill of nodes no colour reached).  want_sum adds
-    (sum of colours, max sweeps of a part); want_unreached adds the number of
-    nodes no colour reached before the fill."""
+           want_unreached: bool = False, want_detached: bool = False):
+    """Step 3.1 for every part plus the projection/assembly into labels:
+    pieces of a patch cut off from their own target part are uncoloured, and
+    every uncoloured node takes its neighbours' colour (Remark 3.1).
+    want_sum adds (sum of colours, max sweeps of a part); want_unreached adds
+    the number of nodes no colour reached; want_detached the number of nodes
+    in cut-off pieces."""
     H = _Held(fine)
     fb = np.ascontiguousarray(fb, dtype=np.uint8).ravel()
     lab = np.empty(fine.N, dtype=np.int16)
     s = np.empty(fine.N, dtype=np.float64) if want_sum else None
     mx = C.c_int(0)
     un = C.c_longlong(0)
+    de = C.c_longlong(0)
     _check(lib().orc_labels(H.ref, _p(fb), int(max_sweeps), _p(lab), _p(s), C.byref(mx),
-                            C.byref(un)), "labels")
+                            C.byref(un), C.byref(de)), "labels")
     out = (lab,)
     if want_sum:
         out = out + (s, mx.value)
     if want_unreached:
         out = out + (un.value,)
+    if want_detached:
+        out = out + (de.value,)
     return out if len(out) > 1 else lab
+
+
+def detach_fragments(fine, labels_: np.ndarray):
+    """Remark 3.1 applied to cut-off pieces: the labels of every connected
+    piece of one label (8 / 26 neighbours) without a target node of that
+    label become -1.  Returns (new labels, number of nodes relabelled)."""
+    H = _Held(fine)
+    lab = np.array(labels_, dtype=np.int16).ravel()
+    de = C.c_longlong(0)
+    _check(lib().orc_detach_fragments(H.ref, _p(lab), C.byref(de)), "detach_fragments")
+    return lab, de.value
+
+
+def fill_labels(fine, labels_: np.ndarray):
+    """Remark 3.1: every -1 node takes the lowest label among its nearest
+    labelled nodes (layer by layer)."""
+    H = _Held(fine)
+    lab = np.array(labels_, dtype=np.int16).ravel()
+    _check(lib().orc_fill_labels(H.ref, _p(lab), None), "fill_labels")
+    return lab
 
 
 def solve_patches(fine, labels_: np.ndarray, tol: float = 0.0, max_sweeps: int = 1_000_000,

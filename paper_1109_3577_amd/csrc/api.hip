@@ -59,23 +59,44 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
   SweepEngine eng(cfg, s);
   eng.add_problem(P, code, &items, v, dbc);
   if (cone) eng.set_cone(*cone);
-  if (cfg.start_u0) {
+  std::vector<int32_t> all((size_t)eng.total_items());
+  for (size_t i = 0; i < all.size(); ++i) all[i] = (int32_t)i;
+  // With the Dirichlet data of eq. dbc a node whose stencil reads another
+  // patch's U^(0) < 1 starts above its fixed point anywhere in the patch,
+  // not only next to the target.  The rounds follow the changes outward
+  // from the target; a pass that then queues every item (the first run of
+  // an item sweeps all of its bricks) checks every node, and is repeated
+  // only when it changed a value (an item ran twice).  The asynchronous
+  // schedule has no end of rounds to check at: it starts from every item.
+  const bool verify = cfg.dbc && !cfg.start_u0 && !cfg.async;
+  if (cfg.start_u0 || (cfg.dbc && cfg.async)) {
     // every item starts away from its fixed point
-    std::vector<int32_t> all((size_t)eng.total_items());
-    for (size_t i = 0; i < all.size(); ++i) all[i] = (int32_t)i;
     eng.begin(&all);
   } else {
     eng.begin();
   }
-  const int status = eng.async_ok() ? eng.run_async() : eng.run();
-  if (st) {
+  int status = eng.async_ok() ? eng.run_async() : eng.run();
+  EngineResult acc = eng.results()[0];
+  long long rounds = eng.rounds();  // kernel time and launches accumulate in the engine
+  while (verify && status == HJB_OK) {
+    eng.begin(&all, true);
+    status = eng.run();
     const EngineResult r = eng.results()[0];
+    acc.work_nodes += r.work_nodes;
+    acc.item_runs += r.item_runs;
+    acc.residual = r.residual;
+    rounds += eng.rounds();
+    if (r.item_runs <= (unsigned long long)all.size()) break;  // nothing was queued again
+    if (rounds >= cfg.max_rounds) status = HJB_ENOCONV;
+  }
+  if (st) {
+    const EngineResult &r = acc;
     st->node_updates = (int64_t)r.work_nodes;
     // controls evaluated per node update: N_c, or the (padded) cone length
     st->updates = (int64_t)r.work_nodes * (cone ? cone->len : P.nc);
     st->item_runs = (int64_t)r.item_runs;
     st->items = eng.total_items();
-    st->rounds = (int32_t)eng.rounds();
+    st->rounds = (int32_t)rounds;
     st->residual = r.residual;
     st->ms_kernel = eng.kernel_ms();
     st->kernel_launches = eng.kernel_launches();
@@ -314,16 +335,28 @@ std::unique_ptr<PatchesHandle> trace_end(TraceJob &job, hipStream_t s) {
   const int dim = H.dim;
   const size_t N = H.N;
   const double t1 = now_ms();
-  DBuf unreached(sizeof(uint32_t) * 2);
-  HJB_HIP(launch_fill_u32(unreached.as<uint32_t>(), 0u, 1, s));
+  HJB_REQUIRE(N < (size_t)INT32_MAX, "grid of %zu nodes is too large for the labels", N);
+  // [0] unreached, [1] fill flag, [2] nodes of cut-off pieces
+  DBuf unreached(sizeof(uint32_t) * 4);
+  HJB_HIP(launch_fill_u32(unreached.as<uint32_t>(), 0u, 4, s));
   HJB_HIP(launch_labels(dim, a, H.labels.as<int16_t>(), unreached.as<uint32_t>(), s));
-  uint32_t un = 0;
+  // pieces of a patch cut off from their own target part are uncoloured
+  DBuf parent(N * sizeof(int32_t)), attached(N);
+  const int32_t nn[3] = {H.n[0], H.n[1], H.n[2]};
+  HJB_HIP(launch_detach_pieces(nn, job.tp_eff.as<int16_t>(), H.labels.as<int16_t>(),
+                               parent.as<int32_t>(), attached.as<uint8_t>(),
+                               unreached.as<uint32_t>() + 2, s));
+  uint32_t cnt4[4] = {0, 0, 0, 0};
   PinnedBuf host(64);
-  HJB_HIP(hipMemcpyAsync(&un, unreached.get(), sizeof un, hipMemcpyDeviceToHost, s));
+  HJB_HIP(hipMemcpyAsync(cnt4, unreached.get(), sizeof cnt4, hipMemcpyDeviceToHost, s));
   HJB_HIP(hipStreamSynchronize(s));
-  if (un > 0) {
+  const uint32_t un = cnt4[0], detached = cnt4[2];
+  // the fill's second buffer lives until the stream is synchronised below
+  // (a block handed back to the pool may be reused by another thread)
+  DBuf tmp;
+  if (un + detached > 0) {
     // Remark 3.1 fill of the nodes no colour reached, layer by layer
-    DBuf tmp(N * sizeof(int16_t));
+    tmp.reset(N * sizeof(int16_t));
     int16_t *cur = H.labels.as<int16_t>(), *nxt = tmp.as<int16_t>();
     const int32_t n3[3] = {H.n[0], H.n[1], H.n[2]};
     uint32_t *flag = unreached.as<uint32_t>() + 1;
@@ -353,6 +386,7 @@ std::unique_ptr<PatchesHandle> trace_end(TraceJob &job, hipStream_t s) {
   H.st.ms_trace = job.ms_rounds + (t2 - t1);
   H.st.trace_node_updates = job.trace_node_updates;
   H.st.unreached = (int32_t)un;
+  H.st.detached = (int32_t)detached;
   H.st.excluded = (int32_t)excluded;
   H.st.rounds = (int32_t)job.rounds;
   H.st.item_runs = job.item_runs;

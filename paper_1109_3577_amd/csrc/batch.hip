@@ -44,40 +44,46 @@ struct Prepared {
 };
 
 // Host copy of an hjb_problem's arrays (for requests queued by the server).
+// The arrays are not zero-filled before the copy: a 193^3 request holds
+// about 100 MB, copied on the caller's thread while the rounds wait.
 struct ProblemCopy {
   hjb_problem p{};
-  std::vector<double> ctrl, speed, drift, bnode;
-  std::vector<int16_t> tp;
+  std::unique_ptr<double[]> ctrl, speed, drift, bnode;
+  std::unique_ptr<int16_t[]> tp;
+  template <typename T>
+  static std::unique_ptr<T[]> copy(const T *src, size_t n, int32_t mem, hipStream_t s) {
+    std::unique_ptr<T[]> dst(new T[n]);
+    if (mem == HJB_MEM_HOST) std::memcpy(dst.get(), src, n * sizeof(T));
+    else HJB_HIP(hipMemcpyAsync(dst.get(), src, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    return dst;
+  }
   void take(const hjb_problem &src, hipStream_t s) {
     p = src;
     const size_t N = (size_t)src.n[0] * src.n[1] * src.n[2];
-    ctrl.resize((size_t)src.n_controls * src.dim);
-    speed.resize(N);
-    tp.resize(N);
-    if (src.drift) drift.resize(N * src.dim);
-    const hipMemcpyKind k = src.mem == HJB_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
-    HJB_HIP(hipMemcpyAsync(ctrl.data(), src.controls, ctrl.size() * sizeof(double), k, s));
-    HJB_HIP(hipMemcpyAsync(speed.data(), src.speed, N * sizeof(double), k, s));
-    HJB_HIP(hipMemcpyAsync(tp.data(), src.target_part, N * sizeof(int16_t), k, s));
-    if (src.drift)
-      HJB_HIP(hipMemcpyAsync(drift.data(), src.drift, drift.size() * sizeof(double), k, s));
-    if (src.beta_node) {
-      bnode.resize(N);
-      HJB_HIP(hipMemcpyAsync(bnode.data(), src.beta_node, N * sizeof(double), k, s));
-    }
-    HJB_HIP(hipStreamSynchronize(s));
-    p.controls = ctrl.data();
-    p.speed = speed.data();
-    p.drift = src.drift ? drift.data() : nullptr;
-    p.target_part = tp.data();
-    p.beta_node = src.beta_node ? bnode.data() : nullptr;
+    ctrl = copy(src.controls, (size_t)src.n_controls * src.dim, src.mem, s);
+    speed = copy(src.speed, N, src.mem, s);
+    tp = copy(src.target_part, N, src.mem, s);
+    if (src.drift) drift = copy(src.drift, N * src.dim, src.mem, s);
+    if (src.beta_node) bnode = copy(src.beta_node, N, src.mem, s);
+    if (src.mem != HJB_MEM_HOST) HJB_HIP(hipStreamSynchronize(s));
+    p.controls = ctrl.get();
+    p.speed = speed.get();
+    p.drift = src.drift ? drift.get() : nullptr;
+    p.target_part = tp.get();
+    p.beta_node = src.beta_node ? bnode.get() : nullptr;
     p.mem = HJB_MEM_HOST;
   }
 };
 
-SweepShape engine_shape(int dim, bool fp64, const hjb_solve_opts *opts) {
-  HJB_REQUIRE(!opts || opts->schedule != HJB_SCHED_ASYNC,
-              "batches and the server run in rounds (HJB_SCHED_ASYNC is for single solves)");
+// `server`: the continuous engine of the server admits requests between
+// rounds, so it runs in rounds only; a batch may also drain its items in
+// one persistent launch (HJB_SCHED_ASYNC).
+SweepShape engine_shape(int dim, bool fp64, const hjb_solve_opts *opts, bool server = false) {
+  HJB_REQUIRE(!server || !opts || opts->schedule != HJB_SCHED_ASYNC,
+              "the server runs in rounds (HJB_SCHED_ASYNC is for single solves and batches)");
+  HJB_REQUIRE(!opts || opts->schedule != HJB_SCHED_ASYNC ||
+                  (opts->order_window == 0.0 && opts->start_u0 == 0 && !opts->use_graph),
+              "HJB_SCHED_ASYNC runs without order_window, start_u0 and use_graph");
   HJB_REQUIRE(!opts || opts->control_cone == 0.0,
               "control_cone is an option of hjb_solve_patches only");
   HJB_REQUIRE(!opts || opts->start_u0 == 0 || opts->start_u0 == 1, "start_u0 must be 0 or 1");
@@ -110,7 +116,9 @@ void finish_prepared(Prepared &pr, bool fp64, const hjb_solve_opts *opts, hipStr
   if (opts && opts->order_window > 0.0)
     build_item_keys(*pr.P, pr.patches->code.as<int16_t>(), pr.patches->u0.as<double>(), sh,
                     pr.items, s);
-  if (start_u0) {  // every item starts away from its fixed point
+  if (start_u0 || (opts && opts->patch_bc == HJB_BC_DIRICHLET)) {
+    // every item starts away from its fixed point (from U^(0), or reading
+    // other patches' U^(0) as Dirichlet data); seeds sweep all bricks first
     pr.items.seeds.resize(pr.items.items.size());
     for (size_t i = 0; i < pr.items.seeds.size(); ++i) pr.items.seeds[i] = (int32_t)i;
   }
@@ -372,6 +380,13 @@ int hjb_batch_run(hjb_batch_t *b, hjb_stream_t stream, hjb_stats *st) {
     const int rpp = std::max(1, b->opts.solve.rounds_per_poll > 0 ? b->opts.solve.rounds_per_poll : 6);
     bool live[2] = {b->eng[0] != nullptr, b->eng[1] != nullptr};
     int status = HJB_OK;
+    // HJB_SCHED_ASYNC: each dimension's items in one persistent launch
+    for (int d = 0; d < 2; ++d) {
+      if (!live[d] || !b->eng[d]->async_ok()) continue;
+      const int sa = b->eng[d]->run_async();
+      if (sa != HJB_OK) status = sa;
+      live[d] = false;
+    }
     while (live[0] || live[1]) {
       for (int d = 0; d < 2; ++d) {
         if (!live[d]) continue;
@@ -405,6 +420,7 @@ int hjb_batch_run(hjb_batch_t *b, hjb_stream_t stream, hjb_stats *st) {
         p->st.ms_prolong_feedback = p->patches->st.ms_prolong_feedback;
         p->st.ms_trace = p->patches->st.ms_trace;
         p->st.unreached = p->patches->st.unreached;
+        p->st.detached = p->patches->st.detached;
         upd += p->st.updates;
         nodes += p->st.node_updates;
         runs += p->st.item_runs;
@@ -457,6 +473,9 @@ struct Request {
   ReqState state = QUEUED;
   std::unique_ptr<Prepared> prep;
   long long rounds_live = 0;
+  // work of the engines this request left behind (they are rebuilt when
+  // requests join or leave)
+  unsigned long long work_acc = 0, runs_acc = 0;
   int status = HJB_OK;
   std::string error;     // message of a failed preparation
   double ms_prepare = 0.0;
@@ -480,6 +499,13 @@ struct hjb_server_s {
   std::map<uint64_t, std::unique_ptr<Request>> reqs;
   std::unique_ptr<SweepEngine> eng[2];
   std::vector<Request *> members[2];  // engine problem index -> request
+  // Each dimension's rounds run on a stream of their own and are polled
+  // separately, so that cheap 2D rounds keep going while a block of 3D
+  // rounds is in flight.
+  hipStream_t es[2] = {nullptr, nullptr};
+  bool inflight[2] = {false, false};
+  int inflight_rounds[2] = {0, 0};
+  std::vector<Request *> joining[2];  // prepared, waiting for their engine to be idle
   std::vector<std::unique_ptr<Request>> retired;  // collected, still listed by an engine
   SolveConfig cfg[2];
   // preparation pool
@@ -500,6 +526,11 @@ struct hjb_server_s {
     }
     pcv.notify_all();
     for (auto &t : workers) t.join();
+    for (int d = 0; d < 2; ++d) {
+      if (es[d]) (void)hipStreamSynchronize(es[d]);
+      eng[d].reset();
+      if (es[d]) (void)hipStreamDestroy(es[d]);
+    }
   }
 };
 
@@ -558,10 +589,16 @@ namespace {
 // carrying the queued items of the running ones over (a queued item keeps
 // its place; only its global id changes).
 void rebuild_engine(hjb_server_s &S, int d, const std::vector<Request *> &added) {
-  std::vector<int32_t> carried;  // (request index in new list, local id)
   std::vector<Request *> keep;
   std::vector<std::vector<int32_t>> carry_local;
   if (S.eng[d]) {
+    const std::vector<EngineResult> res = S.eng[d]->results();
+    for (size_t m = 0; m < S.members[d].size(); ++m) {
+      Request *r = S.members[d][m];
+      if (r->state != LIVE) continue;
+      r->work_acc += res[m].work_nodes;
+      r->runs_acc += res[m].item_runs;
+    }
     const std::vector<int32_t> q = S.eng[d]->queue_now();
     std::vector<std::vector<int32_t>> per(S.members[d].size());
     // map a global id back to (member, local id) through the bases
@@ -585,7 +622,7 @@ void rebuild_engine(hjb_server_s &S, int d, const std::vector<Request *> &added)
   S.eng[d].reset();
   S.members[d].clear();
   if (keep.empty()) return;
-  auto e = std::make_unique<SweepEngine>(S.cfg[d], S.s);
+  auto e = std::make_unique<SweepEngine>(S.cfg[d], S.es[d]);
   std::vector<int32_t> seeds;
   for (size_t i = 0; i < keep.size(); ++i) {
     Prepared &p = *keep[i]->prep;
@@ -631,8 +668,9 @@ int hjb_server_create(size_t hbm_budget, const hjb_server_opts *opts, hjb_stream
     S->s = as_stream(stream);
     for (int d = 0; d < 2; ++d)
       S->cfg[d] = make_config(d + 2, S->fp64, &S->opts.solve, S->opts.tol, 0);
-    (void)engine_shape(2, S->fp64, &S->opts.solve);  // rejects HJB_SCHED_ASYNC
+    (void)engine_shape(2, S->fp64, &S->opts.solve, true);  // rejects HJB_SCHED_ASYNC
     HJB_HIP(hipGetDevice(&S->device));
+    for (int d = 0; d < 2; ++d) HJB_HIP(hipStreamCreate(&S->es[d]));
     for (int t = 0; t < kPrepareThreads; ++t) S->workers.emplace_back([p = S.get()] { p->worker(); });
     *out = S.release();
     return HJB_OK;
@@ -643,8 +681,11 @@ int hjb_server_submit(hjb_server_t *S, const hjb_problem *fine, const hjb_proble
                       uint64_t *ticket) {
   return guarded([&]() -> int {
     HJB_REQUIRE(S != nullptr && ticket != nullptr, "server or ticket is NULL");
-    validate_problem(fine, S->s);
-    validate_problem(coarse, S->s);
+    // The per-node checks (finite data, reach, target parts) run in the
+    // preparation pool, off the serving loop; a request that fails them
+    // returns the error from hjb_server_poll.
+    validate_header(fine);
+    validate_header(coarse);
     HJB_REQUIRE(fine->dim == coarse->dim, "fine and coarse dimensions differ");
     auto r = std::make_unique<Request>();
     r->footprint = footprint_bytes(*fine, *coarse, S->fp64);
@@ -690,7 +731,6 @@ int hjb_server_step(hjb_server_t *S, int32_t rounds, int32_t *live, int32_t *que
       ready.swap(S->prepared);
       S->preparing -= (int)ready.size();
     }
-    std::vector<Request *> added[2];
     for (Request *r : ready) {
       // the request's host copies are no longer needed
       r->fine = ProblemCopy();
@@ -704,51 +744,71 @@ int hjb_server_step(hjb_server_t *S, int32_t rounds, int32_t *live, int32_t *que
       r->st.ms_prolong_feedback = r->prep->patches->st.ms_prolong_feedback;
       r->st.ms_trace = r->prep->patches->st.ms_trace;
       r->st.unreached = r->prep->patches->st.unreached;
+      r->st.detached = r->prep->patches->st.detached;
       r->st.ms_wall = r->ms_prepare;
       r->state = LIVE;
-      added[r->prep->dim - 2].push_back(r);
+      S->joining[r->prep->dim - 2].push_back(r);
     }
-    for (int d = 0; d < 2; ++d)
-      if (!added[d].empty()) rebuild_engine(*S, d, added[d]);
-    // Shared sweep rounds over every live request.
     const long long cap = S->opts.max_sweeps > 0 ? S->opts.max_sweeps : 1000000;
+    const int n = std::max(1, rounds);
+    // A dimension whose engine is idle takes its joiners and enqueues its
+    // next block of rounds; the step then returns as soon as one
+    // dimension's block has finished (the other keeps running).
     for (int d = 0; d < 2; ++d) {
+      if (S->inflight[d]) continue;
+      if (!S->joining[d].empty()) {
+        rebuild_engine(*S, d, S->joining[d]);
+        S->joining[d].clear();
+      }
       if (!S->eng[d]) continue;
       bool any = false;
       for (Request *r : S->members[d]) any |= r->state == LIVE;
       if (!any) continue;
-      const int n = std::max(1, rounds);
-      S->eng[d]->run_rounds(n);
-      const std::vector<uint32_t> pa = S->eng[d]->pactive_now();
-      std::vector<EngineResult> res;
-      bool capped = false;
-      for (size_t m = 0; m < S->members[d].size(); ++m) {
-        Request *r = S->members[d][m];
-        if (r->state != LIVE) continue;
-        r->rounds_live += n;
-        const bool conv = pa[m] == 0;
-        if (conv || r->rounds_live >= cap) {
-          if (res.empty()) res = S->eng[d]->results();
-          r->state = DONE;
-          r->status = conv ? HJB_OK : HJB_ENOCONV;
-          capped |= !conv;
-          r->st.node_updates = (int64_t)res[m].work_nodes;
-          r->st.updates = (int64_t)res[m].work_nodes * r->prep->P->nc;
-          r->st.item_runs = (int64_t)res[m].item_runs;
-          r->st.items = (int32_t)r->prep->items.items.size();
-          r->st.residual = res[m].residual;
-          r->st.rounds = (int32_t)r->rounds_live;
-          r->st.status = r->status;
+      S->eng[d]->launch_rounds_async(n);
+      S->inflight[d] = true;
+      S->inflight_rounds[d] = n;
+    }
+    for (bool finished = false; !finished && (S->inflight[0] || S->inflight[1]);) {
+      for (int d = 0; d < 2; ++d) {
+        if (!S->inflight[d] || !S->eng[d]->rounds_done()) continue;
+        finished = true;
+        S->inflight[d] = false;
+        std::vector<uint32_t> pa;
+        (void)S->eng[d]->rounds_result(&pa);
+        const int nr = S->inflight_rounds[d];
+        std::vector<EngineResult> res;
+        bool capped = false;
+        for (size_t m = 0; m < S->members[d].size(); ++m) {
+          Request *r = S->members[d][m];
+          if (r->state != LIVE) continue;
+          r->rounds_live += nr;
+          const bool conv = pa[m] == 0;
+          if (conv || r->rounds_live >= cap) {
+            if (res.empty()) res = S->eng[d]->results();
+            r->state = DONE;
+            r->status = conv ? HJB_OK : HJB_ENOCONV;
+            capped |= !conv;
+            r->st.node_updates = (int64_t)(r->work_acc + res[m].work_nodes);
+            r->st.updates = r->st.node_updates * r->prep->P->nc;
+            r->st.item_runs = (int64_t)(r->runs_acc + res[m].item_runs);
+            r->st.items = (int32_t)r->prep->items.items.size();
+            r->st.residual = res[m].residual;
+            r->st.rounds = (int32_t)r->rounds_live;
+            r->st.status = r->status;
+          }
         }
+        // A request stopped by the round cap may still have queued items:
+        // rebuild without it so that its buffers are never touched again.
+        if (capped) rebuild_engine(*S, d, {});
       }
-      // A request stopped by the round cap may still have queued items:
-      // rebuild without it so that its buffers are never touched again.
-      if (capped) rebuild_engine(*S, d, {});
+      if (!finished) std::this_thread::yield();
     }
     drop_retired(*S);
     int nl = 0;
-    for (int d = 0; d < 2; ++d)
+    for (int d = 0; d < 2; ++d) {
       for (Request *r : S->members[d]) nl += r->state == LIVE;
+      nl += (int)S->joining[d].size();
+    }
     if (live) *live = nl;
     if (queued) {
       std::lock_guard<std::mutex> g(S->pm);

@@ -11,8 +11,12 @@
 //                    HJBridotta_discreta, for a chunk of parts at once,
 //                    iterated from below (phi <- max(phi, I[phi])) on LDS
 //                    tiles with active-tile lists until nothing changes;
-//   k_label_update   projection/assembly (eq. proiezionecolore, Remark 3.1):
-//                    running argmax over the parts, lowest index on ties.
+//   k_labels         projection/assembly (eq. proiezionecolore, Remark 3.1):
+//                    argmax over the parts, lowest index on ties;
+//   k_piece_*        pieces of a patch cut off from its own target part
+//                    (union-find over equal labels) are uncoloured;
+//   k_label_fill     uncoloured nodes take their neighbours' colour
+//                    (Remark 3.1), one layer per launch.
 //
 // The transport update is monotone in the colours and starts from below,
 // so like the value iteration it reaches the same least fixed point in any
@@ -138,15 +142,17 @@ hipError_t launch_feedback(int dim, const TraceArgs &a, const double *u0, uint8_
 // stay zero); each part's transport is independent of the others, so
 // processing a subset changes no bit of any colour.
 
-// Colour update phi <- max(phi, beta I[phi]): beta = exp(-h) is the
+// Colour update phi <- max(phi, Q(beta I[phi])): beta = exp(-h) is the
 // scheme's per-step factor in the Kruzkov variable, so a colour is the
 // share of exp(-T) part j carries along the frozen feedback and the map is a
 // beta-contraction (undamped, near-closed loops of the frozen feedback make
-// the iteration contract arbitrarily slowly).  Colours below the floor count
-// as zero: only their projection is used (the paper lets this iteration stop
-// very roughly), and the floor keeps each part's support compact.  Both
-// maps are monotone.
-constexpr double kColourFloor = 1e-9;
+// the iteration contract arbitrarily slowly).  Q rounds down to a multiple
+// of 2^-24: only the projection of the colours is used (the paper lets this
+// iteration stop very roughly), so increments below the lattice spacing are
+// not pursued, and each part's support stays compact.  Q is monotone, so
+// the rounded map is too, and every fair order of updates stops at the same
+// colours.  Scaling by a power of two is exact.
+constexpr double kColourLattice = 16777216.0;  // 2^24
 
 // Colour-transport tiles: 2D 32 x 16 nodes, 512 threads, 8 FP64 fields per
 // LDS group, up to 24 in-tile sweeps per activation; 3D 8 x 8 x 8, 256
@@ -190,7 +196,7 @@ hipError_t launch_trace_init(int dim, const TraceArgs &a, hipStream_t s) {
 }
 
 // One colour update from the corner values of the foot cell (x fastest):
-// beta times the nested linear interpolation, colours below the floor to 0.
+// beta times the nested linear interpolation, rounded down to the lattice.
 template <int DIM>
 __device__ __forceinline__ double colour_step(const double *c, double t0, double t1, double t2,
                                               double beta) {
@@ -204,8 +210,7 @@ __device__ __forceinline__ double colour_step(const double *c, double t0, double
     I = Ar<double>::lin(t2, I, I1);
   }
   I = beta * I;
-  if (I < kColourFloor) I = 0.0;
-  return I;
+  return __builtin_floor(I * kColourLattice) * (1.0 / kColourLattice);
 }
 
 // A load from a device buffer through the global address space.  The
@@ -656,8 +661,191 @@ hipError_t launch_labels(int dim, const TraceArgs &a, int16_t *labels, uint32_t 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- cut-off pieces
+
+// The argmax projection can leave a piece of the nodes of label j that holds
+// no target node of part j: no characteristic of patch j runs from it to its
+// target part, and under the state constraint of Step 3.2 its values would
+// stay at or near 1.  Pieces are connected through the 4 (2D) or 6 (3D) axis
+// neighbours: a chain of nodes that touch only at corners is too thin for the
+// interpolation stencil to carry values along it.  Such a piece is uncoloured
+// (label -1) and then takes its neighbours' colour like the nodes no colour
+// reached (Remark 3.1).  Target nodes carry their own part as label, so a
+// piece is attached iff it contains a target node.
+//
+// The pieces are found by union-find: first within each tile in LDS, then
+// across tile faces in global memory.  Parent pointers only ever decrease
+// (atomicMin), so every chain ends at a root and the partition does not
+// depend on the order of the unions.  Parent reads in the cross-tile merge go
+// to the device-coherent level (the workgroups of one launch run on
+// different XCDs).
+
+constexpr int PC2_TX = 16, PC2_TY = 16;            // 2D piece tiles (256 nodes)
+constexpr int PC3_TX = 8, PC3_TY = 8, PC3_TZ = 4;  // 3D piece tiles (256 nodes)
+
+__device__ __forceinline__ int uf_root(const int32_t *p, int x) {
+  int y = ld_dev(p + x);
+  while (y != x) {
+    x = y;
+    y = ld_dev(p + x);
+  }
+  return x;
+}
+
+__device__ __forceinline__ void uf_unite(int32_t *p, int a, int b) {
+  for (;;) {
+    a = uf_root(p, a);
+    b = uf_root(p, b);
+    if (a == b) return;
+    if (a < b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    // link the larger root under the smaller; if a stopped being a root in
+    // the meantime, its new parent is joined with b in the next pass
+    const int old = atomicMin(p + a, b);
+    if (old == a) return;
+    a = old;
+  }
+}
+
+__device__ __forceinline__ int lds_root(const int *p, int x) {
+  int y = __hip_atomic_load(p + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  while (y != x) {
+    x = y;
+    y = __hip_atomic_load(p + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  return x;
+}
+
+__device__ __forceinline__ void lds_unite(int *p, int a, int b) {
+  for (;;) {
+    a = lds_root(p, a);
+    b = lds_root(p, b);
+    if (a == b) return;
+    if (a < b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const int old = atomicMin(p + a, b);
+    if (old == a) return;
+    a = old;
+  }
+}
+
+// Pieces within one tile: parent[g] = the smallest flat index of g's piece
+// inside the tile (local order and flat order agree within a tile).
+template <int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX * TY * TZ)
+k_piece_local(int n0, int n1, int n2, int nt0, int nt1, const int16_t *__restrict__ labels,
+              int32_t *parent) {
+  constexpr int TN = TX * TY * TZ;
+  __shared__ int s_par[TN];
+  __shared__ int s_lab[TN];
+  const int t = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int ox = (tile % nt0) * TX, oy = ((tile / nt0) % nt1) * TY, oz = (tile / (nt0 * nt1)) * TZ;
+  const int lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
+  const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+  const bool inb = gx < n0 && gy < n1 && gz < n2;
+  const size_t g = (size_t)gx + (size_t)n0 * ((size_t)gy + (size_t)n1 * gz);
+  const int L = inb ? labels[g] : -1;
+  s_lab[t] = L;
+  s_par[t] = t;
+  __syncthreads();
+  if (L >= 0) {
+    if (lx + 1 < TX && s_lab[t + 1] == L) lds_unite(s_par, t, t + 1);
+    if (ly + 1 < TY && s_lab[t + TX] == L) lds_unite(s_par, t, t + TX);
+    if (TZ > 1 && lz + 1 < TZ && s_lab[t + TX * TY] == L) lds_unite(s_par, t, t + TX * TY);
+  }
+  __syncthreads();
+  if (L >= 0) {
+    const int r = lds_root(s_par, t);
+    const int rx = ox + r % TX, ry = oy + (r / TX) % TY, rz = oz + r / (TX * TY);
+    parent[g] = (int32_t)((size_t)rx + (size_t)n0 * ((size_t)ry + (size_t)n1 * rz));
+  }
+}
+
+// Unions across tile faces: a labelled node on the +x, +y or +z face of its
+// tile with the axis neighbour beyond it, when that carries the same label.
+template <int TX, int TY, int TZ>
+__global__ void k_piece_faces(int n0, int n1, int n2, const int16_t *__restrict__ labels,
+                              int32_t *parent) {
+  const size_t N = (size_t)n0 * n1 * n2;
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int L = labels[g];
+  if (L < 0) return;
+  const int x = (int)(g % n0), y = (int)((g / n0) % n1), z = (int)(g / ((size_t)n0 * n1));
+  if (x % TX == TX - 1 && x + 1 < n0 && labels[g + 1] == L) uf_unite(parent, (int)g, (int)g + 1);
+  if (y % TY == TY - 1 && y + 1 < n1 && labels[g + n0] == L)
+    uf_unite(parent, (int)g, (int)(g + n0));
+  if (n2 > 1 && z % TZ == TZ - 1 && z + 1 < n2 && labels[g + (size_t)n0 * n1] == L)
+    uf_unite(parent, (int)g, (int)(g + (size_t)n0 * n1));
+}
+
+__global__ void k_piece_clear(size_t N, uint8_t *attached) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < N) attached[g] = 0;
+}
+
+// Every labelled node points at its root; the root of a piece with a
+// target node is marked attached.
+__global__ void k_piece_flatten(size_t N, const int16_t *__restrict__ labels,
+                                const int16_t *__restrict__ tp, int32_t *parent,
+                                uint8_t *attached) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N || labels[g] < 0) return;
+  const int r = uf_root(parent, (int)g);
+  parent[g] = r;
+  if (tp[g] == labels[g]) attached[r] = 1;  // a target node of the piece's part
+}
+
+__global__ void k_piece_detach(size_t N, const int16_t *__restrict__ tp,
+                               const int32_t *__restrict__ parent,
+                               const uint8_t *__restrict__ attached, int16_t *labels,
+                               uint32_t *count) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int cut = 0;
+  if (g < N && tp[g] < 0 && labels[g] >= 0 && !attached[parent[g]]) {
+    labels[g] = -1;
+    cut = 1;
+  }
+  for (int o = 32; o >= 1; o >>= 1) cut += __shfl_xor(cut, o, 64);
+  if ((threadIdx.x & 63) == 0 && cut) atomicAdd(count, (uint32_t)cut);
+}
+
+hipError_t launch_detach_pieces(const int32_t n[3], const int16_t *tp, int16_t *labels,
+                                int32_t *parent, uint8_t *attached, uint32_t *count,
+                                hipStream_t s) {
+  const size_t N = (size_t)n[0] * n[1] * n[2];
+  const dim3 grid((unsigned)((N + 255) / 256)), block(256);
+  if (n[2] == 1) {
+    const int nt0 = (n[0] + PC2_TX - 1) / PC2_TX, nt1 = (n[1] + PC2_TY - 1) / PC2_TY;
+    hipLaunchKernelGGL((k_piece_local<PC2_TX, PC2_TY, 1>), dim3((unsigned)(nt0 * nt1)),
+                       dim3(PC2_TX * PC2_TY), 0, s, n[0], n[1], n[2], nt0, nt1, labels, parent);
+    hipLaunchKernelGGL((k_piece_faces<PC2_TX, PC2_TY, 1>), grid, block, 0, s, n[0], n[1], n[2],
+                       labels, parent);
+  } else {
+    const int nt0 = (n[0] + PC3_TX - 1) / PC3_TX, nt1 = (n[1] + PC3_TY - 1) / PC3_TY;
+    const int nt2 = (n[2] + PC3_TZ - 1) / PC3_TZ;
+    hipLaunchKernelGGL((k_piece_local<PC3_TX, PC3_TY, PC3_TZ>), dim3((unsigned)(nt0 * nt1 * nt2)),
+                       dim3(PC3_TX * PC3_TY * PC3_TZ), 0, s, n[0], n[1], n[2], nt0, nt1, labels,
+                       parent);
+    hipLaunchKernelGGL((k_piece_faces<PC3_TX, PC3_TY, PC3_TZ>), grid, block, 0, s, n[0], n[1],
+                       n[2], labels, parent);
+  }
+  hipLaunchKernelGGL(k_piece_clear, grid, block, 0, s, N, attached);
+  hipLaunchKernelGGL(k_piece_flatten, grid, block, 0, s, N, labels, tp, parent, attached);
+  hipLaunchKernelGGL(k_piece_detach, grid, block, 0, s, N, tp, parent, attached, labels, count);
+  return hipGetLastError();
+}
+
 // Remark 3.1: a node no colour reached takes the smallest label among its
-// labelled neighbours (8 in 2D, 26 in 3D).  One Jacobi layer per launch;
+// labelled axis neighbours (4 in 2D, 6 in 3D), so that it joins a piece of
+// that patch through a face.  One Jacobi layer per launch;
 // repeated until nothing changes, the result is the lowest label among the
 // nearest labelled nodes, independent of the launch schedule.
 __global__ void k_label_fill(int n0, int n1, int n2, const int16_t *__restrict__ in, int16_t *out,
@@ -673,6 +861,7 @@ __global__ void k_label_fill(int n0, int n1, int n2, const int16_t *__restrict__
     for (int dz = dz0; dz <= dz1; ++dz)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
+          if (abs(dx) + abs(dy) + abs(dz) != 1) continue;  // axis neighbours only
           const int X = x + dx, Y = y + dy, Z = z + dz;
           if (X < 0 || Y < 0 || Z < 0 || X >= n0 || Y >= n1 || Z >= n2) continue;
           const int M = in[(size_t)X + (size_t)n0 * ((size_t)Y + (size_t)n1 * Z)];

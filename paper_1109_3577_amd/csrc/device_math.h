@@ -329,7 +329,11 @@ __device__ __forceinline__ void q_finish(const AsyncQ &q, int it, bool again) {
 // `idle` counts consecutive empty attempts; past the limit the launch
 // aborts instead of waiting for ever.
 __device__ __forceinline__ int q_pop(const AsyncQ &q, int64_t &ticket, unsigned &idle) {
-  constexpr unsigned kIdleLimit = 1u << 23;  // about 30 s at the longest back-off
+  // About 1.8 s at the longest back-off: far above the few milliseconds a
+  // workgroup waits while others finish their items, short enough that a
+  // lost wake-up ends the launch with an abort code instead of holding the
+  // GPU.
+  constexpr unsigned kIdleLimit = 1u << 19;
   if (ticket < 0) ticket = (int64_t)atomicAdd(&q.ctr[0], 1u);
   int32_t *slot = &q.ring[q_slot(q, (uint32_t)ticket)];
   const int32_t it = ld_dev(slot);

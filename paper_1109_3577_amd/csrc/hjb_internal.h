@@ -239,6 +239,12 @@ hipError_t launch_labels(int dim, const TraceArgs &a, int16_t *labels, uint32_t 
                          hipStream_t s);
 hipError_t launch_label_fill(const int32_t n[3], const int16_t *in, int16_t *out,
                              uint32_t *changed, hipStream_t s);
+// Pieces of a patch cut off from their own target part (labels of nodes
+// off the target, tp = effective target_part) become -1; count += nodes
+// relabelled.  parent [N] and attached [N] are scratch.  N < 2^31.
+hipError_t launch_detach_pieces(const int32_t n[3], const int16_t *tp, int16_t *labels,
+                                int32_t *parent, uint8_t *attached, uint32_t *count,
+                                hipStream_t s);
 hipError_t launch_count_active(const int16_t *code, size_t N, unsigned long long *out,
                                hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);

@@ -138,7 +138,14 @@ struct ProblemDev {
 
 // Checks every documented requirement of an hjb_problem; throws HJB_EINVAL.
 // ctrl_out (optional) receives the controls as read for the checks.
-void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *ctrl_out = nullptr);
+// scan_dev (optional, kScanBytes of device memory) holds the results of the
+// device-side scan of device inputs; null: a pool block is used.
+constexpr size_t kScanBytes = 48;
+// The checks of validate_problem that need no pass over the nodes: sizes,
+// beta, controls count, pointers, memory kind, steps.
+void validate_header(const hjb_problem *P);
+void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *ctrl_out = nullptr,
+                      void *scan_dev = nullptr);
 // Uploads / borrows the inputs; builds FP32 copies when need32.  `ctrl` is
 // the host copy of the controls from validate_problem (read again if null).
 // Work is enqueued on s; the caller synchronises before the inputs go.
@@ -226,8 +233,9 @@ class SweepEngine {
   int add_problem(const ProblemDev &P, const int16_t *code, const ProblemItems *items, void *v,
                   const double *dbc = nullptr);
   // Uploads the tables and queues `seeds` (global ids) or, when null, the
-  // seeds of every problem.
-  void begin(const std::vector<int32_t> *seeds = nullptr);
+  // seeds of every problem.  `unordered`: the value-ordered schedule lets
+  // every queued item run at once (threshold +inf).
+  void begin(const std::vector<int32_t> *seeds = nullptr, bool unordered = false);
   // Runs rounds until no item is queued or the round cap (HJB_OK / HJB_ENOCONV).
   int run();
   // One persistent launch draining a device work queue (no rounds, no cap).
@@ -239,6 +247,13 @@ class SweepEngine {
   void set_cone(const ConeArgs &c);
   // Enqueues `rounds` rounds, waits, returns the length of the next queue.
   int run_rounds(int rounds);
+  // The same without waiting: the queue length and the per-problem
+  // counters are copied to host memory behind an event.  rounds_done()
+  // tells whether the block has finished; rounds_result() waits for it and
+  // returns the queue length and (optionally) the per-problem queued counts.
+  void launch_rounds_async(int rounds);
+  bool rounds_done();
+  int rounds_result(std::vector<uint32_t> *pactive);
   // The next round's queue (global ids) and per-problem queued counts.
   std::vector<int32_t> queue_now();
   std::vector<uint32_t> pactive_now();
@@ -263,6 +278,9 @@ class SweepEngine {
   std::vector<Item> items_h_;
   DBuf probs_d_, items_d_, lists_[2], flags_[2], count_, counters_;
   std::unique_ptr<PinnedBuf> host_;
+  std::unique_ptr<PinnedBuf> host_cnt_;  // counters copied by launch_rounds_async
+  size_t host_cnt_bytes_ = 0;
+  hipEvent_t blk_ev_ = nullptr;
   hipEvent_t poll_ev_[2] = {nullptr, nullptr};
   std::vector<int32_t> seeds_;
   bool async_ran_ = false;
@@ -340,6 +358,20 @@ int engine_solve(const ProblemDev &P, const int16_t *code, int n_patches, void *
 // Plain Jacobi on the whole grid (one launch per sweep).
 int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out, double tol,
                long long max_sweeps, int poll, bool time_kernels, hipStream_t s, hjb_stats *st);
+// The same iteration in caller-provided buffers: `tmp` [N] values of the
+// solve's precision, `dprob` one device DevProblem, `res` 2 x poll u32 words
+// (poll u64 slots) on the device, `hres` poll u64 slots on the host.
+// Allocates nothing unless time_kernels (events).
+struct JacobiWork {
+  void *tmp;
+  DevProblem *dprob;
+  unsigned long long *res;
+  unsigned long long *hres;
+};
+DevProblem jacobi_problem(const ProblemDev &P, const int16_t *code);
+int run_jacobi_in(const DevProblem &d, size_t N, bool fp64, void *v_out, double tol,
+                  long long max_sweeps, int poll, bool time_kernels, const JacobiWork &w,
+                  hipStream_t s, hjb_stats *st);
 
 double now_ms();
 

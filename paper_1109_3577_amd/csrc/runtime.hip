@@ -192,7 +192,7 @@ PinnedBuf::~PinnedBuf() {
 
 static constexpr double kReachLimit = 1.999;  // |displacement| per axis, cells
 
-void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *ctrl_out) {
+void validate_header(const hjb_problem *P) {
   HJB_REQUIRE(P != nullptr, "problem is NULL");
   HJB_REQUIRE(P->dim == 2 || P->dim == 3, "dim must be 2 or 3 (got %d)", P->dim);
   for (int d = 0; d < P->dim; ++d)
@@ -210,14 +210,19 @@ void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *
   HJB_REQUIRE(P->mem == HJB_MEM_HOST || P->mem == HJB_MEM_DEVICE, "mem must be HJB_MEM_HOST or HJB_MEM_DEVICE");
   for (int d = 0; d < P->dim; ++d)
     HJB_REQUIRE(std::isfinite(P->step[d]) && P->step[d] > 0.0, "step[%d] must be finite and > 0", d);
-  const size_t N = (size_t)Nd;
+}
+
+void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *ctrl_out,
+                      void *scan_dev) {
+  validate_header(P);
+  const size_t N = (size_t)P->n[0] * P->n[1] * P->n[2];
   const int dim = P->dim, nc = P->n_controls;
-  std::vector<double> ctrl((size_t)nc * dim);
+  double ctrl[255 * 3];
+  const size_t nctrl = (size_t)nc * dim;
   if (P->mem == HJB_MEM_HOST) {
-    std::memcpy(ctrl.data(), P->controls, ctrl.size() * sizeof(double));
+    std::memcpy(ctrl, P->controls, nctrl * sizeof(double));
   } else {
-    HJB_HIP(hipMemcpyAsync(ctrl.data(), P->controls, ctrl.size() * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
+    HJB_HIP(hipMemcpyAsync(ctrl, P->controls, nctrl * sizeof(double), hipMemcpyDeviceToHost, s));
     HJB_HIP(hipStreamSynchronize(s));
   }
   double amax[3] = {0, 0, 0};
@@ -243,13 +248,15 @@ void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *
       maxpart = std::max(maxpart, tp);
     }
   } else {
-    DBuf out(4 * sizeof(unsigned long long) + sizeof(int) * 2);
-    HJB_HIP(hipMemsetAsync(out.get(), 0, out.bytes(), s));
-    unsigned long long *o4 = out.as<unsigned long long>();
+    DBuf out;
+    if (!scan_dev) out.reset(kScanBytes);
+    unsigned long long *o4 =
+        static_cast<unsigned long long *>(scan_dev ? scan_dev : out.get());
+    HJB_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(o4), 0u, kScanBytes / 4, s));
     int *bad = reinterpret_cast<int *>(o4 + 4);
     HJB_HIP(launch_scan_problem(*P, N, amax, o4, bad, s));
     unsigned long long h[5] = {0, 0, 0, 0, 0};
-    HJB_HIP(hipMemcpyAsync(h, out.get(), sizeof h, hipMemcpyDeviceToHost, s));
+    HJB_HIP(hipMemcpyAsync(h, o4, sizeof h, hipMemcpyDeviceToHost, s));
     HJB_HIP(hipStreamSynchronize(s));
     int badv = 0;
     std::memcpy(&badv, &h[4], sizeof(int));
@@ -299,7 +306,7 @@ void validate_problem(const hjb_problem *P, hipStream_t s, std::vector<double> *
     }
     HJB_REQUIRE(ok, "beta_node must lie in [0, 1) at every node");
   }
-  if (ctrl_out) *ctrl_out = std::move(ctrl);
+  if (ctrl_out) ctrl_out->assign(ctrl, ctrl + nctrl);
   for (int d = 0; d < dim; ++d)
     HJB_REQUIRE(reach[d] <= kReachLimit,
                 "foot points reach %.4f cells on axis %d; the kernels support < 2 (halo)", reach[d], d);
@@ -573,6 +580,7 @@ SweepEngine::~SweepEngine() {
   for (auto e : events_) (void)hipEventDestroy(e);
   for (auto e : poll_ev_)
     if (e) (void)hipEventDestroy(e);
+  if (blk_ev_) (void)hipEventDestroy(blk_ev_);
 }
 
 int SweepEngine::add_problem(const ProblemDev &P, const int16_t *code, const ProblemItems *items,
@@ -631,7 +639,7 @@ int SweepEngine::add_problem(const ProblemDev &P, const int16_t *code, const Pro
   return (int)dps_.size() - 1;
 }
 
-void SweepEngine::begin(const std::vector<int32_t> *seeds) {
+void SweepEngine::begin(const std::vector<int32_t> *seeds, bool unordered) {
   const size_t np = dps_.size();
   counters_.reset(std::max<size_t>(np, 1) * kCounterWords * sizeof(unsigned long long));
   HJB_HIP(hipMemsetAsync(counters_.get(), 0, counters_.bytes(), s_));
@@ -645,7 +653,7 @@ void SweepEngine::begin(const std::vector<int32_t> *seeds) {
       // round 0: base win_dt, smallest queued key 0 (seeds lie at the target)
       dps_[i].win = reinterpret_cast<uint32_t *>(c + 5 * kSlots + 2);  // [6]
       uint32_t *w0 = &winit[6 * i];
-      const float b0 = dps_[i].win_dt;
+      const float b0 = unordered ? INFINITY : dps_[i].win_dt;
       std::memcpy(&w0[0], &b0, sizeof b0);
       w0[1] = w0[2] = 0u;
       w0[3] = 0u;
@@ -769,6 +777,43 @@ void SweepEngine::launch_block(int rounds) {
     }
   }
   rounds_ += rounds;
+}
+
+void SweepEngine::launch_rounds_async(int rounds) {
+  launch_block(rounds);
+  const size_t np = dps_.size();
+  const size_t cb = std::max<size_t>(np, 1) * kCounterWords * sizeof(unsigned long long);
+  if (!host_cnt_ || host_cnt_bytes_ < cb) {
+    host_cnt_ = std::make_unique<PinnedBuf>(cb);
+    host_cnt_bytes_ = cb;
+  }
+  HJB_HIP(hipMemcpyAsync(host_->as<uint32_t>(), count_.as<uint32_t>() + (r_ % 3), sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, s_));
+  if (np)
+    HJB_HIP(hipMemcpyAsync(host_cnt_->as<void>(), counters_.get(),
+                           np * kCounterWords * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s_));
+  if (!blk_ev_) HJB_HIP(hipEventCreateWithFlags(&blk_ev_, hipEventDisableTiming));
+  HJB_HIP(hipEventRecord(blk_ev_, s_));
+}
+
+bool SweepEngine::rounds_done() {
+  const hipError_t e = hipEventQuery(blk_ev_);
+  if (e == hipErrorNotReady) return false;
+  HJB_HIP(e);
+  return true;
+}
+
+int SweepEngine::rounds_result(std::vector<uint32_t> *pactive) {
+  HJB_HIP(hipEventSynchronize(blk_ev_));
+  if (pactive) {
+    const size_t np = dps_.size();
+    const unsigned long long *cnt = host_cnt_->as<unsigned long long>();
+    pactive->resize(np);
+    for (size_t i = 0; i < np; ++i)
+      (*pactive)[i] = reinterpret_cast<const uint32_t *>(&cnt[i * kCounterWords + 3 * kSlots])[r_ % 3];
+  }
+  return (int)host_->as<uint32_t>()[0];
 }
 
 int SweepEngine::run_rounds(int rounds) {
@@ -999,11 +1044,7 @@ std::vector<EngineResult> SweepEngine::results() {
 
 // ---------------------------------------------------------------- Jacobi
 
-int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out, double tol,
-               long long max_sweeps, int poll, bool time_kernels, hipStream_t s, hjb_stats *st) {
-  const size_t N = P.N;
-  const size_t es = fp64 ? sizeof(double) : sizeof(float);
-  DBuf tmp(N * es);
+DevProblem jacobi_problem(const ProblemDev &P, const int16_t *code) {
   DevProblem d;
   std::memset(&d, 0, sizeof d);
   d.dim = P.dim;
@@ -1032,20 +1073,38 @@ int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out,
   d.drift64 = P.drift64;
   d.drift32 = P.drift32.as<float>();
   d.code = code;
-  DBuf dprob(sizeof(DevProblem));
-  HJB_HIP(hipMemcpyAsync(dprob.get(), &d, sizeof d, hipMemcpyHostToDevice, s));
+  return d;
+}
+
+int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out, double tol,
+               long long max_sweeps, int poll, bool time_kernels, hipStream_t s, hjb_stats *st) {
+  const size_t es = fp64 ? sizeof(double) : sizeof(float);
   poll = std::max(1, poll);
-  DBuf res((size_t)poll * sizeof(unsigned long long));
+  DBuf tmp(P.N * es), dprob(sizeof(DevProblem)), res((size_t)poll * sizeof(unsigned long long));
   PinnedBuf hres((size_t)poll * sizeof(unsigned long long));
-  HJB_HIP(launch_init_values(fp64, code, N, v_out, s));
-  void *a = v_out, *b = tmp.get();
+  const DevProblem d = jacobi_problem(P, code);
+  const JacobiWork w{tmp.get(), dprob.as<DevProblem>(), res.as<unsigned long long>(),
+                     hres.as<unsigned long long>()};
+  return run_jacobi_in(d, P.N, fp64, v_out, tol, max_sweeps, poll, time_kernels, w, s, st);
+}
+
+int run_jacobi_in(const DevProblem &d, size_t N, bool fp64, void *v_out, double tol,
+                  long long max_sweeps, int poll, bool time_kernels, const JacobiWork &w,
+                  hipStream_t s, hjb_stats *st) {
+  const size_t es = fp64 ? sizeof(double) : sizeof(float);
+  poll = std::max(1, poll);
+  // `d` stays alive until the stream is synchronised below
+  HJB_HIP(hipMemcpyAsync(w.dprob, &d, sizeof d, hipMemcpyHostToDevice, s));
+  HJB_HIP(launch_init_values(fp64, d.code, N, v_out, s));
+  void *a = v_out, *b = w.tmp;
   long long sweeps = 0, executed = 0;
   int status = HJB_ENOCONV;
   double last_res = 0.0;
   std::vector<hipEvent_t> ev;
   int launches = 0;
   while (executed < max_sweeps) {
-    HJB_HIP(hipMemsetAsync(res.get(), 0, res.bytes(), s));
+    // a fill kernel rather than a memset node (see the graph notes of the engine)
+    HJB_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(w.res), 0u, 2 * (size_t)poll, s));
     const int m = (int)std::min<long long>(poll, max_sweeps - executed);
     for (int i = 0; i < m; ++i) {
       if (time_kernels) {
@@ -1056,8 +1115,7 @@ int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out,
         }
         HJB_HIP(hipEventRecord(ev[2 * launches], s));
       }
-      HJB_HIP(launch_jacobi(fp64, P.dim, dprob.as<DevProblem>(), N, a, b,
-                            res.as<unsigned long long>() + i, s));
+      HJB_HIP(launch_jacobi(fp64, d.dim, w.dprob, N, a, b, w.res + i, s));
       if (time_kernels) {
         HJB_HIP(hipEventRecord(ev[2 * launches + 1], s));
         ++launches;
@@ -1065,13 +1123,13 @@ int run_jacobi(const ProblemDev &P, const int16_t *code, bool fp64, void *v_out,
       std::swap(a, b);
     }
     executed += m;
-    HJB_HIP(hipMemcpyAsync(hres.as<void>(), res.get(), (size_t)m * sizeof(unsigned long long),
+    HJB_HIP(hipMemcpyAsync(w.hres, w.res, (size_t)m * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, s));
     HJB_HIP(hipStreamSynchronize(s));
     bool stop = false;
     for (int i = 0; i < m; ++i) {
       double rd;
-      std::memcpy(&rd, &hres.as<unsigned long long>()[i], sizeof rd);
+      std::memcpy(&rd, &w.hres[i], sizeof rd);
       last_res = rd;
       if (rd <= tol) {
         sweeps = executed - m + i + 1;

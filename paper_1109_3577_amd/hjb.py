@@ -51,7 +51,8 @@ class hjb_stats(C.Structure):
                 ("ms_prolong_feedback", C.c_double), ("ms_trace", C.c_double),
                 ("trace_node_updates", C.c_int64), ("unreached", C.c_int32),
                 ("sweeps", C.c_int32), ("tile", C.c_int32 * 3), ("threads", C.c_int32),
-                ("inner_sweeps", C.c_int32), ("excluded", C.c_int32)]
+                ("inner_sweeps", C.c_int32), ("excluded", C.c_int32),
+                ("detached", C.c_int32)]
 
     def as_dict(self) -> dict:
         out = {}

@@ -133,3 +133,36 @@ def test_batch_preparation_chunks_equal_alone(H, pr, prepare_bytes):
         got, _ = H.hjb_batch_result(b, i)
         ref, _ = _alone(H, f, c, H.HJB_F32)
         assert np.array_equal(got, ref), i
+
+
+@pytest.mark.parametrize("sched", ["graph", "async"])
+def test_batch_schedules_bitwise(H, pr, sched):
+    """The batch in other launch forms: its rounds captured once and replayed
+    as a hipGraph (solve.use_graph), and all of its items drained by one
+    persistent launch per dimension (HJB_SCHED_ASYNC).  Every schedule of the
+    monotone iteration stops at the same fixed point, so each problem's
+    values equal the plain rounds' bit for bit: FP32 and FP64, 2D and 3D
+    problems, state constraint and the Dirichlet data of eq. dbc."""
+    import torch
+    probs = _mixed_problems(pr, 4)
+    fs, cs = [f for f, _ in probs], [c for _, c in probs]
+    s = torch.cuda.Stream()
+    for prec in (H.HJB_F32, H.HJB_F64):
+        for bc in (H.HJB_BC_STATE, H.HJB_BC_DIRICHLET):
+            ref = H.hjb_batch_create(fs, cs, prec, 0.0, 0, H.make_opts(patch_bc=bc), stream=s)
+            H.hjb_batch_run(ref)
+            kw = {"use_graph": True} if sched == "graph" else {"schedule": H.HJB_SCHED_ASYNC}
+            b = H.hjb_batch_create(fs, cs, prec, 0.0, 0, H.make_opts(patch_bc=bc, **kw), stream=s)
+            st = H.hjb_batch_run(b)
+            assert st["status"] == H.HJB_OK
+            for i in range(len(probs)):
+                want, _ = H.hjb_batch_result(ref, i)
+                got, _ = H.hjb_batch_result(b, i)
+                assert np.array_equal(got, want), (prec, bc, i)
+            b.free()
+            ref.free()
+
+
+def test_server_refuses_async(H):
+    with pytest.raises(H.HjbError):
+        H.hjb_server_create(1 << 30, H.HJB_F32, 0.0, 0, H.make_opts(schedule=H.HJB_SCHED_ASYNC))

@@ -1,0 +1,110 @@
+"""FP32 error of the patchy GPU solve against the FP64 oracle as the grid is
+refined, element by element, on the 2D and 3D variable-speed workloads.
+
+FP32 values stay within 1e-5 of the oracle's exact fixed point at every size
+(rounding accumulates along characteristics damped by beta per step, so the
+bound does not follow from the per-update error alone, and is measured); FP64
+values are the oracle's bit for bit (SHA-256 of all values).  The oracle
+results at 513^2, 1025^2, 65^3 and 129^3 are stored by
+tests/golden/make_golden.py (oracle only); 257^2 runs the oracle here.  The
+solves use the default launch configuration of the benchmark at tol = 0.
+"""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1109_3577_amd import hjb
+    return hjb
+
+
+def _sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.float64).tobytes()).hexdigest()
+
+
+def _gpu_patchy(H, f, c):
+    import torch
+    F = H.Problem(f, device=True)
+    ch = H.hjb_coarse_solve(H.Problem(c, device=True))
+    ph = H.hjb_build_patches(F, ch)
+    out = {}
+    for prec, dt in ((H.HJB_F32, torch.float32), (H.HJB_F64, torch.float64)):
+        v = torch.empty(f.N, dtype=dt, device="cuda")
+        st = H.hjb_solve_patches(F, ph, prec, v, 0.0, 0)
+        assert st["status"] == H.HJB_OK
+        out[prec] = v.double().cpu().numpy()
+    return ph, out[H.HJB_F32], out[H.HJB_F64]
+
+
+def _coarse3(n):
+    return min(33, max(9, round((n - 1) / 8) + 1))
+
+
+CASES = [("2d", 257), ("2d", 513), ("2d", 1025), ("3d", 65), ("3d", 129)]
+
+
+@pytest.mark.parametrize("kind,n", CASES, ids=[f"{k}-{n}" for k, n in CASES])
+def test_fp32_error_against_oracle(H, orc, pr, kind, n, capsys):
+    if kind == "2d":
+        f, c = pr.config2(0, n, pr.coarse_size_2d(n))
+        name = "config2_s0_full.npz" if n == 1025 else f"config2_s0_{n}.npz"
+    else:
+        f, c = pr.config3(0, n, _coarse3(n))
+        name = f"config3_s0_{n}.npz"
+    path = os.path.join(GOLDEN, name)
+    if os.path.exists(path):
+        g = np.load(path)
+        lab_ref, sha_ref = g["labels"], str(g["v64_sha256"])
+        det_ref = int(g["detached"])
+        if "v32" in g:
+            idx, ref = None, g["v32"].astype(np.float64)
+        else:
+            idx, ref = g["idx"], g["v64_at_idx"]
+    else:
+        r = orc.patchy(f, c)
+        _, det_ref = orc.labels(f, r["feedback"], want_detached=True)
+        lab_ref, sha_ref, idx, ref = r["labels"], _sha(r["v"]), None, r["v"]
+    ph, v32, v64 = _gpu_patchy(H, f, c)
+    assert np.array_equal(ph.labels(), lab_ref)
+    assert ph.stats["detached"] == det_ref
+    assert _sha(v64) == sha_ref
+    e = np.abs(v32 - ref).max() if idx is None else np.abs(v32[idx] - ref).max()
+    with capsys.disabled():
+        where = "all nodes" if idx is None else f"{idx.size} sampled nodes"
+        print(f"\n[fp32 error] {kind} {n}: max |v32 - oracle| = {e:.3e} over {where}; "
+              f"FP64 bit-exact; {det_ref} nodes of cut-off pieces relabelled")
+    assert e <= TOL32
+
+
+def test_dirichlet_patch_data_exact_config2(H, orc, pr):
+    """Eq. dbc on the 2D variable-speed workload at 257^2: the patch boundary
+    holds U^(0) of Step 2, so nodes anywhere in a patch may start above their
+    fixed point, not only those next to the target.  FP64 bit-exact with the
+    oracle's Jacobi iteration, FP32 within 1e-5."""
+    import torch
+    f, c = pr.config2(0, 257, 17)
+    r = orc.patchy(f, c)
+    ref, _ = orc.solve_patches_ex(f, r["labels"], u0=r["u0"])
+    F = H.Problem(f, device=True)
+    ph = H.hjb_build_patches(F, H.hjb_coarse_solve(c))
+    assert np.array_equal(ph.labels(), r["labels"])
+    opts = H.make_opts(patch_bc=H.HJB_BC_DIRICHLET)
+    for prec, dt in ((H.HJB_F64, torch.float64), (H.HJB_F32, torch.float32)):
+        v = torch.empty(f.N, dtype=dt, device="cuda")
+        H.hjb_solve_patches(F, ph, prec, v, 0.0, 0, opts)
+        vn = v.double().cpu().numpy()
+        if prec == H.HJB_F64:
+            assert np.array_equal(vn, ref)
+        else:
+            assert np.abs(vn - ref).max() <= TOL32

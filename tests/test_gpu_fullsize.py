@@ -2,10 +2,9 @@
 
 2D (1025^2 fine / 65^2 coarse, 32 controls, 16 parts): coarse values,
 feedback and labels are compared bit for bit with stored oracle results
-(tests/golden/make_golden.py writes them with the oracle only); the FP32
-values are checked node by node at sampled nodes, where the oracle evaluates
-the scheme's operator on the GPU grid: the fixed point must satisfy
-v = F(v) to FP32 rounding.
+(tests/golden/make_golden.py writes them with the oracle only), and the FP32
+values element by element with the oracle's merged patchy values; the run at
+the benchmark's tolerance is an upper bound within its contraction bound.
 
 3D (257^3 / 33^3, 98 controls, 64 parts): the oracle's coarse solve and
 prolongation run in full and must match bit for bit; feedback is compared
@@ -67,19 +66,12 @@ def test_config2_fullsize(H, orc, pr, stream):
     assert st["status"] == H.HJB_OK
     tgt = f.target_part >= 0
     assert np.all(vn[tgt] == 0.0) and vn.min() >= 0.0 and vn.max() <= 1.0
-    # node-by-node: F evaluated by the oracle on the GPU fixed point
-    rng = np.random.default_rng(0)
-    border = np.flatnonzero(np.diff(lab.reshape(f.shape), axis=1).ravel() != 0)[:500]
-    idx = _sample(rng, f.N, 6000, border)
-    idx = idx[~tgt[idx]]
-    Fv = np.empty(idx.size)
-    for j in np.unique(lab[idx]):
-        m = lab[idx] == j
-        Fv[m] = orc.F_at(f, vn, idx[m], labels=gold["labels"], patch=int(j))
-    assert np.abs(np.minimum(vn[idx], Fv) - vn[idx]).max() <= 2e-7
-    assert np.abs(Fv - vn[idx]).max() <= 2e-6
+    # every node: the oracle's merged patchy values (stored rounded to FP32,
+    # within 6e-8 of FP64)
+    assert np.abs(vn - gold["v32"].astype(np.float64)).max() <= 1e-5
+    # tol = 1e-5 stops above the fixed point, within tol beta / (1 - beta)
     dt = vt.double().cpu().numpy() - vn
-    assert dt.min() >= 0.0 and dt.max() <= 5e-4
+    assert dt.min() >= 0.0 and dt.max() <= 1e-5 * f.beta / (1.0 - f.beta)
 
 
 def test_config3_fullsize(H, orc, pr, stream):
