@@ -368,6 +368,28 @@ int hjb_batch_run(hjb_batch_t *b, hjb_stream_t stream, hjb_stats *st);
 int hjb_batch_result(const hjb_batch_t *b, int32_t i, void *v_out, int32_t mem, hjb_stats *st);
 void hjb_batch_free(hjb_batch_t *b);
 
+/* ---------------------------------------------------------------- no allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the plain
+ * global solve of hjb_solve_global with HJB_SCHED_JACOBI, bitwise the same
+ * values and statistics, with every buffer beyond the caller's inputs and
+ * v_out in one static device array of the library (48 MiB per GPU, held
+ * until the process ends).  It calls no hipMalloc, hipFree or other
+ * allocating routine.
+ *   - fine: device inputs (mem = HJB_MEM_DEVICE) of the family
+ *     f = c(x) a + w(x) with one beta (no beta_node, foot or beta_pk);
+ *     at most HJB_NOALLOC_MAX_NODES nodes; otherwise HJB_EINVAL before any
+ *     device work.
+ *   - v_out: device, N values of the precision; the stats as
+ *     hjb_solve_global (no kernel timing).
+ *   - Every call on a GPU uses that GPU's one array, which keeps the last
+ *     call's contents: calls that overlap on one GPU (several host threads
+ *     or streams) race and must be serialised by the caller. */
+#define HJB_NOALLOC_MAX_NODES (1 << 21)
+int hjb_solve_global_noalloc(const hjb_problem *fine, int32_t precision, double tol,
+                             int32_t max_sweeps, void *v_out, hjb_stats *st,
+                             hjb_stream_t stream);
+
 /* ---------------------------------------------------------------- serving
  * Continuous batching of solve requests: a submitted request is admitted
  * when its HBM footprint fits the budget, goes through Steps 1-3.1, and its

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhjb.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["sweep.hip", "build.hip", "runtime.hip", "api.hip", "batch.hip"]
+SOURCES = ["sweep.hip", "build.hip", "runtime.hip", "api.hip", "batch.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -22,13 +22,15 @@ HJB_F32, HJB_F64 = 0, 1
 HJB_SCHED_TILED, HJB_SCHED_JACOBI, HJB_SCHED_ASYNC = 0, 1, 2
 HJB_BC_STATE, HJB_BC_DIRICHLET = 0, 1
 HJB_OBSTACLE = -2
+HJB_NOALLOC_MAX_NODES = 1 << 21
 
 # Every symbol include/hjb.h declares.
 EXPORTS = (
     "hjb_coarse_solve", "hjb_coarse_values", "hjb_coarse_free", "hjb_build_patches",
     "hjb_build_patches_ex",
     "hjb_patches_labels", "hjb_patches_feedback", "hjb_patches_u0", "hjb_patches_free",
-    "hjb_solve_patches", "hjb_solve_global", "hjb_batch_create", "hjb_batch_run",
+    "hjb_solve_patches", "hjb_solve_global", "hjb_solve_global_noalloc", "hjb_batch_create",
+    "hjb_batch_run",
     "hjb_batch_result", "hjb_batch_free", "hjb_server_create", "hjb_server_submit",
     "hjb_server_step", "hjb_server_poll", "hjb_server_free", "hjb_last_error", "hjb_version",
 )
@@ -113,6 +115,7 @@ def _load():
                                     P(hjb_stats), vp]
     L.hjb_solve_global.argtypes = [P(hjb_problem), i32, d, i32, vp, P(hjb_solve_opts),
                                    P(hjb_stats), vp]
+    L.hjb_solve_global_noalloc.argtypes = [P(hjb_problem), i32, d, i32, vp, P(hjb_stats), vp]
     L.hjb_batch_create.argtypes = [P(P(hjb_problem)), P(P(hjb_problem)), i32, P(hjb_batch_opts),
                                    vp, P(vp)]
     L.hjb_batch_run.argtypes = [vp, vp, P(hjb_stats)]
@@ -342,6 +345,19 @@ def hjb_solve_global(fine, precision: int, v_out, tol: float = 0.0, max_sweeps: 
     rc = lib.hjb_solve_global(P.ref, int(precision), float(tol), int(max_sweeps), v_out.data_ptr(),
                               None if opts is None else C.byref(opts), C.byref(st), _stream(stream))
     _check(rc, "hjb_solve_global", (HJB_OK, HJB_ENOCONV) if allow_noconv else (HJB_OK,))
+    return st.as_dict()
+
+
+def hjb_solve_global_noalloc(fine, precision: int, v_out, tol: float = 0.0, max_sweeps: int = 0,
+                             stream=None, allow_noconv: bool = False) -> dict:
+    """The plain global solve (HJB_SCHED_JACOBI) with no device allocation:
+    `fine` must hold device inputs (Problem(..., device=True))."""
+    P = _as_problem(fine)
+    _check_out(v_out, P.N, precision)
+    st = hjb_stats()
+    rc = lib.hjb_solve_global_noalloc(P.ref, int(precision), float(tol), int(max_sweeps),
+                                      v_out.data_ptr(), C.byref(st), _stream(stream))
+    _check(rc, "hjb_solve_global_noalloc", (HJB_OK, HJB_ENOCONV) if allow_noconv else (HJB_OK,))
     return st.as_dict()
 
 
