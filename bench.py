@@ -309,6 +309,49 @@ def bench_batch(args):
         "speedup_vs_sequential_plain": t_seq / (t_prep + t_run)}))
 
 
+def pooled_requests(specs, pool, window=96):
+    """Builds the requests of `specs` on a process pool, in order, at most
+    `window` of them ahead of the consumer."""
+    from collections import deque
+
+    from paper_1109_3577_amd import problems
+    q = deque()
+    for spec in specs:
+        q.append(pool.submit(problems.serving_request, spec))
+        if len(q) >= window:
+            yield q.popleft().result()
+    while q:
+        yield q.popleft().result()
+
+
+def bench_serve_stream(args, pool):
+    """The serving workload at its stated length (e.g. 10,000 requests):
+    the closed-loop capacity is measured on the first 300 requests, then the
+    whole Poisson stream at load x capacity is served with the requests
+    built on the fly by a pool of host processes (the arrays of 10,000
+    requests would not fit host memory at once)."""
+    import torch
+
+    from paper_1109_3577_amd import problems, serve
+    torch.cuda.set_device(0)
+    budget = int(0.8 * torch.cuda.mem_get_info()[0])
+    sample = list(pooled_requests(problems.serving_specs(300, 1.0, seed=0), pool))
+    cap = serve.run(sample, budget, tol=args.tol, closed_loop=True)
+    del sample
+    rate = args.load * cap["requests_per_s"]
+    print(f"[bench] capacity {cap['requests_per_s']:.1f} requests/s; serving {args.count} requests "
+          f"at {rate:.1f}/s", file=sys.stderr, flush=True)
+    specs = list(problems.serving_specs(args.count, rate, seed=0))
+    n3 = sum(1 for s in specs if s[2] == 3)
+    res = serve.run_stream(pooled_requests(specs, pool), budget, tol=args.tol,
+                           progress_every=500)
+    print(json.dumps({
+        "metric": "serving: p50/p99 latency and node-control updates/s at a fixed Poisson rate",
+        "mode": "serve", "requests": args.count, "requests_3d": n3,
+        "capacity_requests_per_s": cap["requests_per_s"], "capacity_sample": 300,
+        "load": args.load, "arrival_rate_per_s": rate, **res}))
+
+
 def bench_serve(args):
     """Poisson stream of solve requests through the continuous-batching
     server: 80% 2D (side 129..1025; half eikonal with 16 parts, half the
@@ -364,6 +407,14 @@ def main():
                           "sharded across GPUs with no exchange during the solve, which is "
                           "not implemented here", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.mode == "serve" and args.count > 1000:
+        # the request builders run in processes started before this one
+        # touches the GPU
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        workers = max(2, min(14, len(os.sched_getaffinity(0)) - 2))
+        with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as pool:
+            return bench_serve_stream(args, pool)
     import numpy as np
     import torch
 

@@ -213,10 +213,16 @@ def variable_speed_2d(seed: int, n: int = 1025, nc_coarse: int = 65, nc: int = 3
         lo, hi = (-1.0, -1.0), (1.0, 1.0)
         kk = 2.0 / (nn - 1)
         X, Y = grid_coords(2, (nn, nn), lo, hi)
-        c = 1.0 + 0.5 * np.sin(2.0 * math.pi * k1 * X) * np.sin(2.0 * math.pi * k2 * Y)
+        # sines of each axis once, broadcast over the grid (the same values
+        # and products as evaluating them node by node)
+        ax = lo[0] + kk * np.arange(nn, dtype=np.float64)
+        sx, sy = np.sin(2.0 * math.pi * k1 * ax), np.sin(2.0 * math.pi * k2 * ax)
+        c = (1.0 + 0.5 * sx[None, :] * sy[:, None]).ravel()
         w = None
         if drift_sign is not None:
-            w = 0.3 * drift_sign * np.stack([-np.sin(math.pi * Y), np.sin(math.pi * X)], axis=1)
+            wy = np.broadcast_to(-np.sin(math.pi * ax)[:, None], (nn, nn)).ravel()
+            wx = np.broadcast_to(np.sin(math.pi * ax)[None, :], (nn, nn)).ravel()
+            w = 0.3 * drift_sign * np.stack([wy, wx], axis=1)
         tp = _ball_sectors_2d(X, Y, centre, r, R)
         out.append(_make(2, (nn, nn), kk, unit_controls_2d(nc), c, w, tp, R, is_fp32,
                          f"{name}-s{seed}-n{nn}",
@@ -234,6 +240,9 @@ def _sphere_parts(X, Y, Z, centre, r, bands, sectors):
     dx, dy, dz = X - centre[0], Y - centre[1], Z - centre[2]
     rr = dx * dx + dy * dy + dz * dz
     inside = rr <= r * r
+    out = np.full(X.shape, -1, dtype=np.int16)
+    # parts of the nodes inside the ball only (the rest stays -1)
+    dx, dy, dz, rr = dx[inside], dy[inside], dz[inside], rr[inside]
     rad = np.sqrt(rr)
     uz = np.where(rad > 0.0, dz / np.where(rad > 0.0, rad, 1.0), 1.0)
     band = np.minimum(bands - 1, np.floor(bands * (1.0 - uz) / 2.0).astype(np.int64))
@@ -241,8 +250,15 @@ def _sphere_parts(X, Y, Z, centre, r, bands, sectors):
     th = np.where(th < 0.0, th + 2.0 * math.pi, th)
     sec = np.minimum(sectors - 1, np.floor(sectors * th / (2.0 * math.pi)).astype(np.int64))
     part = band * sectors + sec
-    part = np.where(rad > 0.0, part, 0)
-    return np.where(inside, part, -1).astype(np.int16)
+    out[inside] = np.where(rad > 0.0, part, 0).astype(np.int16)
+    return out
+
+
+def sphere_target_nodes(n: int, r: float = 0.15) -> int:
+    """Number of nodes of the n^3 grid on [-1,1]^3 inside the ball of radius
+    r at the origin (the target of the 3D variable-speed generator)."""
+    X, Y, Z = grid_coords(3, (n, n, n), (-1.0,) * 3, (1.0,) * 3)
+    return int((X * X + Y * Y + Z * Z <= r * r).sum())
 
 
 def variable_speed_3d(seed: int, n: int = 257, nc_coarse: int = 33, nc: int = 98,
@@ -259,8 +275,11 @@ def variable_speed_3d(seed: int, n: int = 257, nc_coarse: int = 33, nc: int = 98
         lo, hi = (-1.0,) * 3, (1.0,) * 3
         kk = 2.0 / (nn - 1)
         X, Y, Z = grid_coords(3, (nn, nn, nn), lo, hi)
-        c = 1.0 + 0.4 * (np.sin(2.0 * math.pi * ks[0] * X) * np.sin(2.0 * math.pi * ks[1] * Y)
-                         * np.sin(2.0 * math.pi * ks[2] * Z))
+        # the sines of each axis once, broadcast over the grid (the same
+        # values and products as evaluating them node by node)
+        ax = lo[0] + kk * np.arange(nn, dtype=np.float64)
+        sx, sy, sz = (np.sin(2.0 * math.pi * ks[d] * ax) for d in range(3))
+        c = (1.0 + 0.4 * (sx[None, None, :] * sy[None, :, None] * sz[:, None, None])).ravel()
         tp = _sphere_parts(X, Y, Z, (0.0, 0.0, 0.0), r, bands, sectors)
         out.append(_make(3, (nn, nn, nn), kk, fibonacci_controls_3d(nc), c, None, tp, R, is_fp32,
                          f"{name}-s{seed}-n{nn}", meta=dict(seed=seed, ks=ks, r=r)))
@@ -531,11 +550,12 @@ class ServingRequest:
     coarse: Problem
 
 
-def serving_stream(count: int, rate_per_s: float, seed: int = 0,
-                   n2d=(129, 1025), n3d=(65, 193), frac3d: float = 0.2):
-    """Poisson arrivals of solve requests: ``1 - frac3d`` 2D (half eikonal
-    with 16 sector parts, half the batched generator), ``frac3d`` 3D (the 3D
-    variable-speed generator).  Returns a generator of ServingRequest."""
+def serving_specs(count: int, rate_per_s: float, seed: int = 0,
+                  n2d=(129, 1025), n3d=(65, 193), frac3d: float = 0.2):
+    """The random draws of the serving stream, request by request:
+    (rid, arrival time, kind, sub-seed, grid side), kind 3 for the 3D
+    variable-speed generator, 1 for the 2D eikonal, 4 for the batched 2D
+    generator.  Cheap; serving_request builds the arrays of one spec."""
     rng = np.random.default_rng(seed)
     t = 0.0
     for i in range(count):
@@ -543,23 +563,41 @@ def serving_stream(count: int, rate_per_s: float, seed: int = 0,
         u = float(rng.uniform())
         sub = int(rng.integers(0, 2 ** 31 - 1))
         if u < frac3d:
-            n = int(rng.integers(n3d[0], n3d[1] + 1))
-            ncoarse = int(min(33, max(9, round((n - 1) / 8) + 1)))
-            srng = np.random.default_rng(sub)
-            ks_seed = int(srng.integers(0, 2 ** 31 - 1))
-            f, c = variable_speed_3d(ks_seed, n, ncoarse, 98, 8, 8, 0.15, True, f"req{i}")
-            tnodes = int((f.target_part >= 0).sum())
-            R = int(min(64, max(8, tnodes // 16)))
-            if R != 64:
-                bands = max(1, int(round(math.sqrt(R))))
-                sectors = max(1, R // bands)
-                f, c = variable_speed_3d(ks_seed, n, ncoarse, 98, bands, sectors, 0.15, True,
-                                         f"req{i}")
+            kind, n = 3, int(rng.integers(n3d[0], n3d[1] + 1))
         elif u < frac3d + (1.0 - frac3d) / 2.0:
-            n = int(rng.integers(n2d[0], n2d[1] + 1))
-            f = eikonal_2d(n, 32, 0.1, 16, (0.0, 0.0), True, f"req{i}")
-            c = eikonal_2d(coarse_size_2d(n), 32, 0.1, 16, (0.0, 0.0), False, f"req{i}-c")
+            kind, n = 1, int(rng.integers(n2d[0], n2d[1] + 1))
         else:
-            n = int(rng.integers(n2d[0], n2d[1] + 1))
-            f, c = batched_problem(np.random.SeedSequence(sub), i, (n, n))
-        yield ServingRequest(i, t, f, c)
+            kind, n = 4, int(rng.integers(n2d[0], n2d[1] + 1))
+        yield (i, t, kind, sub, n)
+
+
+def serving_request(spec) -> "ServingRequest":
+    """The request of one serving spec: 80% 2D (half eikonal with 16 sector
+    parts, half the batched generator), 20% 3D (the 3D variable-speed
+    generator with R = min(64, max(8, target nodes / 16)))."""
+    i, t, kind, sub, n = spec
+    if kind == 3:
+        ncoarse = int(min(33, max(9, round((n - 1) / 8) + 1)))
+        srng = np.random.default_rng(sub)
+        ks_seed = int(srng.integers(0, 2 ** 31 - 1))
+        R = int(min(64, max(8, sphere_target_nodes(n, 0.15) // 16)))
+        bands, sectors = 8, 8
+        if R != 64:
+            bands = max(1, int(round(math.sqrt(R))))
+            sectors = max(1, R // bands)
+        f, c = variable_speed_3d(ks_seed, n, ncoarse, 98, bands, sectors, 0.15, True, f"req{i}")
+    elif kind == 1:
+        f = eikonal_2d(n, 32, 0.1, 16, (0.0, 0.0), True, f"req{i}")
+        c = eikonal_2d(coarse_size_2d(n), 32, 0.1, 16, (0.0, 0.0), False, f"req{i}-c")
+    else:
+        f, c = batched_problem(np.random.SeedSequence(sub), i, (n, n))
+    return ServingRequest(i, t, f, c)
+
+
+def serving_stream(count: int, rate_per_s: float, seed: int = 0,
+                   n2d=(129, 1025), n3d=(65, 193), frac3d: float = 0.2):
+    """Poisson arrivals of solve requests: ``1 - frac3d`` 2D (half eikonal
+    with 16 sector parts, half the batched generator), ``frac3d`` 3D (the 3D
+    variable-speed generator).  Returns a generator of ServingRequest."""
+    for spec in serving_specs(count, rate_per_s, seed, n2d, n3d, frac3d):
+        yield serving_request(spec)

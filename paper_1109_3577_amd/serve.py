@@ -72,3 +72,54 @@ def run(requests: Iterable, hbm_budget: int, precision: int = hjb.HJB_F32, tol: 
     if keep_results:
         out["results"] = results
     return out
+
+
+def run_stream(requests: Iterable, hbm_budget: int, precision: int = hjb.HJB_F32,
+               tol: float = 1e-5, rounds_per_step: int = 4,
+               opts: Optional[hjb.hjb_solve_opts] = None, progress_every: int = 0) -> dict:
+    """Runs the server over a stream of requests in arrival order (arrival_s
+    from the start of the run), holding only the requests in flight: each
+    one is submitted when its arrival time has passed (the server copies its
+    arrays) and dropped once its result is collected.  For long request
+    streams whose arrays would not fit host memory all at once.  Returns
+    latency percentiles and throughput."""
+    S = hjb.hjb_server_create(hbm_budget, precision, tol, 0, opts)
+    it = iter(requests)
+    nxt = next(it, None)
+    t0 = time.perf_counter()
+    pending = {}
+    lat: List[float] = []
+    late: List[float] = []
+    upd = 0
+    done = 0
+    while nxt is not None or pending:
+        now = time.perf_counter() - t0
+        while nxt is not None and nxt.arrival_s <= now:
+            late.append(now - nxt.arrival_s)
+            pending[nxt.rid] = (S.submit(nxt.fine, nxt.coarse), nxt.arrival_s)
+            nxt = next(it, None)
+            now = time.perf_counter() - t0
+        if not pending:
+            if nxt is not None:
+                time.sleep(max(0.0, nxt.arrival_s - now))
+            continue
+        S.step(rounds_per_step)
+        t_now = time.perf_counter() - t0
+        for rid, (t, arr) in list(pending.items()):
+            out, st = S.poll(t)
+            if out is not None:
+                lat.append(t_now - arr)
+                upd += st["updates"]
+                done += 1
+                del pending[rid]
+                if progress_every and done % progress_every == 0:
+                    import sys
+                    print(f"[serve] t={t_now:.1f}s done {done}", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    S.free()
+    L = np.array(lat)
+    return {"requests": len(lat), "wall_s": wall,
+            "p50_ms": float(np.percentile(L, 50) * 1e3), "p99_ms": float(np.percentile(L, 99) * 1e3),
+            "mean_ms": float(L.mean() * 1e3), "max_ms": float(L.max() * 1e3),
+            "requests_per_s": len(lat) / wall, "updates": int(upd), "updates_per_s": upd / wall,
+            "submit_late_max_ms": float(max(late) * 1e3) if late else 0.0}
