@@ -28,6 +28,11 @@ def _np(t):
 
 
 def _case(pr, case):
+    if case == "c2_257":
+        # the headline generator at 257^2 / 17^2: patches that straddle
+        # tiles, nodes of other patches as Dirichlet data next to every
+        # patch
+        return pr.config2(0, 257, pr.coarse_size_2d(257))
     if case == "2d":
         return pr.variable_speed_2d(2, 193, 17, 32, 16, 0.1, True)
     if case == "2d_drift":
@@ -35,7 +40,7 @@ def _case(pr, case):
     return pr.variable_speed_3d(0, 37, 11, 98, 4, 4, 0.25, True)
 
 
-@pytest.mark.parametrize("case", ["2d", "2d_drift", "3d"])
+@pytest.mark.parametrize("case", ["2d", "2d_drift", "3d", "c2_257"])
 def test_dbc_solve_parity(H, orc, pr, case):
     f, c = _case(pr, case)
     out = orc.patchy(f, c)
