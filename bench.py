@@ -403,7 +403,7 @@ def bench_serve(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the patches would be "
+        print(json.dumps({"error": "the benchmark runs on one GPU only; the patches would be "
                           "sharded across GPUs with no exchange during the solve, which is "
                           "not implemented here", "n_gpus": args.gpus}))
         sys.exit(2)
