@@ -1,0 +1,34 @@
+"""Many target parts in 2D: 100 equal-angle parts (four words of part bits
+per tile), 193^2 / 17^2.  The colour transport loads only the parts present
+around a tile, in groups, shared by two workgroups per tile; the labels
+must still be the oracle's bit for bit (Section 3, Step 3.1 and eq.
+proiezionecolore), and the merged values of Steps 3.2-4 too (FP64 exact,
+FP32 within 1e-5)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1109_3577_amd import hjb
+    return hjb
+
+
+def test_hundred_parts_2d(H, orc, pr):
+    import torch
+    f, c = pr.variable_speed_2d(5, 193, 17, 32, 100, 0.1, True)
+    out = orc.patchy(f, c)
+    assert len(np.unique(out["labels"])) == 100
+    ch = H.hjb_coarse_solve(c)
+    ph = H.hjb_build_patches(f, ch)
+    assert np.array_equal(ph.labels(), out["labels"])
+    v64 = torch.empty(f.N, dtype=torch.float64, device="cuda")
+    H.hjb_solve_patches(f, ph, H.HJB_F64, v64)
+    assert np.array_equal(v64.cpu().numpy(), out["v"])
+    v32 = torch.empty(f.N, dtype=torch.float32, device="cuda")
+    H.hjb_solve_patches(f, ph, H.HJB_F32, v32)
+    assert np.abs(v32.double().cpu().numpy() - out["v"]).max() <= 1e-5
