@@ -476,8 +476,9 @@ class Server:
         rc = lib.hjb_server_poll(self.h, C.c_uint64(ticket), _ptr(out), mem, C.byref(st))
         if rc == HJB_EAGAIN:
             return None, None
-        _check(rc, "hjb_server_poll", (HJB_OK, HJB_ENOCONV))
+        # collected: a result, or the error of a request that failed
         del self.sizes[ticket]
+        _check(rc, "hjb_server_poll", (HJB_OK, HJB_ENOCONV))
         return out, st.as_dict()
 
     def free(self):

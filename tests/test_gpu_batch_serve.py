@@ -166,3 +166,37 @@ def test_batch_schedules_bitwise(H, pr, sched):
 def test_server_refuses_async(H):
     with pytest.raises(H.HjbError):
         H.hjb_server_create(1 << 30, H.HJB_F32, 0.0, 0, H.make_opts(schedule=H.HJB_SCHED_ASYNC))
+
+
+def test_server_failed_request_leaves_others(H, pr):
+    """A request whose data fail the per-node checks (a non-finite speed,
+    found by the preparation pool) is collected with its error; its budget
+    is released, and the requests around it finish with the bits of their
+    solves alone."""
+    import copy
+    f, c = pr.variable_speed_2d(1, 129, 17, 16, 4, 0.1, True)
+    bad = copy.deepcopy(f)
+    bad.speed = np.array(bad.speed, dtype=np.float64)
+    bad.speed[777] = np.nan
+    S = H.hjb_server_create(6 << 20, H.HJB_F32)
+    t1 = S.submit(f, c)
+    tb = S.submit(bad, c)
+    t2 = S.submit(f, c)
+    out, err = {}, {}
+    for _ in range(5000):
+        S.step(4)
+        for t in (t1, tb, t2):
+            if t in out or t in err:
+                continue
+            try:
+                v, st = S.poll(t)
+            except H.HjbError as e:
+                err[t] = e
+                continue
+            if v is not None:
+                out[t] = v
+        if len(out) + len(err) == 3:
+            break
+    assert set(err) == {tb} and err[tb].status == H.HJB_EINVAL
+    ref, _ = _alone(H, f, c, H.HJB_F32)
+    assert np.array_equal(out[t1], ref) and np.array_equal(out[t2], ref)
