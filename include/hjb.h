@@ -318,8 +318,13 @@ void hjb_patches_free(hjb_patches_t *p);
  * the label is -1.  precision HJB_F32: v stored and iterated in FP32, the
  * stopping residual in FP64; HJB_F64: FP64 throughout, bitwise equal to any
  * other exact-fixed-point schedule of the same operator.  tol as in
- * hjb_coarse_solve.  v_out: caller-owned DEVICE buffer of N floats or
- * doubles.  opts and st may be NULL. */
+ * hjb_coarse_solve.  With tol = 0 every schedule (tile shape, sweeps per
+ * round, graph replay, persistent launch) stops at the same bits, in FP32
+ * too; with tol > 0 the point where the iteration stops depends on the
+ * order in which workgroups ran, so two runs may differ in the last bits
+ * (each within the tolerance bound of the fixed point).  v_out:
+ * caller-owned DEVICE buffer of N floats or doubles.  opts and st may be
+ * NULL. */
 int hjb_solve_patches(const hjb_problem *fine, const hjb_patches_t *p, int32_t precision,
                       double tol, int32_t max_sweeps, void *v_out, const hjb_solve_opts *opts,
                       hjb_stats *st, hjb_stream_t stream);
