@@ -2,8 +2,9 @@
 grid sizes that leave ragged tiles, 4-64 controls, 1-40 target parts of
 every size, drift in either sense, 2D and 3D.  Labels and the Step 2
 values are compared bit for bit, the merged values of Steps 3.2-4 bit for
-bit in FP64 and within 1e-5 in FP32, and the eq. dbc solve bit for bit in
-FP64."""
+bit in FP64 and within 1e-5 in FP32, the eq. dbc solve and the control
+cones of add-on AO3 (r = 4) bit for bit in FP64, and the value-ordered
+schedule of add-on AO2 bit for bit against the plain one."""
 import numpy as np
 import pytest
 
@@ -69,3 +70,10 @@ def test_random_instance(H, orc, pr, i):
     d64 = torch.empty(f.N, dtype=torch.float64, device="cuda")
     H.hjb_solve_patches(f, ph, H.HJB_F64, d64, opts=H.make_opts(patch_bc=H.HJB_BC_DIRICHLET))
     assert np.array_equal(d64.cpu().numpy(), ref)
+    cone, _ = orc.solve_patches_cone(f, out["labels"], out["feedback"], 4.0)
+    c64 = torch.empty(f.N, dtype=torch.float64, device="cuda")
+    H.hjb_solve_patches(f, ph, H.HJB_F64, c64, opts=H.make_opts(control_cone=4.0))
+    assert np.array_equal(c64.cpu().numpy(), cone)
+    o64 = torch.empty(f.N, dtype=torch.float64, device="cuda")
+    H.hjb_solve_patches(f, ph, H.HJB_F64, o64, opts=H.make_opts(order_window=6.0))
+    assert np.array_equal(o64.cpu().numpy(), out["v"])
