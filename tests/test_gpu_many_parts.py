@@ -32,3 +32,22 @@ def test_hundred_parts_2d(H, orc, pr):
     v32 = torch.empty(f.N, dtype=torch.float32, device="cuda")
     H.hjb_solve_patches(f, ph, H.HJB_F32, v32)
     assert np.abs(v32.double().cpu().numpy() - out["v"]).max() <= 1e-5
+
+
+def test_largest_part_count_2d(H, orc, pr):
+    """1,024 parts (the most the transport supports: 32 words of part bits
+    per tile), 955 of them holding target nodes, on a 97^2 grid; one more
+    part is refused."""
+    import torch
+    f, c = pr.variable_speed_2d(6, 97, 17, 32, 1024, 0.6, True)
+    out = orc.patchy(f, c)
+    ch = H.hjb_coarse_solve(c)
+    ph = H.hjb_build_patches(f, ch)
+    assert np.array_equal(ph.labels(), out["labels"])
+    v64 = torch.empty(f.N, dtype=torch.float64, device="cuda")
+    H.hjb_solve_patches(f, ph, H.HJB_F64, v64)
+    assert np.array_equal(v64.cpu().numpy(), out["v"])
+    g, _ = pr.variable_speed_2d(6, 97, 17, 32, 1025, 0.6, True)
+    with pytest.raises(H.HjbError) as e:
+        H.hjb_build_patches(g, ch)
+    assert e.value.status == H.HJB_EINVAL
