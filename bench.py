@@ -38,7 +38,7 @@ PEAK_HBM = 8.0e12
 # while these files are unchanged.
 SWEEP_SOURCES = ("paper_1109_3577_amd/csrc/sweep.hip", "paper_1109_3577_amd/csrc/device_math.h",
                  "paper_1109_3577_amd/csrc/hjb_internal.h")
-PMC_SUMMARY = "profiles/k_sweep_f32_2d_1025_pmc.md"
+PMC_SUMMARIES = ("profiles/k_sweep_f32_2d_1025_pmc.md", "profiles/k_sweep_f32_3d_257_pmc.md")
 
 
 def sweep_source_hash() -> str:
@@ -55,16 +55,17 @@ def recorded_traffic(kernel: str):
     (FETCH_SIZE x fetch factor + WRITE_SIZE x write factor), the factors being
     what the same counters read for a copy of known size.  None when there is
     no record for this kernel or its sources changed since it was taken."""
-    path = os.path.join(ROOT, PMC_SUMMARY)
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        for line in fh:
-            if line.startswith("pmc: "):
-                rec = json.loads(line[5:])
-                if rec.get("kernel") == kernel and rec.get("source_hash") == sweep_source_hash():
-                    return (rec["fetch_kib_per_dispatch"] * 1024.0 * rec["fetch_factor"]
-                            + rec["write_kib_per_dispatch"] * 1024.0 * rec["write_factor"])
+    for name in PMC_SUMMARIES:
+        path = os.path.join(ROOT, name)
+        if not os.path.exists(path):
+            continue
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("pmc: "):
+                    rec = json.loads(line[5:])
+                    if rec.get("kernel") == kernel and rec.get("source_hash") == sweep_source_hash():
+                        return (rec["fetch_kib_per_dispatch"] * 1024.0 * rec["fetch_factor"]
+                                + rec["write_kib_per_dispatch"] * 1024.0 * rec["write_factor"])
     return None
 
 
