@@ -13,6 +13,9 @@ Outputs (compressed numpy archives next to this script):
                            parts, seed 0: labels and merged patchy values.
   config3_s0_129.npz    -- the same at 129^3 / 17^3: labels, and the merged
                            patchy values at 60,000 sampled nodes.
+  config3_s0_257.npz    -- the same at the full 257^3 / 33^3: all labels, and
+                           the merged patchy values at 100,000 sampled nodes
+                           (a few hours of oracle time on 8 cores).
   config2_s0_1025_reading.npz -- the paper's own Step 3.1 transport (no
                            factor; scheme step, and the step |h_i f| = k) at
                            1025^2: part of the largest colour per node and
@@ -119,6 +122,7 @@ JOBS = {
     "config2_513": lambda: config2_side(513),
     "config3_65": lambda: config3_side(65),
     "config3_129": lambda: config3_side(129, sample=60000),
+    "config3_full": lambda: config3_side(257, sample=100000),
     "config2_reading": lambda: config2_reading(0),
 }
 
