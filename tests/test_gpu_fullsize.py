@@ -9,7 +9,8 @@ the benchmark's tolerance is an upper bound within its contraction bound.
 3D (257^3 / 33^3, 98 controls, 64 parts): the oracle's coarse solve and
 prolongation run in full and must match bit for bit; feedback is compared
 at sampled nodes; labels and values are checked through properties that
-hold at any size.
+hold at any size (tests/test_gpu_fp32_error.py compares all labels and the
+FP64 values with stored oracle results at this size).
 """
 import os
 
